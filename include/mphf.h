@@ -1,0 +1,150 @@
+/*
+ * mphf.h -- C ABI of the MI355X (gfx950) cascading-bit-array minimal perfect
+ * hash function of Limasset, Rizk, Chikhi and Peterlongo, "Fast and scalable
+ * minimal perfect hashing for massive key sets" (arXiv 1702.03154).
+ *
+ * Given N distinct 64-bit keys, the build computes a bijection of the keys
+ * onto [1, N] (Section 1, first paragraph).  Level d hashes every key of the
+ * set F_d into a bit array A_d of m_d = ceil(gamma * |F_d|) positions; a
+ * position keeps a 1 iff exactly one key lands on it, and the keys that
+ * collided form F_{d+1} (Section 2.1; Section 2.2, "Collision detection";
+ * Algorithms 1 and 2).  After at most max_levels levels the leftover keys go
+ * to a fallback table (Section 3, "Termination").  A query walks the levels
+ * until its bit is 1 and returns the number of ones before that bit in the
+ * concatenation of all A_d, plus one (Section 2.1, query paragraph;
+ * Section 2.2, "Minimality"; Algorithm 3), using 64-bit counters sampled
+ * every 512 positions (Section 3.1, "Rank structure").
+ *
+ * Conventions for every entry point:
+ *  - Key, query and label arrays are DEVICE pointers (hipMalloc memory or a
+ *    ROCm tensor's storage) on the current HIP device.  The caller owns them;
+ *    keys and queries are only read.  A host pointer is rejected with
+ *    MPHF_E_INVALID.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - An mphf_t owns all the device memory of one function and is immutable
+ *    after the build, so lookups on one handle from several streams or host
+ *    threads at once are safe.  mphf_destroy must not overlap any of them.
+ *  - Errors return a status; mphf_last_error() gives this thread's message
+ *    for the last failing call.  On error nothing is leaked and *out is NULL.
+ */
+#ifndef MPHF_H
+#define MPHF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPHF_MAX_LEVELS 64
+
+typedef struct mphf mphf_t;
+
+typedef enum mphf_status {
+    MPHF_OK = 0,
+    MPHF_E_INVALID = 1,        /* bad argument: gamma < 1 or NaN, NULL or host pointer, bad option */
+    MPHF_E_NOMEM = 2,          /* device allocation failed or mem_budget exceeded */
+    MPHF_E_DUPLICATE_KEYS = 3, /* two input keys are equal (they collide at every level) */
+    MPHF_E_DEVICE = 4          /* a HIP call failed; the message carries hipGetErrorString */
+} mphf_status;
+
+/* Build options.  mphf_default_opts() fills the defaults. */
+typedef struct mphf_opts {
+    uint32_t max_levels;      /* D, the number of levels before the fallback table:
+                                 1..MPHF_MAX_LEVELS, default 25 (Section 3, "Termination") */
+    uint32_t rank_sample;     /* positions per rank counter: 512 (default, Section 3.1) or
+                                 1024 (the "minirank" row of Table 1) */
+    uint64_t mem_budget;      /* upper bound on the device bytes the build holds at once
+                                 (workspace plus the structure); 0 = no bound */
+    uint32_t keep_collisions; /* nonzero: keep every C_d so that mphf_export_collisions works */
+    uint32_t flags;           /* reserved, must be 0 */
+} mphf_opts;
+
+/* Per-level sizes and totals of a built function (all host values). */
+typedef struct mphf_stats {
+    uint64_t n;                               /* N */
+    double gamma;
+    uint64_t seed;
+    uint32_t num_levels;                      /* levels actually built (last + 1) */
+    uint32_t rank_sample;
+    uint64_t level_n[MPHF_MAX_LEVELS];        /* |F_d| */
+    uint64_t level_m[MPHF_MAX_LEVELS];        /* |A_d| = ceil(gamma |F_d|) */
+    uint64_t level_weight[MPHF_MAX_LEVELS];   /* ones in A_d = keys placed at level d */
+    uint64_t level_offset[MPHF_MAX_LEVELS];   /* bit offset of A_d in the concatenated A */
+    uint64_t level_seed[MPHF_MAX_LEVELS];     /* s_d */
+    uint64_t n_fallback;                      /* |L|, keys in the fallback table */
+    uint64_t total_bits;                      /* M, bits of the concatenated A (64-bit padded levels) */
+    uint64_t rank_entries;                    /* ceil(M / rank_sample) */
+    uint64_t structure_bytes;                 /* A + rank counters + fallback keys */
+    double bits_per_key;                      /* (M + 64 * rank_entries + 128 * n_fallback) / N */
+    uint64_t peak_bytes;                      /* most device bytes the build held at once */
+} mphf_stats_t;
+
+/* Read-only device views of a built function (owned by the handle). */
+typedef struct mphf_view {
+    const uint64_t* words;          /* concatenated A: bit p of level d is bit (o+p)%64 of word (o+p)/64,
+                                       o = level_offset[d]; padding bits are 0 */
+    const uint64_t* rank;           /* rank[b] = ones of A before bit b * rank_sample */
+    const uint64_t* fallback_keys;  /* ascending; key i has label N - n_fallback + 1 + i */
+    uint64_t total_words;
+    uint64_t rank_entries;
+    uint64_t n_fallback;
+} mphf_view_t;
+
+/* Fill *opts with the defaults (max_levels 25, rank_sample 512, no budget). */
+mphf_status mphf_default_opts(mphf_opts* opts);
+
+/* Build from n distinct device keys with parameter gamma (Section 2.2: |A_d| = gamma |F_d|,
+ * gamma >= 1) and hash seed `seed` (the level seeds s_d are the outputs of a SplitMix64
+ * stream started at `seed`).  Default options, null stream; returns once the function is
+ * complete.  NULL on error (see mphf_last_error). */
+mphf_t* mphf_build(const uint64_t* keys, uint64_t n, double gamma, uint64_t seed);
+
+/* Label each of the n device queries into the device array out (Algorithm 3): a key of the
+ * set gets its label in [1, N]; any other key gets a deterministic value, which is 0 when it
+ * falls through every level and is not in the fallback table (the footnote of Algorithm 3
+ * allows any value).  Synchronous on the null stream.  Returns an mphf_status. */
+int mphf_lookup(const mphf_t* h, const uint64_t* keys, uint64_t n, uint64_t* out);
+
+/* mphf_build with options (NULL = defaults) on `stream`.  The build reads the level sizes back
+ * to the host once per level, so it returns only when the function is complete on `stream`. */
+mphf_status mphf_build_ex(const uint64_t* keys, uint64_t n, double gamma, uint64_t seed,
+                          const mphf_opts* opts, void* stream, mphf_t** out);
+
+/* mphf_lookup enqueued on `stream`; returns without waiting.  `out` may not alias `keys`. */
+mphf_status mphf_lookup_ex(const mphf_t* h, const uint64_t* keys, uint64_t n, uint64_t* out,
+                           void* stream);
+
+/* Free every device buffer of h.  NULL is allowed. */
+void mphf_destroy(mphf_t* h);
+
+/* Sizes and per-level counts of h. */
+mphf_status mphf_stats(const mphf_t* h, mphf_stats_t* st);
+
+/* Device pointers to the structure of h, valid until mphf_destroy(h). */
+mphf_status mphf_view(const mphf_t* h, mphf_view_t* v);
+
+/* Copy the structure to host arrays (synchronous): `words` receives total_words words of the
+ * concatenated A, `rank` rank_entries counters, `fallback_keys` n_fallback keys.  Each size must
+ * equal the one mphf_stats reports; a NULL array with size 0 skips that part. */
+mphf_status mphf_export(const mphf_t* h, uint64_t* words, uint64_t nwords, uint64_t* rank,
+                        uint64_t nrank, uint64_t* fallback_keys, uint64_t nfb);
+
+/* Copy C_d (the collision array of level d, Section 2.2) into the host array out of
+ * ceil(level_m[d] / 64) words, packed like A_d.  Needs keep_collisions at build time. */
+mphf_status mphf_export_collisions(const mphf_t* h, uint32_t level, uint64_t* out, uint64_t nwords);
+
+/* The level-d position of each device key: fmix64(key XOR level_seed) mod m, the reduction of
+ * Algorithms 1-3, exactly as the build and lookup kernels compute it (m >= 1).  For checks of the
+ * hash and of the exact division by m; out is a device array of n words. */
+mphf_status mphf_positions(const uint64_t* keys, uint64_t n, uint64_t level_seed, uint64_t m,
+                           uint64_t* out, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mphf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPHF_H */

@@ -1,0 +1,439 @@
+// HIP kernels of the cascading-bit-array MPHF for gfx950 (wave64), and their launchers.
+//
+// Layouts in HBM:
+//  * W, the working array of the level being filled: 64-bit words, each holding 32 positions
+//    as an A half (bits 0..31) and a C half (bits 32..63), so that the collision bit of a
+//    position lives in the same word (and cache line) as its A bit.  Position p of the level
+//    is A bit p%32 / C bit 32+p%32 of word p/32.  2*ceil(m/64) words.
+//  * A, the concatenation of the finalized levels: bit p of level d is bit (o+p)%64 of word
+//    (o+p)/64 with o the level's bit offset, a multiple of 64; padding bits stay 0.
+//  * rank[b]: 64-bit count of the ones of A before position b*rank_sample.
+#include "internal.h"
+
+namespace mphfk {
+
+namespace {
+
+constexpr int NT = 256;          // threads per block for the streaming kernels
+constexpr int MAX_GRID = 8192;   // grid-stride kernels: enough blocks to fill 256 CUs
+
+inline unsigned grid_for(uint64_t items, uint64_t per_block) {
+    uint64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > MAX_GRID) b = MAX_GRID;
+    return (unsigned)b;
+}
+
+// Record one key landing on position p of the level held in W (Algorithm 2 with the
+// collision array): the first key sets the A bit; any later key finds it set and sets the
+// C bit.  The final state, A = exactly one key and C = two or more after the finalize step,
+// does not depend on the order of the atomics.
+__device__ __forceinline__ void mark(unsigned long long* W, uint64_t p) {
+    unsigned long long* w = W + (p >> 5);
+    const unsigned long long b = 1ull << (p & 31);
+    const unsigned long long old = atomicOr(w, b);
+    if (old & b) atomicOr(w, b << 32);
+}
+
+__global__ void k_zero(uint64_t* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+__global__ void k_fill(const uint64_t* __restrict__ keys, uint64_t n, unsigned long long* W,
+                       LevelHash L) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        mark(W, level_pos(keys[i], L));
+}
+
+// A_d = A & ~C over each pair of W words; weight(A_d) accumulated into *weight.
+__global__ void k_finalize(const ulonglong2* __restrict__ W, uint64_t nwords,
+                           uint64_t* __restrict__ A, uint64_t* __restrict__ C,
+                           unsigned long long* weight) {
+    __shared__ unsigned long long part[NT / 64];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long cnt = 0;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nwords; j += stride) {
+        const ulonglong2 v = W[j];
+        const uint64_t a0 = (uint32_t)v.x & ~(uint32_t)(v.x >> 32);
+        const uint64_t a1 = (uint32_t)v.y & ~(uint32_t)(v.y >> 32);
+        const uint64_t a = a0 | (a1 << 32);
+        A[j] = a;
+        if (C) C[j] = (v.x >> 32) | ((v.y >> 32) << 32);
+        cnt += __popcll(a);
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < NT / 64; ++i) s += part[i];
+        if (s) atomicAdd(weight, s);
+    }
+}
+
+// Filter of level d fused with the fill of level d+1 (Algorithm 1): a key whose A_d bit is 0
+// collided at level d, so it goes to F_{d+1} (compacted into Fout) and, when there is a next
+// level, is marked in W at its level d+1 position.  One block reserves its output range with
+// one atomic on *count; the order of F_{d+1} does not affect any result.
+template <int ITEMS>
+__global__ void k_filter_fill(const uint64_t* __restrict__ Fin, uint64_t n,
+                              const uint64_t* __restrict__ words, LevelHash Ld,
+                              uint64_t* __restrict__ Fout, uint64_t cap,
+                              unsigned long long* count, unsigned long long* W, LevelHash Ln,
+                              int do_fill) {
+    __shared__ uint32_t sh[NT / 64 + 1];
+    __shared__ unsigned long long base_sh;
+    constexpr uint64_t TILE = (uint64_t)NT * ITEMS;
+    const uint64_t ntiles = (n + TILE - 1) / TILE;
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const uint64_t t0 = t * TILE;
+        uint64_t k[ITEMS];
+        uint32_t surv = 0;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const uint64_t i = t0 + (uint64_t)it * NT + threadIdx.x;
+            k[it] = 0;
+            if (i < n) {
+                const uint64_t x = Fin[i];
+                k[it] = x;
+                const uint64_t g = Ld.bit_off + level_pos(x, Ld);
+                if (!((words[g >> 6] >> (g & 63)) & 1ull)) {
+                    surv |= 1u << it;
+                    if (do_fill) mark(W, level_pos(x, Ln));
+                }
+            }
+        }
+        const uint32_t c = __popc(surv);
+        uint32_t total;
+        const uint32_t pre = block_exclusive_sum<NT>(c, sh, &total);
+        if (threadIdx.x == 0) base_sh = total ? atomicAdd(count, (unsigned long long)total) : 0;
+        __syncthreads();
+        uint64_t o = base_sh + pre;
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            if ((surv >> it) & 1u) {
+                if (o < cap) Fout[o] = k[it];
+                ++o;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- rank table
+
+// Ones in each rank block of wpb words.
+__global__ void k_rank_counts(const uint64_t* __restrict__ words, uint64_t total_words,
+                              uint32_t wpb, uint32_t* __restrict__ counts, uint64_t nb) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+        const uint64_t w0 = b * wpb;
+        uint64_t w1 = w0 + wpb;
+        if (w1 > total_words) w1 = total_words;
+        uint32_t c = 0;
+        for (uint64_t w = w0; w < w1; ++w) c += __popcll(words[w]);
+        counts[b] = c;
+    }
+}
+
+// Three-phase exclusive scan of u32 counts into u64 prefixes.
+constexpr int SCAN_ITEMS = 16;
+constexpr uint64_t SCAN_TILE = (uint64_t)NT * SCAN_ITEMS;
+
+__global__ void k_scan_tile_sums(const uint32_t* __restrict__ in, uint64_t n,
+                                 uint64_t* __restrict__ tile_sums) {
+    __shared__ uint64_t part[NT / 64];
+    const uint64_t t = blockIdx.x;
+    const uint64_t i0 = t * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t s = 0;
+    for (int it = 0; it < SCAN_ITEMS; ++it)
+        if (i0 + it < n) s += in[i0 + it];
+    s = wave_sum(s);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t a = 0;
+        for (int i = 0; i < NT / 64; ++i) a += part[i];
+        tile_sums[t] = a;
+    }
+}
+
+__global__ void k_scan_tiles(uint64_t* __restrict__ tile_sums, uint64_t ntiles) {
+    __shared__ uint64_t sh[NT / 64 + 1];
+    uint64_t carry = 0;
+    for (uint64_t c0 = 0; c0 < ntiles; c0 += NT) {
+        const uint64_t i = c0 + threadIdx.x;
+        const uint64_t v = i < ntiles ? tile_sums[i] : 0;
+        uint64_t total;
+        const uint64_t pre = block_exclusive_sum<NT>(v, sh, &total);
+        if (i < ntiles) tile_sums[i] = carry + pre;
+        carry += total;
+    }
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n,
+                             const uint64_t* __restrict__ tile_off) {
+    __shared__ uint64_t sh[NT / 64 + 1];
+    const uint64_t t = blockIdx.x;
+    const uint64_t i0 = t * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint64_t s = 0;
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        v[it] = i0 + it < n ? in[i0 + it] : 0;
+        s += v[it];
+    }
+    uint64_t total;
+    uint64_t run = tile_off[t] + block_exclusive_sum<NT>(s, sh, &total);
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        if (i0 + it < n) out[i0 + it] = run;
+        run += v[it];
+    }
+}
+
+// ---------------------------------------------------------------- radix sort (fallback keys)
+
+constexpr int RADIX_ROUNDS = 8;
+constexpr uint64_t RADIX_TILE = (uint64_t)NT * RADIX_ROUNDS;
+
+__global__ void k_radix_hist(const uint64_t* __restrict__ in, uint64_t n, int shift,
+                             uint32_t* __restrict__ counts, uint64_t ntiles) {
+    __shared__ uint32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t = blockIdx.x;
+    for (int r = 0; r < RADIX_ROUNDS; ++r) {
+        const uint64_t i = t * RADIX_TILE + (uint64_t)r * NT + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(in[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(uint64_t)threadIdx.x * ntiles + t] = hist[threadIdx.x];
+}
+
+// Stable scatter: keys of a tile keep their order within each digit.
+__global__ void k_radix_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
+                                uint64_t n, int shift, const uint64_t* __restrict__ offsets,
+                                uint64_t ntiles) {
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[NT / 64][256];
+    running[threadIdx.x] = 0;
+    for (int w = 0; w < NT / 64; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t t = blockIdx.x;
+    const int w = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1;
+    for (int r = 0; r < RADIX_ROUNDS; ++r) {
+        const uint64_t i = t * RADIX_TILE + (uint64_t)r * NT + threadIdx.x;
+        const bool valid = i < n;
+        const uint64_t key = valid ? in[i] : 0;
+        const uint32_t dig = (uint32_t)(key >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t bb = __ballot(valid && bit);
+            match &= bit ? bb : ~bb;
+        }
+        const uint32_t rank = __popcll(match & lt);
+        if (valid && rank == 0) wcnt[w][dig] = __popcll(match);
+        __syncthreads();
+        if (valid) {
+            uint64_t pos = offsets[(uint64_t)dig * ntiles + t] + running[dig] + rank;
+            for (int v = 0; v < w; ++v) pos += wcnt[v][dig];
+            out[pos] = key;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int v = 0; v < NT / 64; ++v) {
+            add += wcnt[v][threadIdx.x];
+            wcnt[v][threadIdx.x] = 0;
+        }
+        running[threadIdx.x] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void k_find_duplicates(const uint64_t* __restrict__ s, uint64_t n,
+                                  unsigned long long* flag) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += stride)
+        if (s[i] == s[i + 1]) atomicOr(flag, 1ull);
+}
+
+// ---------------------------------------------------------------- lookup (Algorithm 3)
+
+__global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* __restrict__ out,
+                         const DevLevel* __restrict__ lev, uint32_t nlev,
+                         const uint64_t* __restrict__ words, const uint64_t* __restrict__ rank,
+                         uint32_t rank_shift, const uint64_t* __restrict__ fbk, uint64_t nfb,
+                         uint64_t N) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t x = q[i];
+        uint64_t label = 0;
+        bool found = false;
+        for (uint32_t d = 0; d < nlev; ++d) {
+            const DevLevel L = lev[d];
+            const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
+            const uint64_t wi = g >> 6;
+            const uint64_t w = words[wi];
+            if ((w >> (g & 63)) & 1ull) {
+                // ones before g = counter of its rank block + whole words of the block before wi
+                // + the bits of wi below g
+                const uint64_t b = g >> rank_shift;
+                uint64_t r = rank[b];
+                for (uint64_t k = (b << rank_shift) >> 6; k < wi; ++k) r += __popcll(words[k]);
+                r += __popcll(w & ((1ull << (g & 63)) - 1));
+                label = r + 1;
+                found = true;
+                break;
+            }
+        }
+        if (!found && nfb) {
+            uint64_t lo = 0, hi = nfb;   // first index with fbk[idx] >= x
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (fbk[mid] < x) lo = mid + 1; else hi = mid;
+            }
+            if (lo < nfb && fbk[lo] == x) label = N - nfb + 1 + lo;
+        }
+        out[i] = label;
+    }
+}
+
+__global__ void k_positions(const uint64_t* __restrict__ keys, uint64_t n, LevelHash L,
+                            uint64_t* __restrict__ out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = level_pos(keys[i], L);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+LevelHash make_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
+    // Granlund-Montgomery 1994, Figure 4.1, for 64-bit words: l = ceil(log2 m),
+    // magic = floor(2^64 (2^l - m) / m) + 1, sh1 = min(l, 1), sh2 = max(l - 1, 0).
+    LevelHash L{};
+    L.seed = seed;
+    L.m = m;
+    L.bit_off = bit_off;
+    if (m == 0) return L;   // an empty level is never hashed
+    uint32_t l = 0;
+    while (l < 64 && ((unsigned __int128)1 << l) < (unsigned __int128)m) ++l;
+    const unsigned __int128 num = (((unsigned __int128)1 << l) - m) << 64;
+    L.magic = (uint64_t)(num / m) + 1;
+    L.sh1 = l < 1 ? l : 1;
+    L.sh2 = l > 1 ? l - 1 : 0;
+    return L;
+}
+
+hipError_t launch_zero(uint64_t* p, uint64_t nwords, hipStream_t s) {
+    if (!nwords) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(nwords, NT * 4)), dim3(NT), 0, s, p, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const uint64_t* keys, uint64_t n, uint64_t* W, const LevelHash& L,
+                       hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, keys, n,
+                       (unsigned long long*)W, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const uint64_t* W, uint64_t nwords, uint64_t* A, uint64_t* C,
+                           unsigned long long* weight, hipStream_t s) {
+    if (!nwords) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(grid_for(nwords, NT * 4)), dim3(NT), 0, s,
+                       (const ulonglong2*)W, nwords, A, C, weight);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_fill(const uint64_t* Fin, uint64_t n, const uint64_t* words,
+                              const LevelHash& Ld, uint64_t* Fout, uint64_t cap,
+                              unsigned long long* count, uint64_t* W, const LevelHash& Lnext,
+                              bool do_fill, hipStream_t s) {
+    if (!n) return hipSuccess;
+    constexpr int ITEMS = 16;
+    hipLaunchKernelGGL(k_filter_fill<ITEMS>, dim3(grid_for(n, (uint64_t)NT * ITEMS)), dim3(NT), 0,
+                       s, Fin, n, words, Ld, Fout, cap, count, (unsigned long long*)W, Lnext,
+                       do_fill ? 1 : 0);
+    return hipGetLastError();
+}
+
+uint64_t scan_tmp_tiles(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
+                                 hipStream_t s) {
+    if (!n) return hipSuccess;
+    const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(NT), 0, s, in, n, tmp_tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(NT), 0, s, tmp_tiles, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(NT), 0, s, in, out, n, tmp_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const uint64_t* words, uint64_t total_words, uint32_t rank_sample,
+                       uint64_t* rank, uint64_t nrank, uint32_t* tmp_counts, uint64_t* tmp_tiles,
+                       hipStream_t s) {
+    if (!nrank) return hipSuccess;
+    hipLaunchKernelGGL(k_rank_counts, dim3(grid_for(nrank, NT)), dim3(NT), 0, s, words, total_words,
+                       rank_sample / 64, tmp_counts, nrank);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_exclusive_scan(tmp_counts, rank, nrank, tmp_tiles, s);
+}
+
+uint64_t radix_tmp_counts(uint64_t n) { return 256 * ((n + RADIX_TILE - 1) / RADIX_TILE); }
+
+hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t n, uint32_t* counts,
+                          uint64_t* offsets, uint64_t* tmp_tiles, hipStream_t s) {
+    if (n < 2) return hipSuccess;
+    const uint64_t ntiles = (n + RADIX_TILE - 1) / RADIX_TILE;
+    uint64_t* src = a;
+    uint64_t* dst = b;
+    for (int shift = 0; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(NT), 0, s, src, n, shift,
+                           counts, ntiles);
+        hipError_t e = launch_exclusive_scan(counts, offsets, 256 * ntiles, tmp_tiles, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(NT), 0, s, src, dst, n,
+                           shift, offsets, ntiles);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t* t = src;
+        src = dst;
+        dst = t;
+    }
+    return hipSuccess;   // eight passes: the result is back in a
+}
+
+hipError_t launch_find_duplicates(const uint64_t* sorted, uint64_t n, unsigned long long* flag,
+                                  hipStream_t s) {
+    if (n < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_find_duplicates, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, sorted, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
+                         uint32_t nlev, const uint64_t* words, const uint64_t* rank,
+                         uint32_t rank_shift, const uint64_t* fb_keys, uint64_t nfb, uint64_t N,
+                         hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_lookup, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, q, n, out, lev, nlev,
+                       words, rank, rank_shift, fb_keys, nfb, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
+                            hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_positions, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, keys, n, L, out);
+    return hipGetLastError();
+}
+
+}  // namespace mphfk

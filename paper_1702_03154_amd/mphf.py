@@ -1,0 +1,212 @@
+"""Python binding of ``libmphf.so`` (ctypes): argument marshalling only.
+
+Every step of the build and of the lookup runs in the library's HIP kernels.
+PyTorch supplies device memory and the current stream, nothing else.  If the
+library is missing, every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmphf.so")
+MAX_LEVELS = 64
+
+OK, E_INVALID, E_NOMEM, E_DUPLICATE_KEYS, E_DEVICE = range(5)
+
+
+class MphfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mphf status {status}: {msg}")
+        self.status = status
+
+
+class DuplicateKeysError(MphfError):
+    pass
+
+
+class Opts(C.Structure):
+    _fields_ = [("max_levels", C.c_uint32), ("rank_sample", C.c_uint32),
+                ("mem_budget", C.c_uint64), ("keep_collisions", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+_U64L = C.c_uint64 * MAX_LEVELS
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("gamma", C.c_double), ("seed", C.c_uint64),
+                ("num_levels", C.c_uint32), ("rank_sample", C.c_uint32),
+                ("level_n", _U64L), ("level_m", _U64L), ("level_weight", _U64L),
+                ("level_offset", _U64L), ("level_seed", _U64L),
+                ("n_fallback", C.c_uint64), ("total_bits", C.c_uint64),
+                ("rank_entries", C.c_uint64), ("structure_bytes", C.c_uint64),
+                ("bits_per_key", C.c_double), ("peak_bytes", C.c_uint64)]
+
+
+class View(C.Structure):
+    _fields_ = [("words", C.c_void_p), ("rank", C.c_void_p), ("fallback_keys", C.c_void_p),
+                ("total_words", C.c_uint64), ("rank_entries", C.c_uint64),
+                ("n_fallback", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libmphf.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32, st = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
+        sig = {
+            "mphf_default_opts": (st, [C.POINTER(Opts)]),
+            "mphf_build": (vp, [vp, u64, C.c_double, u64]),
+            "mphf_lookup": (C.c_int, [vp, vp, u64, vp]),
+            "mphf_build_ex": (st, [vp, u64, C.c_double, u64, C.POINTER(Opts), vp, C.POINTER(vp)]),
+            "mphf_lookup_ex": (st, [vp, vp, u64, vp, vp]),
+            "mphf_destroy": (None, [vp]),
+            "mphf_stats": (st, [vp, C.POINTER(Stats)]),
+            "mphf_view": (st, [vp, C.POINTER(View)]),
+            "mphf_export": (st, [vp, vp, u64, vp, u64, vp, u64]),
+            "mphf_export_collisions": (st, [vp, u32, vp, u64]),
+            "mphf_positions": (st, [vp, u64, u64, u64, vp, vp]),
+            "mphf_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        msg = lib().mphf_last_error().decode(errors="replace")
+        cls = DuplicateKeysError if status == E_DUPLICATE_KEYS else MphfError
+        raise cls(status, msg)
+
+
+def _dev(t: torch.Tensor, name: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a tensor in GPU memory")
+    if t.dtype not in (torch.int64, torch.uint64) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 64-bit integer tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class _DeviceArray:
+    """A device buffer owned by the library, seen by torch without a copy."""
+
+    def __init__(self, ptr: int, n: int):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i8", "data": (ptr, True),
+                                         "version": 2, "strides": None}
+
+
+class MPHF:
+    """A built function; owns its device memory until close()."""
+
+    def __init__(self, handle: int, keys_device: torch.device):
+        self._h = handle
+        self.device = keys_device
+
+    @classmethod
+    def build(cls, keys: torch.Tensor, gamma: float = 2.0, seed: int = 0, max_levels: int = 25,
+              rank_sample: int = 512, mem_budget: int = 0, keep_collisions: bool = False,
+              stream=None) -> "MPHF":
+        L = lib()
+        ptr = _dev(keys, "keys") if keys.numel() else (keys.data_ptr() if keys.is_cuda else 0)
+        if not keys.is_cuda:
+            raise ValueError("keys must be a tensor in GPU memory")
+        o = Opts(max_levels, rank_sample, mem_budget, 1 if keep_collisions else 0, 0)
+        h = C.c_void_p()
+        with torch.cuda.device(keys.device):
+            _check(L.mphf_build_ex(ptr, keys.numel(), float(gamma), seed & (2**64 - 1), C.byref(o),
+                                   _stream(stream), C.byref(h)))
+        return cls(h.value, keys.device)
+
+    def lookup(self, queries: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(queries.numel(), dtype=torch.int64, device=queries.device)
+        if queries.numel():
+            _check(lib().mphf_lookup_ex(self._h, _dev(queries, "queries"), queries.numel(),
+                                        _dev(out, "out"), _stream(stream)))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().mphf_stats(self._h, C.byref(s)))
+        L = s.num_levels
+        return {
+            "n": s.n, "gamma": s.gamma, "seed": s.seed, "num_levels": L,
+            "rank_sample": s.rank_sample,
+            "level_n": list(s.level_n[:L]), "level_m": list(s.level_m[:L]),
+            "level_weight": list(s.level_weight[:L]), "level_offset": list(s.level_offset[:L]),
+            "level_seed": list(s.level_seed[:L]), "n_fallback": s.n_fallback,
+            "total_bits": s.total_bits, "rank_entries": s.rank_entries,
+            "structure_bytes": s.structure_bytes, "bits_per_key": s.bits_per_key,
+            "peak_bytes": s.peak_bytes,
+        }
+
+    def export(self) -> dict:
+        """Host copies (numpy uint64) of the concatenated A, the rank table and H's keys."""
+        st = self.stats()
+        w = np.zeros(st["total_bits"] // 64, dtype=np.uint64)
+        r = np.zeros(st["rank_entries"], dtype=np.uint64)
+        f = np.zeros(st["n_fallback"], dtype=np.uint64)
+        _check(lib().mphf_export(self._h, w.ctypes.data, len(w), r.ctypes.data, len(r),
+                                 f.ctypes.data, len(f)))
+        return {"words": w, "rank": r, "fallback_keys": f}
+
+    def export_collisions(self, level: int) -> np.ndarray:
+        m = self.stats()["level_m"][level]
+        out = np.zeros((m + 63) // 64, dtype=np.uint64)
+        _check(lib().mphf_export_collisions(self._h, level, out.ctypes.data, len(out)))
+        return out
+
+    def device_views(self) -> dict:
+        """int64 torch views (no copy) of the device words, rank table and fallback keys."""
+        v = View()
+        _check(lib().mphf_view(self._h, C.byref(v)))
+        res = {}
+        for name, ptr, n in (("words", v.words, v.total_words), ("rank", v.rank, v.rank_entries),
+                             ("fallback_keys", v.fallback_keys, v.n_fallback)):
+            res[name] = (torch.as_tensor(_DeviceArray(ptr, n), device=self.device) if n
+                         else torch.zeros(0, dtype=torch.int64, device=self.device))
+        return res
+
+    def close(self):
+        if self._h:
+            lib().mphf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build(keys: torch.Tensor, gamma: float = 2.0, seed: int = 0, **kw) -> MPHF:
+    return MPHF.build(keys, gamma, seed, **kw)
+
+
+def positions(keys: torch.Tensor, level_seed: int, m: int, stream=None) -> torch.Tensor:
+    """The device level-hash position of each key (the kernels' hash and exact mod)."""
+    out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    if keys.numel():
+        _check(lib().mphf_positions(_dev(keys, "keys"), keys.numel(), level_seed & (2**64 - 1), m,
+                                    _dev(out, "out"), _stream(stream)))
+    return out

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every bit array A_d and C_d, the rank table, the fallback table, the level sizes
+and every label must be identical (bit-exact: the method is integer work whose
+result does not depend on the order of the atomics)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mphf_oracle as O
+from paper_1702_03154_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+U64 = (1 << 64) - 1
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_03154_amd import mphf
+    mphf.lib()
+    return mphf
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def check_against_oracle(M, keys_np, gamma, seed=0, max_levels=25, rank_sample=512,
+                         queries_np=None):
+    keys = torch.from_numpy(keys_np.view(np.int64)).cuda()
+    h = M.build(keys, gamma, seed, max_levels=max_levels, rank_sample=rank_sample,
+                keep_collisions=True)
+    st = O.build(keys_np, gamma, seed, max_levels=max_levels, rank_sample=rank_sample)
+    s = h.stats()
+    assert s["num_levels"] == st.num_levels
+    assert s["level_n"] == [l.n for l in st.levels]
+    assert s["level_m"] == [l.m for l in st.levels]
+    assert s["level_weight"] == [l.weight for l in st.levels]
+    assert s["level_offset"] == [l.offset for l in st.levels]
+    assert s["level_seed"] == [l.seed for l in st.levels]
+    assert s["total_bits"] == st.total_bits
+    assert s["n_fallback"] == len(st.fallback_keys)
+    ex = h.export()
+    assert np.array_equal(ex["words"], st.words)
+    assert np.array_equal(ex["rank"], st.rank)
+    assert np.array_equal(ex["fallback_keys"], st.fallback_keys)
+    for d in range(st.num_levels):
+        assert np.array_equal(h.export_collisions(d), O.collision_words(st, d)), d
+    lab = host(h.lookup(keys))
+    want = O.lookup(st, keys_np)
+    assert np.array_equal(lab, want)
+    if queries_np is not None:
+        q = torch.from_numpy(queries_np.view(np.int64)).cuda()
+        assert np.array_equal(host(h.lookup(q)), O.lookup(st, queries_np))
+    assert abs(s["bits_per_key"] - st.bits_per_key) < 1e-9
+    h.close()
+    return st
+
+
+def keys_np(n, seed=1):
+    return I.keys(n, seed).numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------ hash + exact mod
+
+@pytest.mark.parametrize("m", [1, 2, 3, 7, 64, 1000, 1_000_003, 2**31 - 1, 2_000_000_000, 2**32 - 1,
+                               2**32, 2**32 + 15, 6_000_000_001, 2**40 - 3, 2**52 + 7, 2**62 + 1,
+                               2**63 - 1])
+def test_device_positions_equal_plain_mod(M, m):
+    rng = np.random.default_rng(m % 1000)
+    k = np.concatenate([np.array([0, 1, 2, U64, U64 - 1, 2**63, 2**63 - 1, 2**32, 2**32 - 1],
+                                 dtype=np.uint64),
+                        keys_np(20_000, seed=m % 97),
+                        rng.integers(0, 2**63, size=2000, dtype=np.uint64) * np.uint64(2)])
+    for seed in (0, 0x9E3779B97F4A7C15, U64):
+        got = host(M.positions(torch.from_numpy(k.view(np.int64)).cuda(), seed, m))
+        assert np.array_equal(got, O.level_positions(k, seed, m)), (m, seed)
+
+
+def test_device_mod_on_hash_values_near_the_top(M):
+    # keys chosen so that fmix64(key ^ 0) covers h near 2^64 - 1 is not controllable; instead use
+    # the bijection: invert fmix64 on the host for chosen h values.
+    inv1 = pow(0xFF51AFD7ED558CCD, -1, 1 << 64)
+    inv2 = pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)
+
+    def unfmix(y):
+        z = y ^ (y >> 33)
+        z = (z * inv2) & U64
+        z ^= z >> 33
+        z = (z * inv1) & U64
+        return z ^ (z >> 33)
+
+    hs = [U64 - i for i in range(64)] + [(1 << 63) + i for i in range(-32, 32)] + list(range(64))
+    k = np.array([unfmix(h) for h in hs], dtype=np.uint64)
+    assert np.array_equal(O.fmix64(k), np.array(hs, dtype=np.uint64))
+    for m in (3, 1000, 2**32 + 1, 2**61 - 1, 2**63 - 25):
+        got = host(M.positions(torch.from_numpy(k.view(np.int64)).cuda(), 0, m))
+        assert np.array_equal(got, np.array([h % m for h in hs], dtype=np.uint64))
+
+
+# ------------------------------------------------------------ whole structure
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 5, 64, 100, 1000, 4097, 33_333, 100_000])
+@pytest.mark.parametrize("gamma", [1.0, 2.0])
+def test_parity_small(M, n, gamma):
+    absent = keys_np(3000, seed=77)
+    check_against_oracle(M, keys_np(n), gamma, queries_np=absent)
+
+
+@pytest.mark.parametrize("gamma", [1.5, 3.7, 5.0, 10.0])
+def test_parity_other_gammas(M, gamma):
+    check_against_oracle(M, keys_np(50_000, seed=3), gamma, seed=11)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, U64])
+def test_parity_seeds(M, seed):
+    check_against_oracle(M, keys_np(20_000, seed=5), 2.0, seed=seed)
+
+
+def test_parity_config1_1e6_gamma2(M):
+    """1e6 SplitMix64 keys (seed 1), gamma 2, every key queried in input order."""
+    k = keys_np(1_000_000)
+    assert len(np.unique(k)) == len(k)
+    st = check_against_oracle(M, k, 2.0)
+    assert len(st.fallback_keys) == 0
+
+
+def test_parity_1e6_gamma1_with_fallback(M):
+    st = check_against_oracle(M, keys_np(1_000_000), 1.0, queries_np=keys_np(100_000, seed=9))
+    assert st.num_levels == 25 and len(st.fallback_keys) > 0
+
+
+def test_parity_minirank(M):
+    check_against_oracle(M, keys_np(200_000), 1.0, rank_sample=1024)
+
+
+@pytest.mark.parametrize("max_levels", [1, 2, 3])
+def test_parity_forced_fallback(M, max_levels):
+    st = check_against_oracle(M, keys_np(100_000, seed=4), 2.0, max_levels=max_levels)
+    assert len(st.fallback_keys) > 1000
+
+
+def test_parity_structured_keys(M):
+    # dense small integers and a strided set: the hash must still spread them
+    k = np.concatenate([np.arange(1, 50_001, dtype=np.uint64),
+                        np.arange(50_001, dtype=np.uint64) * np.uint64(2**40) + np.uint64(2**63)])
+    check_against_oracle(M, np.unique(k), 2.0)
+
+
+def test_order_independence_on_gpu(M):
+    k = keys_np(300_000)
+    t = torch.from_numpy(k.view(np.int64)).cuda()
+    a = M.build(t, 2.0, 0)
+    perm = torch.randperm(len(k), generator=torch.Generator().manual_seed(3)).cuda()
+    b = M.build(t[perm].contiguous(), 2.0, 0)
+    ea, eb = a.export(), b.export()
+    assert np.array_equal(ea["words"], eb["words"]) and np.array_equal(ea["rank"], eb["rank"])
+    assert torch.equal(a.lookup(t), b.lookup(t))
+
+
+def test_repeat_builds_identical(M):
+    t = torch.from_numpy(keys_np(200_000).view(np.int64)).cuda()
+    ref = M.build(t, 1.0, 0).export()["words"]
+    for _ in range(3):
+        assert np.array_equal(M.build(t, 1.0, 0).export()["words"], ref)
+
+
+# ------------------------------------------------------------ errors and edge cases
+
+def test_duplicate_keys(M):
+    k = keys_np(10_000)
+    k[9000] = k[10]
+    with pytest.raises(M.DuplicateKeysError):
+        M.build(torch.from_numpy(k.view(np.int64)).cuda(), 2.0)
+
+
+def test_invalid_arguments(M):
+    t = torch.from_numpy(keys_np(100).view(np.int64)).cuda()
+    for g in (0.99, float("nan"), float("inf"), -2.0):
+        with pytest.raises(M.MphfError) as e:
+            M.build(t, g)
+        assert e.value.status == M.E_INVALID
+    for kw in ({"max_levels": 0}, {"max_levels": 65}, {"rank_sample": 256}):
+        with pytest.raises(M.MphfError):
+            M.build(t, 2.0, **kw)
+
+
+def test_host_pointer_rejected(M):
+    import ctypes
+    k = keys_np(16)
+    h = ctypes.c_void_p()
+    st = M.lib().mphf_build_ex(k.ctypes.data, 16, 2.0, 0, None, None, ctypes.byref(h))
+    assert st == M.E_INVALID and not h.value
+
+
+def test_mem_budget(M):
+    t = torch.from_numpy(keys_np(100_000).view(np.int64)).cuda()
+    with pytest.raises(M.MphfError) as e:
+        M.build(t, 2.0, mem_budget=4096)
+    assert e.value.status == M.E_NOMEM
+    h = M.build(t, 2.0, mem_budget=64 << 20)
+    assert 0 < h.stats()["peak_bytes"] <= 64 << 20
+
+
+def test_empty_and_single(M):
+    e = torch.zeros(0, dtype=torch.int64, device="cuda")
+    h = M.build(e, 2.0)
+    assert h.stats()["num_levels"] == 0
+    q = torch.from_numpy(keys_np(10).view(np.int64)).cuda()
+    assert h.lookup(q).tolist() == [0] * 10
+    one = q[:1].contiguous()
+    h1 = M.build(one, 1.0)
+    assert h1.lookup(one).tolist() == [1]
+
+
+def test_concurrent_lookups_on_streams(M):
+    k = keys_np(500_000)
+    t = torch.from_numpy(k.view(np.int64)).cuda()
+    h = M.build(t, 2.0)
+    ref = h.lookup(t)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    outs = []
+    for i, s in enumerate(streams):
+        with torch.cuda.stream(s):
+            outs.append(h.lookup(t[i::4].contiguous(), stream=s))
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert torch.equal(o, ref[i::4])
