@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--gamma", type=float, default=2.0)
     ap.add_argument("--cpu-sample", type=float, default=2e7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported on this build "
@@ -65,6 +67,13 @@ def main():
     out = torch.empty(n, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     print(f"# inputs ready: {n} keys", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     s = torch.cuda.current_stream()
     build_ms, lookup_ms, step_ms = [], [], []

@@ -57,8 +57,12 @@ typedef struct mphf_opts {
     uint64_t mem_budget;      /* upper bound on the device bytes the build holds at once
                                  (workspace plus the structure); 0 = no bound */
     uint32_t keep_collisions; /* nonzero: keep every C_d so that mphf_export_collisions works */
-    uint32_t flags;           /* reserved, must be 0 */
+    uint32_t flags;           /* 0, or MPHF_FLAG_ATOMIC_LEVELS */
 } mphf_opts;
+
+/* Build every level by global atomic test-and-set on the interleaved A/C words instead of the
+ * default position-partitioned LDS passes.  Same result, slower; for comparison and tests. */
+#define MPHF_FLAG_ATOMIC_LEVELS 1u
 
 /* Per-level sizes and totals of a built function (all host values). */
 typedef struct mphf_stats {
@@ -78,6 +82,8 @@ typedef struct mphf_stats {
     uint64_t structure_bytes;                 /* A + rank counters + fallback keys */
     double bits_per_key;                      /* (M + 64 * rank_entries + 128 * n_fallback) / N */
     uint64_t peak_bytes;                      /* most device bytes the build held at once */
+    uint64_t lookup_bytes;                    /* the lookup's copy of A: 64-byte sectors that each hold a
+                                                 32-bit rank counter and 480 bits, plus superblock counters */
 } mphf_stats_t;
 
 /* Read-only device views of a built function (owned by the handle). */
@@ -86,6 +92,7 @@ typedef struct mphf_view {
                                        o = level_offset[d]; padding bits are 0 */
     const uint64_t* rank;           /* rank[b] = ones of A before bit b * rank_sample */
     const uint64_t* fallback_keys;  /* ascending; key i has label N - n_fallback + 1 + i */
+    const uint64_t* collisions;     /* C of every level laid out like A, or NULL without keep_collisions */
     uint64_t total_words;
     uint64_t rank_entries;
     uint64_t n_fallback;
@@ -139,6 +146,10 @@ mphf_status mphf_export_collisions(const mphf_t* h, uint32_t level, uint64_t* ou
  * hash and of the exact division by m; out is a device array of n words. */
 mphf_status mphf_positions(const uint64_t* keys, uint64_t n, uint64_t level_seed, uint64_t m,
                            uint64_t* out, void* stream);
+
+/* Free the build temporaries the library keeps per device between builds (a few times the
+ * largest key set built so far).  Must not overlap a build. */
+mphf_status mphf_trim(void);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* mphf_last_error(void);

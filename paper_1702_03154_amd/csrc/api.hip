@@ -1,7 +1,11 @@
 // Host runtime and C ABI: the level driver of the build (Algorithm 1), the fallback table,
 // the rank table and the lookup entry points.  Every step of the method runs in the kernels of
 // kernels.hip; the host only sizes levels, allocates, and reads one count back per level.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -32,14 +36,39 @@ struct mphf {
     uint32_t rank_shift = 9;
     uint64_t* fb_keys = nullptr;
     uint64_t nfb = 0;
+    uint32_t* sec = nullptr;        // lookup layout: 64-byte sectors of (rank counter, 480 bits of A)
+    uint64_t* super = nullptr;
+    uint64_t nsec = 0;
     DevLevel* dlev = nullptr;
-    std::vector<uint64_t*> coll;
+    uint64_t* coll_all = nullptr;   // C of every level, laid out like A (keep_collisions)
     uint64_t peak_bytes = 0;
 };
 
 namespace {
 
 thread_local std::string g_err;
+
+// Optional host-side phase trace of the build (MPHF_TRACE=1 in the environment): wall time of
+// each phase after a stream synchronisation, printed to stderr.
+struct Trace {
+    bool on;
+    hipStream_t s;
+    std::chrono::steady_clock::time_point t0, last;
+    explicit Trace(hipStream_t st) : s(st) {
+        const char* e = std::getenv("MPHF_TRACE");
+        on = e && *e && *e != '0';
+        t0 = last = std::chrono::steady_clock::now();
+    }
+    void mark(const char* what, long a = -1) {
+        if (!on) return;
+        (void)hipStreamSynchronize(s);
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[mphf] %-22s %9.3f ms (total %9.3f)  %ld\n", what,
+                     std::chrono::duration<double, std::milli>(now - last).count(),
+                     std::chrono::duration<double, std::milli>(now - t0).count(), a);
+        last = now;
+    }
+};
 
 mphf_status fail(mphf_status st, const std::string& msg) {
     g_err = msg;
@@ -82,14 +111,58 @@ void level_seeds(uint64_t seed, uint32_t count, uint64_t* out) {
 // |A_d| = gamma |F_d| (Section 2.2), rounded up; the product is taken in IEEE double.
 uint64_t level_size(double gamma, uint64_t n) { return (uint64_t)std::ceil(gamma * (double)n); }
 
+// Device memory comes from the stream-ordered allocator (hipMallocAsync) with the device's
+// default pool set to keep freed memory, so repeated builds reuse their workspace instead of
+// paying hipMalloc each time.
+void configure_pool(int dev) {
+    static std::mutex mu;
+    static bool done[64] = {};
+    std::lock_guard<std::mutex> g(mu);
+    if (dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    done[dev] = true;
+}
+
+// Temporaries of the partitioned levels (a few times the key set) and the pinned readback buffer,
+// kept per device between builds so that repeated builds reuse them.  A build takes its device's
+// workspace if no other build holds it, else it allocates private temporaries; a build with a
+// memory budget always uses private temporaries so that the budget counts them.
+struct WsBufs {
+    uint64_t *Z = nullptr, *X = nullptr, *Y[2] = {nullptr, nullptr}, *preZ = nullptr,
+             *preY[2] = {nullptr, nullptr}, *tiles = nullptr, *host = nullptr;
+    uint16_t* Xlp = nullptr;
+    uint32_t *cntZ = nullptr, *cntX = nullptr, *surv[2] = {nullptr, nullptr};
+    uint64_t capZ = 0, capX = 0, capXlp = 0, capCntZ = 0, capCntX = 0, capTiles = 0, capPreZ = 0;
+    uint64_t capY[2] = {0, 0}, capSurv[2] = {0, 0}, capPreY[2] = {0, 0};
+};
+
+struct Workspace {
+    std::mutex mu;
+    WsBufs b;
+    void release() {
+        void* bufs[] = {b.Z, b.X, b.Y[0], b.Y[1], b.preZ, b.preY[0], b.preY[1], b.tiles, b.Xlp, b.cntZ,
+                        b.cntX, b.surv[0], b.surv[1]};
+        for (void* q : bufs)
+            if (q) (void)hipFree(q);
+        if (b.host) (void)hipHostFree(b.host);
+        b = WsBufs();
+    }
+};
+Workspace g_ws[64];
+
 // Device memory of one build: every buffer is released when the builder goes out of scope
 // unless it was handed to the finished function.  Tracks the bytes held against mem_budget.
 class Arena {
   public:
-    explicit Arena(uint64_t budget) : budget_(budget) {}
+    Arena(uint64_t budget, hipStream_t s) : budget_(budget), s_(s) {}
     ~Arena() {
         for (auto& b : bufs_)
-            if (b.first) (void)hipFree(b.first);
+            if (b.first) (void)hipFreeAsync(b.first, s_);
     }
     template <typename T>
     mphf_status alloc(T** p, uint64_t count, const char* what) {
@@ -99,7 +172,7 @@ class Arena {
         if (budget_ && held_ + bytes > budget_)
             return fail(MPHF_E_NOMEM, std::string(what) + ": mem_budget exceeded");
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, bytes);
+        hipError_t e = hipMallocAsync(&q, bytes, s_);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return hip_fail(e, what);
@@ -110,11 +183,11 @@ class Arena {
         *p = (T*)q;
         return MPHF_OK;
     }
-    void release(void* p) {   // free now
+    void release(void* p) {   // free (in stream order)
         if (!p) return;
         for (auto& b : bufs_)
             if (b.first == p) {
-                (void)hipFree(p);
+                (void)hipFreeAsync(p, s_);
                 held_ -= b.second;
                 b.first = nullptr;
                 return;
@@ -127,17 +200,20 @@ class Arena {
     uint64_t peak() const { return peak_; }
 
   private:
-    uint64_t budget_, held_ = 0, peak_ = 0;
+    uint64_t budget_;
+    hipStream_t s_;
+    uint64_t held_ = 0, peak_ = 0;
     std::vector<std::pair<void*, uint64_t>> bufs_;
 };
 
 void free_handle(mphf* h) {
     if (!h) return;
-    (void)hipFree(h->words);
-    (void)hipFree(h->rank);
-    (void)hipFree(h->fb_keys);
-    (void)hipFree(h->dlev);
-    for (uint64_t* c : h->coll) (void)hipFree(c);
+    // lookups may still be in flight on any stream: wait for the device before freeing
+    (void)hipDeviceSynchronize();
+    void* bufs[] = {h->words, h->rank, h->fb_keys, h->dlev, h->coll_all, h->sec, h->super};
+    for (void* p : bufs)
+        if (p) (void)hipFreeAsync(p, nullptr);
+    (void)hipStreamSynchronize(nullptr);
     delete h;
 }
 
@@ -146,9 +222,502 @@ mphf_status check_opts(const mphf_opts& o) {
         return fail(MPHF_E_INVALID, "max_levels must be in 1..64");
     if (o.rank_sample != 512 && o.rank_sample != 1024)
         return fail(MPHF_E_INVALID, "rank_sample must be 512 or 1024");
-    if (o.flags) return fail(MPHF_E_INVALID, "flags must be 0");
+    if (o.flags & ~(uint32_t)MPHF_FLAG_ATOMIC_LEVELS) return fail(MPHF_E_INVALID, "unknown flags");
     return MPHF_OK;
 }
+
+// A key set on the device: dense (one segment of stride 0) or partitioned into segments
+// s = 0..nseg-1 holding keys base[s*stride ..], with exclusive prefix pre[0..nseg] of their sizes.
+struct KeySet {
+    const uint64_t* base = nullptr;
+    uint64_t stride = 0;
+    const uint64_t* pre = nullptr;
+    uint32_t nseg = 0;
+    uint64_t n = 0;
+};
+
+// Capacity of a region expected to receive e keys: 8 standard deviations and a margin above e.
+uint64_t region_cap(double e) { return (uint64_t)std::ceil(e + 8.0 * std::sqrt(e) + 64.0); }
+
+uint32_t ceil_log2(uint64_t x) {
+    uint32_t l = 0;
+    while (l < 64 && (1ull << l) < x) ++l;
+    return l;
+}
+
+class Builder {
+  public:
+    Builder(mphf* h, const mphf_opts& o, hipStream_t s)
+        : h_(h), o_(o), s_(s), ar_(o.mem_budget, s), tr_(s) {}
+    ~Builder() {
+        if (host_ && !cached_) (void)hipHostFree(host_);
+    }
+
+    mphf_status run(const uint64_t* keys, uint64_t n, double gamma) {
+        mphf_status st;
+        gamma_ = gamma;
+        acquire_workspace();
+        level_seeds(h_->seed, o_.max_levels, seeds_.s);
+        if (cached_ && ws_->host) {
+            host_ = ws_->host;
+        } else {
+            HIP_TRY(hipHostMalloc((void**)&host_, 4096, hipHostMallocDefault), "hipHostMalloc");
+            if (cached_) ws_->host = host_;
+        }
+        if ((st = ar_.alloc(&dev_, 512, "counters")) != MPHF_OK) return st;
+        HIP_TRY(launch_zero(dev_, 512, s_), "zero counters");
+        if ((st = ar_.alloc(&tail_rec_, MPHF_MAX_LEVELS, "tail records")) != MPHF_OK) return st;
+        // The concatenated A: reserve the expected gamma e^{1/gamma} N bits (Section 2.3) plus
+        // slack; grown by copying in the rare case the levels need more.
+        {
+            const double expect = gamma * std::exp(1.0 / gamma) * (double)n;
+            const uint64_t w0 = (level_size(gamma, n) + 63) / 64;
+            uint64_t cap = (uint64_t)(expect * 1.02 / 64.0) + 4 * (uint64_t)o_.max_levels + 1024;
+            if (cap < w0 + 1) cap = w0 + 1;
+            if ((st = ensure_words(cap)) != MPHF_OK) return st;
+        }
+        tr_.mark("setup");
+        const bool atomic_only = o_.flags & MPHF_FLAG_ATOMIC_LEVELS;
+        KeySet cur;
+        uint64_t* pre0 = nullptr;
+        if ((st = ar_.alloc(&pre0, 2, "prefix")) != MPHF_OK) return st;
+        host_[0] = 0;
+        host_[1] = n;
+        HIP_TRY(hipMemcpyAsync(pre0, host_, 16, hipMemcpyHostToDevice, s_), "copy prefix");
+        cur.base = keys;
+        cur.pre = pre0;
+        cur.nseg = 1;
+        cur.n = n;
+
+        uint32_t d = 0;
+        uint64_t off = 0;
+        const uint32_t D = o_.max_levels;
+        const uint32_t tk = tail_capacity(gamma);
+        const BucketGeometry geo = bucket_geometry(gamma);
+        bool fallback = atomic_only || geo.pbits == 0;
+        while (!fallback && cur.n > 0 && d < D) {
+            if (cur.n <= tk) {
+                if ((st = tail(cur, d, off, tk)) != MPHF_OK) return st;
+                tr_.mark("tail", (long)h_->num_levels);
+                cur.n = 0;   // the tail built every remaining level and wrote the leftovers
+                d = h_->num_levels;
+                break;
+            }
+            KeySet next;
+            bool ok = false;
+            if ((st = partitioned_level(cur, d, off, geo, &next, &ok)) != MPHF_OK) return st;
+            tr_.mark("partitioned level", (long)d);
+            if (!ok) {
+                fallback = true;
+                break;
+            }
+            off += 64 * ((h_->level_m[d] + 63) / 64);
+            ++d;
+            cur = next;
+        }
+        if (cur.n > 0) {
+            // dense copy of what is left: either the input of the global-atomic levels, or the
+            // leftovers after D levels
+            uint64_t* dense = nullptr;
+            if (cur.nseg == 1 && cur.stride == 0) {
+                dense = const_cast<uint64_t*>(cur.base);
+            } else {
+                if ((st = ar_.alloc(&dense, cur.n, "dense keys")) != MPHF_OK) return st;
+                HIP_TRY(launch_gather(cur.base, cur.stride, cur.pre, cur.nseg, cur.n, dense, s_), "gather");
+            }
+            if (d < D) {
+                if ((st = atomic_levels(dense, cur.n, d, off)) != MPHF_OK) return st;
+            } else {
+                left_ = dense;
+                nleft_ = cur.n;
+                h_->total_bits = off;
+            }
+        } else if (h_->num_levels == d) {
+            h_->total_bits = std::max(h_->total_bits, off);
+        }
+        h_->total_words = h_->total_bits / 64;
+        tr_.mark("levels done");
+        if ((st = fallback_table()) != MPHF_OK) return st;
+        tr_.mark("fallback table", (long)nleft_);
+        if ((st = rank_table()) != MPHF_OK) return st;
+        tr_.mark("rank table");
+        if ((st = lookup_layout()) != MPHF_OK) return st;
+        tr_.mark("lookup layout");
+        if ((st = level_table()) != MPHF_OK) return st;
+        tr_.mark("level table");
+        h_->words = words_;
+        ar_.keep(words_);
+        if (coll_) {
+            h_->coll_all = coll_;
+            ar_.keep(coll_);
+        }
+        HIP_TRY(hipStreamSynchronize(s_), "final sync");
+        h_->peak_bytes = ar_.peak();
+        tr_.mark("done");
+        return MPHF_OK;
+    }
+
+  private:
+    mphf* h_;
+    mphf_opts o_;
+    hipStream_t s_;
+    Arena ar_;
+    Trace tr_;
+    double gamma_ = 0;
+    SeedTable seeds_{};
+    uint64_t* host_ = nullptr;
+    uint64_t* dev_ = nullptr;        // [0..63] weights, [64..127] survivor counts, [128] dup flag,
+                                     // [129] overflow flag, [130..132] tail summary
+    TailLevel* tail_rec_ = nullptr;
+    uint64_t* words_ = nullptr;
+    uint64_t* coll_ = nullptr;
+    uint64_t cap_words_ = 0;
+    uint64_t* left_ = nullptr;
+    uint64_t nleft_ = 0;
+    // partition temporaries: the device's cached workspace, or a private one
+    WsBufs priv_;
+    WsBufs* ws_ = &priv_;
+    bool cached_ = false;
+    std::unique_lock<std::mutex> lock_;
+    int ypar_ = 0;
+
+    void record(uint32_t d, uint64_t n, uint64_t m, uint64_t weight, uint64_t off) {
+        h_->level_n[d] = n;
+        h_->level_m[d] = m;
+        h_->level_weight[d] = weight;
+        h_->level_offset[d] = off;
+        h_->level_seed[d] = seeds_.s[d];
+        h_->num_levels = d + 1;
+        h_->total_bits = off + 64 * ((m + 63) / 64);
+    }
+
+    mphf_status ensure_words(uint64_t need) {
+        if (need <= cap_words_) return MPHF_OK;
+        mphf_status st;
+        const uint64_t ncap = cap_words_ ? need * 5 / 4 + 64 : need;
+        uint64_t* nw = nullptr;
+        if ((st = ar_.alloc(&nw, ncap, "A")) != MPHF_OK) return st;
+        if (words_) {   // (every word below total_bits is written by its level; no zeroing needed)
+            HIP_TRY(hipMemcpyAsync(nw, words_, cap_words_ * 8, hipMemcpyDeviceToDevice, s_), "grow A");
+        }
+        uint64_t* nc = nullptr;
+        if (o_.keep_collisions) {
+            if ((st = ar_.alloc(&nc, ncap, "C")) != MPHF_OK) return st;
+            HIP_TRY(launch_zero(nc, ncap, s_), "zero C");
+            if (coll_) HIP_TRY(hipMemcpyAsync(nc, coll_, cap_words_ * 8, hipMemcpyDeviceToDevice, s_), "grow C");
+        }
+        HIP_TRY(hipStreamSynchronize(s_), "grow sync");
+        ar_.release(words_);
+        ar_.release(coll_);
+        words_ = nw;
+        coll_ = nc;
+        cap_words_ = ncap;
+        return MPHF_OK;
+    }
+
+    template <typename T>
+    mphf_status ensure(T** buf, uint64_t* cap, uint64_t need, const char* what) {
+        if (need <= *cap) return MPHF_OK;
+        if (!cached_) {
+            ar_.release(*buf);
+            *buf = nullptr;
+            *cap = 0;
+            mphf_status st = ar_.alloc(buf, need, what);
+            if (st == MPHF_OK) *cap = need;
+            return st;
+        }
+        // cached workspace: plain device allocations that outlive the build
+        HIP_TRY(hipStreamSynchronize(s_), "workspace sync");
+        if (*buf) (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+        const uint64_t grown = need + need / 8;
+        hipError_t e = hipMalloc((void**)buf, grown * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            *buf = nullptr;
+            return hip_fail(e, what);
+        }
+        *cap = grown;
+        return MPHF_OK;
+    }
+
+    void acquire_workspace() {
+        if (o_.mem_budget) return;   // a budgeted build counts its own temporaries
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+        std::unique_lock<std::mutex> lk(g_ws[dev].mu, std::try_to_lock);
+        if (!lk.owns_lock()) return;
+        lock_ = std::move(lk);
+        ws_ = &g_ws[dev].b;
+        cached_ = true;
+    }
+
+    mphf_status read_back(const void* dev, uint64_t bytes) {
+        HIP_TRY(hipMemcpyAsync(host_, dev, bytes, hipMemcpyDeviceToHost, s_), "read back");
+        HIP_TRY(hipStreamSynchronize(s_), "level sync");
+        return MPHF_OK;
+    }
+
+    // Exclusive prefix of `n` u32 counts (the array has a trailing 0 at index n) into pre[0..n].
+    mphf_status prefix(const uint32_t* cnt, uint64_t n, uint64_t* pre) {
+        mphf_status st;
+        if ((st = ensure(&ws_->tiles, &ws_->capTiles, scan_tmp_tiles(n + 1), "scan tiles")) != MPHF_OK) return st;
+        HIP_TRY(launch_exclusive_scan(cnt, pre, n + 1, ws_->tiles, s_), "prefix");
+        return MPHF_OK;
+    }
+
+    // One level by radix partition + per-bucket LDS pass.  *ok = false means a region or a
+    // bucket overflowed its capacity (only for adversarial key sets): nothing of the level is
+    // kept and the caller redoes it with global atomics.
+    mphf_status partitioned_level(const KeySet& in, uint32_t d, uint64_t off, const BucketGeometry& g,
+                                  KeySet* out, bool* ok) {
+        mphf_status st;
+        *ok = false;
+        const uint64_t n = in.n;
+        const uint64_t m = level_size(gamma_, n);
+        const uint64_t wd = (m + 63) / 64;
+        if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
+        const LevelHash L = make_level_hash(seeds_.s[d], m, off);
+        const uint32_t pb = g.pbits;
+        const uint64_t P = 1ull << pb;
+        const uint64_t B = (m + P - 1) / P;
+        const uint32_t lb = ceil_log2(B);
+        if (lb > 18) return MPHF_OK;   // beyond two passes: use the atomic levels
+        unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
+        HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
+        uint64_t xcap;
+        uint32_t S;
+        if (B <= 1024) {
+            // one pass: every workgroup scatters its share straight into the buckets
+            uint64_t W = (n + 8191) / 8192;
+            W = std::max<uint64_t>(1, std::min<uint64_t>(W, 256));
+            const uint64_t cap = region_cap((double)n / W * (double)P / (double)m);
+            if ((st = ensure(&ws_->X, &ws_->capX, B * W * cap, "partition X")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->Xlp, &ws_->capXlp, B * W * cap, "partition X positions")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
+            HIP_TRY(launch_partition(B <= 256 ? 8 : 10, true, in.base, in.stride, in.pre, 1, in.nseg,
+                                     (uint32_t)W, L, pb, 0, false, 0, B, ws_->X, ws_->Xlp, cap, (uint32_t)W,
+                                     ws_->cntX, ovf, s_),
+                    "partition");
+            xcap = cap;
+            S = (uint32_t)W;
+        } else {
+            // two passes: coarse bins of 2^fb buckets, then the buckets of each coarse bin
+            const uint32_t fb = lb - 8;
+            const uint64_t C = (B + (1ull << fb) - 1) >> fb;
+            uint64_t W = (n + 65535) / 65536;
+            W = std::max<uint64_t>(1, std::min<uint64_t>(W, 768));
+            const double pc = (double)(P << fb) / (double)m;
+            const uint64_t cap1 = region_cap((double)n / W * pc);
+            if ((st = ensure(&ws_->Z, &ws_->capZ, C * W * cap1, "partition Z")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->cntZ, &ws_->capCntZ, C * W + 1, "counts Z")) != MPHF_OK) return st;
+            HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
+                                     fb, false, 0, C, ws_->Z, nullptr, cap1, (uint32_t)W, ws_->cntZ, ovf, s_),
+                    "partition 1");
+            HIP_TRY(launch_zero32(ws_->cntZ + C * W, 1, s_), "zero count tail");
+            if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
+            if ((st = prefix(ws_->cntZ, C * W, ws_->preZ)) != MPHF_OK) return st;
+            uint64_t K = 768 / C;
+            K = std::max<uint64_t>(1, std::min<uint64_t>(K, 64));
+            const double bin_keys = (double)n * pc;
+            const double e2 = bin_keys / (double)K / (double)(1ull << fb) * (1.0 + 8.0 / std::sqrt(bin_keys));
+            const uint64_t cap2 = region_cap(e2);
+            if ((st = ensure(&ws_->X, &ws_->capX, B * K * cap2, "partition X")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->Xlp, &ws_->capXlp, B * K * cap2, "partition X positions")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
+            HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, ws_->Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
+                                     (uint32_t)K, L, pb, 0, true, fb, B, ws_->X, ws_->Xlp, cap2, (uint32_t)K,
+                                     ws_->cntX, ovf, s_),
+                    "partition 2");
+            xcap = cap2;
+            S = (uint32_t)K;
+        }
+        // buckets: fill, finalize and filter in LDS
+        const int yp = ypar_;
+        ypar_ ^= 1;
+        if ((st = ensure(&ws_->Y[yp], &ws_->capY[yp], B * g.kcap, "survivors")) != MPHF_OK) return st;
+        if ((st = ensure(&ws_->surv[yp], &ws_->capSurv[yp], B + 1, "survivor counts")) != MPHF_OK) return st;
+        if ((st = ensure(&ws_->preY[yp], &ws_->capPreY[yp], B + 1, "survivor prefix")) != MPHF_OK) return st;
+        uint64_t* C_level = coll_ ? coll_ + off / 64 : nullptr;
+        HIP_TRY(launch_bucket(ws_->X, ws_->Xlp, xcap, ws_->cntX, S, B, pb, g.kcap, words_ + off / 64, C_level, wd,
+                              ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_),
+                "bucket");
+        HIP_TRY(launch_zero32(ws_->surv[yp] + B, 1, s_), "zero count tail");
+        if ((st = prefix(ws_->surv[yp], B, ws_->preY[yp])) != MPHF_OK) return st;
+        HIP_TRY(hipMemcpyAsync(dev_ + 130, ws_->preY[yp] + B, 8, hipMemcpyDeviceToDevice, s_), "copy total");
+        if ((st = read_back(dev_ + 129, 16)) != MPHF_OK) return st;
+        if (host_[0]) return MPHF_OK;   // overflow: redo with atomics
+        const uint64_t nnext = host_[1];
+        if (nnext > n) return fail(MPHF_E_DEVICE, "survivors exceed the level's keys");
+        record(d, n, m, n - nnext, off);
+        out->base = ws_->Y[yp];
+        out->stride = g.kcap;
+        out->pre = ws_->preY[yp];
+        out->nseg = (uint32_t)B;
+        out->n = nnext;
+        *ok = true;
+        return MPHF_OK;
+    }
+
+    // Every remaining level in one workgroup (the set fits in its LDS).
+    mphf_status tail(const KeySet& in, uint32_t d0, uint64_t off, uint32_t tk) {
+        mphf_status st;
+        const uint32_t D = o_.max_levels;
+        const uint64_t per = (uint64_t)std::ceil(gamma_ * tk) / 64 + 2;
+        if ((st = ensure_words(off / 64 + (uint64_t)(D - d0) * per + 1)) != MPHF_OK) return st;
+        uint64_t* left = nullptr;
+        if ((st = ar_.alloc(&left, in.n, "leftovers")) != MPHF_OK) return st;
+        HIP_TRY(launch_tail(in.base, in.stride, in.pre, in.nseg, tk, gamma_, seeds_, d0, D, off, words_,
+                            coll_, tail_rec_, left, (TailSummary*)(dev_ + 130), s_),
+                "tail");
+        if ((st = read_back(dev_ + 130, 24)) != MPHF_OK) return st;
+        const uint64_t end = host_[0], nleft = host_[1], bit_end = host_[2];
+        std::vector<TailLevel> rec(MPHF_MAX_LEVELS);
+        HIP_TRY(hipMemcpy(rec.data(), tail_rec_, sizeof(TailLevel) * MPHF_MAX_LEVELS, hipMemcpyDeviceToHost),
+                "read tail records");
+        for (uint64_t d = d0; d < end; ++d) record((uint32_t)d, rec[d].n, rec[d].m, rec[d].weight, rec[d].offset);
+        h_->total_bits = bit_end;
+        if (nleft) {
+            left_ = left;
+            nleft_ = nleft;
+        }
+        return MPHF_OK;
+    }
+
+    // Levels d.. built with global atomics on the interleaved A/C words (used when a level's
+    // partition overflows, or on request).  F is dense.
+    mphf_status atomic_levels(const uint64_t* F, uint64_t n, uint32_t d0, uint64_t off) {
+        mphf_status st;
+        const uint32_t D = o_.max_levels;
+        const uint64_t m0 = level_size(gamma_, n);
+        const uint64_t w0 = (m0 + 63) / 64;
+        uint64_t* W = nullptr;
+        if ((st = ar_.alloc(&W, 2 * w0 + 2, "W")) != MPHF_OK) return st;
+        unsigned long long* counters = (unsigned long long*)dev_;
+        HIP_TRY(launch_zero(dev_, 128, s_), "zero counters");
+        uint64_t* Fbuf[2] = {nullptr, nullptr};
+        const uint64_t* Fin = F;
+        uint64_t nd = n;
+        LevelHash L = make_level_hash(seeds_.s[d0], m0, off);
+        if ((st = ensure_words(off / 64 + w0 + 1)) != MPHF_OK) return st;
+        HIP_TRY(launch_zero(W, 2 * w0, s_), "zero W");
+        HIP_TRY(launch_fill(Fin, nd, W, L, s_), "fill");
+        for (uint32_t d = d0; nd > 0; ++d) {
+            const uint64_t m = L.m;
+            const uint64_t wd = (m + 63) / 64;
+            HIP_TRY(launch_finalize(W, wd, words_ + off / 64, coll_ ? coll_ + off / 64 : nullptr,
+                                    counters + d, s_),
+                    "finalize");
+            if ((st = read_back(counters + d, 8)) != MPHF_OK) return st;
+            const uint64_t weight = host_[0];
+            if (weight > nd) return fail(MPHF_E_DEVICE, "level weight exceeds the level's keys");
+            record(d, nd, m, weight, off);
+            const uint64_t nnext = nd - weight;
+            const uint64_t off_next = off + 64 * wd;
+            off = off_next;
+            if (nnext == 0) break;
+            const bool last = d + 1 == D;
+            LevelHash Ln{};
+            if (!last) {
+                const uint64_t mn = level_size(gamma_, nnext);
+                const uint64_t wn = (mn + 63) / 64;
+                Ln = make_level_hash(seeds_.s[d + 1], mn, off_next);
+                if ((st = ensure_words(off_next / 64 + wn + 1)) != MPHF_OK) return st;
+                HIP_TRY(launch_zero(W, 2 * wn, s_), "zero W");
+            }
+            uint64_t*& Fo = Fbuf[(d - d0) & 1];
+            if (!Fo && (st = ar_.alloc(&Fo, nnext, "F")) != MPHF_OK) return st;
+            const LevelHash Ld = make_level_hash(seeds_.s[d], m, h_->level_offset[d]);
+            HIP_TRY(launch_filter_fill(Fin, nd, words_, Ld, Fo, nnext, counters + 64 + d, W, Ln, !last, s_),
+                    "filter");
+            Fin = Fo;
+            nd = nnext;
+            L = Ln;
+            if (last) {
+                left_ = Fo;
+                nleft_ = nnext;
+                break;
+            }
+        }
+        return MPHF_OK;
+    }
+
+    // Fallback table (Section 3, "Termination"): leftovers sorted ascending get N-|L|+1 .. N.
+    mphf_status fallback_table() {
+        if (!nleft_) return MPHF_OK;
+        mphf_status st;
+        uint64_t *fb = nullptr, *tmp = nullptr, *roffs = nullptr, *rtiles = nullptr;
+        uint32_t* rcounts = nullptr;
+        const uint64_t nc = radix_tmp_counts(nleft_);
+        if ((st = ar_.alloc(&fb, nleft_, "fallback keys")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&tmp, nleft_, "sort scratch")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&rcounts, nc, "sort counts")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&roffs, nc, "sort offsets")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&rtiles, scan_tmp_tiles(nc), "sort tiles")) != MPHF_OK) return st;
+        HIP_TRY(hipMemcpyAsync(fb, left_, nleft_ * 8, hipMemcpyDeviceToDevice, s_), "copy leftovers");
+        HIP_TRY(radix_sort_u64(fb, tmp, nleft_, rcounts, roffs, rtiles, s_), "sort");
+        HIP_TRY(launch_zero(dev_ + 128, 1, s_), "zero flag");
+        HIP_TRY(launch_find_duplicates(fb, nleft_, (unsigned long long*)(dev_ + 128), s_), "duplicates");
+        if ((st = read_back(dev_ + 128, 8)) != MPHF_OK) return st;
+        if (host_[0]) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in the input");
+        h_->fb_keys = fb;
+        h_->nfb = nleft_;
+        ar_.keep(fb);
+        return MPHF_OK;
+    }
+
+    // Rank table (Section 3.1).
+    mphf_status rank_table() {
+        h_->nrank = (h_->total_bits + o_.rank_sample - 1) / o_.rank_sample;
+        if (!h_->nrank) return MPHF_OK;
+        mphf_status st;
+        uint32_t* rc = nullptr;
+        uint64_t* rt = nullptr;
+        if ((st = ar_.alloc(&h_->rank, h_->nrank, "rank")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&rc, h_->nrank, "rank counts")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&rt, scan_tmp_tiles(h_->nrank), "rank tiles")) != MPHF_OK) return st;
+        HIP_TRY(launch_rank(words_, h_->total_words, o_.rank_sample, h_->rank, h_->nrank, rc, rt, s_),
+                "rank");
+        ar_.keep(h_->rank);
+        return MPHF_OK;
+    }
+
+    // The lookup's copy of A in 64-byte sectors with embedded rank counters.
+    mphf_status lookup_layout() {
+        h_->nsec = sector_count(h_->total_bits);
+        if (!h_->nsec) return MPHF_OK;
+        mphf_status st;
+        uint32_t* cnt = nullptr;
+        uint64_t *pre = nullptr, *tiles = nullptr;
+        if ((st = ar_.alloc(&h_->sec, h_->nsec * 16, "lookup sectors")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&h_->super, super_count(h_->nsec), "lookup superblocks")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&cnt, h_->nsec, "sector counts")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&pre, h_->nsec, "sector prefix")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&tiles, scan_tmp_tiles(h_->nsec), "sector tiles")) != MPHF_OK) return st;
+        HIP_TRY(launch_sectors(words_, h_->total_bits, h_->sec, h_->super, cnt, pre, tiles, s_), "sectors");
+        ar_.keep(h_->sec);
+        ar_.keep(h_->super);
+        return MPHF_OK;
+    }
+
+    // Level table for the lookup kernel.
+    mphf_status level_table() {
+        if (!h_->num_levels) return MPHF_OK;
+        mphf_status st;
+        DevLevel hl[MPHF_MAX_LEVELS];
+        for (uint32_t d = 0; d < h_->num_levels; ++d) {
+            const LevelHash x = make_level_hash(h_->level_seed[d], h_->level_m[d], h_->level_offset[d]);
+            hl[d] = DevLevel{x.seed, x.m, x.magic, x.bit_off, x.sh1, x.sh2};
+        }
+        if ((st = ar_.alloc(&h_->dlev, h_->num_levels, "level table")) != MPHF_OK) return st;
+        HIP_TRY(hipMemcpyAsync(h_->dlev, hl, sizeof(DevLevel) * h_->num_levels, hipMemcpyHostToDevice, s_),
+                "copy level table");
+        HIP_TRY(hipStreamSynchronize(s_), "level table sync");
+        ar_.keep(h_->dlev);
+        return MPHF_OK;
+    }
+};
 
 mphf_status build_impl(const uint64_t* keys, uint64_t n, double gamma, uint64_t seed,
                        const mphf_opts& opts, hipStream_t s, mphf** out) {
@@ -159,182 +728,22 @@ mphf_status build_impl(const uint64_t* keys, uint64_t n, double gamma, uint64_t 
     if (gamma * (double)n >= 9.2e18) return fail(MPHF_E_INVALID, "gamma * n too large");
     mphf_status st = check_opts(opts);
     if (st != MPHF_OK) return st;
-
     mphf* h = new mphf();
-    struct Guard {
-        mphf* h;
-        ~Guard() { free_handle(h); }
-    } guard{h};
     HIP_TRY(hipGetDevice(&h->device), "hipGetDevice");
+    configure_pool(h->device);
     h->n = n;
     h->gamma = gamma;
     h->seed = seed;
     h->opts = opts;
     h->rank_shift = opts.rank_sample == 1024 ? 10 : 9;
-    uint64_t seeds[MPHF_MAX_LEVELS];
-    level_seeds(seed, opts.max_levels, seeds);
-
-    Arena ar(opts.mem_budget);
-    const uint64_t m0 = level_size(gamma, n);
-    const uint64_t w0 = (m0 + 63) / 64;
-
-    // The concatenated A: reserve the expected gamma e^{1/gamma} N bits (Section 2.3) plus slack;
-    // grown by copying in the rare case the levels need more.
-    uint64_t cap_words = 0;
-    uint64_t* words = nullptr;
     {
-        const double expect = gamma * std::exp(1.0 / gamma) * (double)n;
-        cap_words = (uint64_t)(expect * 1.02 / 64.0) + 2 * (uint64_t)opts.max_levels + 64;
-        if (cap_words < w0 + 1) cap_words = w0 + 1;
-        if ((st = ar.alloc(&words, cap_words, "A")) != MPHF_OK) return st;
+        Builder b(h, opts, s);
+        st = b.run(keys, n, gamma);
     }
-    uint64_t* W = nullptr;                 // working A/C pairs of the level being filled
-    unsigned long long* counters = nullptr;  // [0..63] weights, [64..127] survivor counts, [128] dup flag
-    if ((st = ar.alloc(&W, 2 * w0 + 2, "W")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&counters, 160, "counters")) != MPHF_OK) return st;
-    HIP_TRY(launch_zero((uint64_t*)counters, 160, s), "zero counters");
-
-    uint64_t* host_cnt = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&host_cnt, 64, hipHostMallocDefault), "hipHostMalloc");
-    struct HostGuard {
-        uint64_t* p;
-        ~HostGuard() { (void)hipHostFree(p); }
-    } hg{host_cnt};
-
-    uint64_t* Fbuf[2] = {nullptr, nullptr};
-    const uint64_t* Fin = keys;
-    uint64_t nd = n;
-    uint64_t off_bits = 0;
-    uint64_t* leftovers = nullptr;
-    uint64_t nleft = 0;
-
-    LevelHash L{};
-    if (n) {
-        L = make_level_hash(seeds[0], m0, 0);
-        HIP_TRY(launch_zero(W, 2 * w0, s), "zero W");
-        HIP_TRY(launch_fill(keys, n, W, L, s), "fill");
+    if (st != MPHF_OK) {
+        free_handle(h);
+        return st;
     }
-    for (uint32_t d = 0; nd > 0; ++d) {
-        const uint64_t m = L.m;
-        const uint64_t wd = (m + 63) / 64;
-        uint64_t* C = nullptr;
-        if (opts.keep_collisions) {
-            if ((st = ar.alloc(&C, wd, "C")) != MPHF_OK) return st;
-            h->coll.push_back(C);
-        }
-        HIP_TRY(launch_finalize(W, wd, words + off_bits / 64, C, counters + d, s), "finalize");
-        HIP_TRY(hipMemcpyAsync(host_cnt, counters + d, 8, hipMemcpyDeviceToHost, s), "copy weight");
-        HIP_TRY(hipStreamSynchronize(s), "level sync");
-        const uint64_t weight = host_cnt[0];
-        if (weight > nd) return fail(MPHF_E_DEVICE, "level weight exceeds the level's keys");
-        h->level_n[d] = nd;
-        h->level_m[d] = m;
-        h->level_weight[d] = weight;
-        h->level_offset[d] = off_bits;
-        h->level_seed[d] = seeds[d];
-        h->num_levels = d + 1;
-        const uint64_t nnext = nd - weight;
-        const uint64_t off_next = off_bits + 64 * wd;
-        if (nnext == 0) {
-            off_bits = off_next;
-            break;
-        }
-        const bool last = d + 1 == opts.max_levels;
-        LevelHash Ln{};
-        if (!last) {
-            const uint64_t mn = level_size(gamma, nnext);
-            const uint64_t wn = (mn + 63) / 64;
-            Ln = make_level_hash(seeds[d + 1], mn, off_next);
-            if (off_next / 64 + wn > cap_words) {   // grow A
-                uint64_t ncap = (off_next / 64 + wn) * 5 / 4 + 64;
-                uint64_t* nw = nullptr;
-                if ((st = ar.alloc(&nw, ncap, "A (grown)")) != MPHF_OK) return st;
-                HIP_TRY(hipMemcpyAsync(nw, words, off_next / 8, hipMemcpyDeviceToDevice, s), "grow A");
-                HIP_TRY(hipStreamSynchronize(s), "grow sync");
-                ar.release(words);
-                words = nw;
-                cap_words = ncap;
-            }
-            HIP_TRY(launch_zero(W, 2 * wn, s), "zero W");
-        }
-        // F_{d+1}: ping-pong buffers, the one for odd levels sized by n_1 and the other by n_2
-        // (sizes only shrink from level to level).
-        uint64_t*& Fo = Fbuf[d & 1];
-        if (!Fo && (st = ar.alloc(&Fo, nnext, "F")) != MPHF_OK) return st;
-        {
-            const LevelHash Ld = make_level_hash(seeds[d], m, off_bits);
-            HIP_TRY(launch_filter_fill(Fin, nd, words, Ld, Fo, nnext, counters + 64 + d, W, Ln,
-                                       !last, s),
-                    "filter");
-        }
-        off_bits = off_next;
-        Fin = Fo;
-        nd = nnext;
-        L = Ln;
-        if (last) {
-            leftovers = Fo;
-            nleft = nnext;
-            break;
-        }
-    }
-    h->total_bits = off_bits;
-    h->total_words = off_bits / 64;
-
-    // Fallback table (Section 3, "Termination"): leftovers sorted ascending get N-|L|+1 .. N.
-    if (nleft) {
-        uint64_t* fb = nullptr;
-        uint64_t* tmp = nullptr;
-        uint32_t* rcounts = nullptr;
-        uint64_t* roffs = nullptr;
-        uint64_t* rtiles = nullptr;
-        const uint64_t nc = radix_tmp_counts(nleft);
-        if ((st = ar.alloc(&fb, nleft, "fallback keys")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&tmp, nleft, "sort scratch")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&rcounts, nc, "sort counts")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&roffs, nc, "sort offsets")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&rtiles, scan_tmp_tiles(nc), "sort tiles")) != MPHF_OK) return st;
-        HIP_TRY(hipMemcpyAsync(fb, leftovers, nleft * 8, hipMemcpyDeviceToDevice, s), "copy leftovers");
-        HIP_TRY(radix_sort_u64(fb, tmp, nleft, rcounts, roffs, rtiles, s), "sort");
-        HIP_TRY(launch_find_duplicates(fb, nleft, counters + 128, s), "duplicates");
-        HIP_TRY(hipMemcpyAsync(host_cnt, counters + 128, 8, hipMemcpyDeviceToHost, s), "copy flag");
-        HIP_TRY(hipStreamSynchronize(s), "fallback sync");
-        if (host_cnt[0]) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in the input");
-        h->fb_keys = fb;
-        h->nfb = nleft;
-        ar.keep(fb);
-    }
-
-    // Rank table (Section 3.1).
-    h->nrank = (h->total_bits + opts.rank_sample - 1) / opts.rank_sample;
-    if (h->nrank) {
-        uint32_t* rc = nullptr;
-        uint64_t* rt = nullptr;
-        if ((st = ar.alloc(&h->rank, h->nrank, "rank")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&rc, h->nrank, "rank counts")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&rt, scan_tmp_tiles(h->nrank), "rank tiles")) != MPHF_OK) return st;
-        HIP_TRY(launch_rank(words, h->total_words, opts.rank_sample, h->rank, h->nrank, rc, rt, s),
-                "rank");
-        ar.keep(h->rank);
-    }
-
-    // Level table for the lookup kernel.
-    if (h->num_levels) {
-        DevLevel hl[MPHF_MAX_LEVELS];
-        for (uint32_t d = 0; d < h->num_levels; ++d) {
-            const LevelHash x = make_level_hash(h->level_seed[d], h->level_m[d], h->level_offset[d]);
-            hl[d] = DevLevel{x.seed, x.m, x.magic, x.bit_off, x.sh1, x.sh2};
-        }
-        if ((st = ar.alloc(&h->dlev, h->num_levels, "level table")) != MPHF_OK) return st;
-        HIP_TRY(hipMemcpyAsync(h->dlev, hl, sizeof(DevLevel) * h->num_levels, hipMemcpyHostToDevice, s),
-                "copy level table");
-        ar.keep(h->dlev);
-    }
-    h->words = words;
-    ar.keep(words);
-    for (uint64_t* c : h->coll) ar.keep(c);
-    HIP_TRY(hipStreamSynchronize(s), "final sync");
-    h->peak_bytes = ar.peak();
-    guard.h = nullptr;
     *out = h;
     return MPHF_OK;
 }
@@ -375,8 +784,8 @@ mphf_status mphf_lookup_ex(const mphf_t* h, const uint64_t* keys, uint64_t n, ui
     if (!is_device_ptr(keys) || !is_device_ptr(out))
         return fail(MPHF_E_INVALID, "keys and out must be device memory");
     if (keys == out) return fail(MPHF_E_INVALID, "out may not alias keys");
-    HIP_TRY(launch_lookup(keys, n, out, h->dlev, h->num_levels, h->words, h->rank, h->rank_shift,
-                          h->fb_keys, h->nfb, h->n, (hipStream_t)stream),
+    HIP_TRY(launch_lookup(keys, n, out, h->dlev, h->num_levels, h->sec, h->super, h->fb_keys, h->nfb,
+                          h->n, (hipStream_t)stream),
             "lookup");
     return MPHF_OK;
 }
@@ -410,6 +819,7 @@ mphf_status mphf_stats(const mphf_t* h, mphf_stats_t* st) {
     st->total_bits = h->total_bits;
     st->rank_entries = h->nrank;
     st->structure_bytes = h->total_words * 8 + h->nrank * 8 + h->nfb * 8;
+    st->lookup_bytes = h->nsec * 64 + (h->nsec ? super_count(h->nsec) * 8 : 0) + h->nfb * 8;
     st->bits_per_key = h->n ? (double)(h->total_bits + 64 * h->nrank + 128 * h->nfb) / (double)h->n : 0.0;
     st->peak_bytes = h->peak_bytes;
     return MPHF_OK;
@@ -420,6 +830,7 @@ mphf_status mphf_view(const mphf_t* h, mphf_view_t* v) {
     v->words = h->words;
     v->rank = h->rank;
     v->fallback_keys = h->fb_keys;
+    v->collisions = h->coll_all;
     v->total_words = h->total_words;
     v->rank_entries = h->nrank;
     v->n_fallback = h->nfb;
@@ -442,10 +853,11 @@ mphf_status mphf_export(const mphf_t* h, uint64_t* words, uint64_t nwords, uint6
 mphf_status mphf_export_collisions(const mphf_t* h, uint32_t level, uint64_t* out, uint64_t nwords) {
     if (!h || !out) return fail(MPHF_E_INVALID, "NULL argument");
     if (level >= h->num_levels) return fail(MPHF_E_INVALID, "no such level");
-    if (level >= h->coll.size()) return fail(MPHF_E_INVALID, "collisions were not kept (keep_collisions)");
+    if (!h->coll_all) return fail(MPHF_E_INVALID, "collisions were not kept (keep_collisions)");
     const uint64_t need = (h->level_m[level] + 63) / 64;
     if (nwords < need) return fail(MPHF_E_INVALID, "output too small");
-    HIP_TRY(hipMemcpy(out, h->coll[level], need * 8, hipMemcpyDeviceToHost), "copy C");
+    HIP_TRY(hipMemcpy(out, h->coll_all + h->level_offset[level] / 64, need * 8, hipMemcpyDeviceToHost),
+            "copy C");
     return MPHF_OK;
 }
 
@@ -457,6 +869,20 @@ mphf_status mphf_positions(const uint64_t* keys, uint64_t n, uint64_t level_seed
         return fail(MPHF_E_INVALID, "keys and out must be device memory");
     HIP_TRY(launch_positions(keys, n, make_level_hash(level_seed, m, 0), out, (hipStream_t)stream),
             "positions");
+    return MPHF_OK;
+}
+
+mphf_status mphf_trim(void) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (int d = 0; d < 64; ++d) {
+        std::lock_guard<std::mutex> g(g_ws[d].mu);
+        if (!g_ws[d].b.host && !g_ws[d].b.Z && !g_ws[d].b.X && !g_ws[d].b.Y[0] && !g_ws[d].b.tiles) continue;
+        if (hipSetDevice(d) != hipSuccess) continue;
+        (void)hipDeviceSynchronize();
+        g_ws[d].release();
+    }
+    (void)hipSetDevice(cur);
     return MPHF_OK;
 }
 

@@ -20,8 +20,48 @@ struct DevLevel {
 
 LevelHash make_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off);
 
+struct SeedTable {
+    uint64_t s[64];
+};
+
+// What the one-workgroup kernel for the last levels reports per level and at the end.
+struct TailLevel {
+    uint64_t n, m, weight, offset;
+};
+struct TailSummary {
+    uint64_t end_level;   // first level not built
+    uint64_t n_left;      // keys left for the fallback table
+    uint64_t bit_end;     // bit offset after the last level built
+};
+
+// Bucket size of the partitioned levels: 2^pbits positions and room for kcap keys in LDS.
+struct BucketGeometry {
+    uint32_t pbits;
+    uint32_t kcap;
+};
+BucketGeometry bucket_geometry(double gamma);
+uint32_t tail_capacity(double gamma);
+
+hipError_t launch_partition(int dbits, bool lpos, const uint64_t* in, uint64_t in_stride,
+                            const uint64_t* pre, uint32_t groups, uint32_t SG, uint32_t K,
+                            const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
+                            uint32_t group_shift, uint64_t nbins, uint64_t* out, uint16_t* out_lp,
+                            uint64_t out_cap, uint32_t S_out, uint32_t* out_cnt,
+                            unsigned long long* overflow, hipStream_t s);
+hipError_t launch_bucket(const uint64_t* in, const uint16_t* in_lp, uint64_t in_cap, const uint32_t* cnt,
+                         uint32_t S, uint64_t nbuckets, uint32_t pbits, uint32_t kcap, uint64_t* A,
+                         uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
+                         uint32_t* surv, unsigned long long* overflow, hipStream_t s);
+hipError_t launch_gather(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
+                         uint64_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_tail(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
+                       uint32_t kcap, double gamma, const SeedTable& seeds, uint32_t d0, uint32_t D,
+                       uint64_t bit_off, uint64_t* A, uint64_t* Cout, TailLevel* rec, uint64_t* left,
+                       TailSummary* sum, hipStream_t s);
+
 // ---- launchers (all asynchronous on `s`) ----
 hipError_t launch_zero(uint64_t* p, uint64_t nwords, hipStream_t s);
+hipError_t launch_zero32(uint32_t* p, uint64_t n, hipStream_t s);
 hipError_t launch_fill(const uint64_t* keys, uint64_t n, uint64_t* W, const LevelHash& L,
                        hipStream_t s);
 hipError_t launch_finalize(const uint64_t* W, uint64_t nwords, uint64_t* A, uint64_t* C,
@@ -42,10 +82,13 @@ hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t n, uint32_t* counts
                           uint64_t* offsets, uint64_t* tmp_tiles, hipStream_t s);
 hipError_t launch_find_duplicates(const uint64_t* sorted, uint64_t n, unsigned long long* flag,
                                   hipStream_t s);
+uint64_t sector_count(uint64_t total_bits);
+uint64_t super_count(uint64_t nsec);
+hipError_t launch_sectors(const uint64_t* words, uint64_t total_bits, uint32_t* sec, uint64_t* super,
+                          uint32_t* tmp_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s);
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
-                         uint32_t nlev, const uint64_t* words, const uint64_t* rank,
-                         uint32_t rank_shift, const uint64_t* fb_keys, uint64_t nfb, uint64_t N,
-                         hipStream_t s);
+                         uint32_t nlev, const uint32_t* sec, const uint64_t* super,
+                         const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);
 hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
                             hipStream_t s);
 

@@ -40,6 +40,11 @@ __global__ void k_zero(uint64_t* __restrict__ p, uint64_t n) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
 }
 
+__global__ void k_zero32(uint32_t* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
 __global__ void k_fill(const uint64_t* __restrict__ keys, uint64_t n, unsigned long long* W,
                        LevelHash L) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -262,13 +267,58 @@ __global__ void k_find_duplicates(const uint64_t* __restrict__ s, uint64_t n,
         if (s[i] == s[i + 1]) atomicOr(flag, 1ull);
 }
 
+// ---------------------------------------------------------------- lookup layout
+//
+// The lookup reads A through a copy laid out in 64-byte sectors.  A random read on gfx950 moves
+// one 128-byte line from HBM whatever its width, and the L1/L2 request rate caps how many 16-byte
+// pieces a lane may load per probe, so a probe should touch one small aligned unit that holds both
+// the probed bit and what its rank needs: u32 word 0 of sector s holds the ones of A before bit
+// 480*s, counted from the start of its superblock of 2^21 sectors; u32 words 1..15 hold bits
+// [480*s, 480*s + 480) of A.  super[s >> 21] holds the ones before the superblock.  The probe of a
+// level and, when its bit is set, the rank of that bit (Section 3.1's counters, here one 32-bit
+// counter per 480 positions plus the superblocks) come from one sector: four 16-byte loads.
+constexpr uint64_t SEC_BITS = 480;
+constexpr uint32_t SEC_WORDS = 16;
+constexpr uint32_t SUPER_SHIFT = 21;
+
+__global__ void k_sector_counts(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec,
+                                uint32_t* __restrict__ counts) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nsec; j += stride) {
+        uint32_t c = 0;
+        for (uint64_t w = 15 * j; w < 15 * j + 15 && w < nwords32; ++w) c += __popc(A32[w]);
+        counts[j] = c;
+    }
+}
+
+// One thread per u32 word of the sector layout.
+__global__ void k_sector_write(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec,
+                               const uint64_t* __restrict__ pre, uint32_t* __restrict__ sec,
+                               uint64_t* __restrict__ super) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t total = nsec * SEC_WORDS;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const uint64_t j = t / SEC_WORDS;
+        const uint32_t w = (uint32_t)(t % SEC_WORDS);
+        uint32_t v;
+        if (w == 0) {
+            const uint64_t sj = j & ~((1ull << SUPER_SHIFT) - 1);
+            v = (uint32_t)(pre[j] - pre[sj]);
+            if (j == sj) super[j >> SUPER_SHIFT] = pre[j];
+        } else {
+            const uint64_t src = 15 * j + (w - 1);
+            v = src < nwords32 ? A32[src] : 0u;
+        }
+        sec[t] = v;
+    }
+}
+
 // ---------------------------------------------------------------- lookup (Algorithm 3)
 
 __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* __restrict__ out,
                          const DevLevel* __restrict__ lev, uint32_t nlev,
-                         const uint64_t* __restrict__ words, const uint64_t* __restrict__ rank,
-                         uint32_t rank_shift, const uint64_t* __restrict__ fbk, uint64_t nfb,
-                         uint64_t N) {
+                         const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
+                         const uint64_t* __restrict__ fbk, uint64_t nfb, uint64_t N) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t x = q[i];
@@ -277,16 +327,29 @@ __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* _
         for (uint32_t d = 0; d < nlev; ++d) {
             const DevLevel L = lev[d];
             const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
-            const uint64_t wi = g >> 6;
-            const uint64_t w = words[wi];
-            if ((w >> (g & 63)) & 1ull) {
-                // ones before g = counter of its rank block + whole words of the block before wi
-                // + the bits of wi below g
-                const uint64_t b = g >> rank_shift;
-                uint64_t r = rank[b];
-                for (uint64_t k = (b << rank_shift) >> 6; k < wi; ++k) r += __popcll(words[k]);
-                r += __popcll(w & ((1ull << (g & 63)) - 1));
-                label = r + 1;
+            const uint64_t j = g / SEC_BITS;
+            const uint32_t r = (uint32_t)(g - j * SEC_BITS);
+            const uint32_t t = 1 + (r >> 5), b = r & 31u;   // the bit's u32 word in the sector
+            const uint4* s4 = (const uint4*)(sec + j * SEC_WORDS);
+            uint4 v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = s4[c];
+            const uint32_t e[16] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
+                                    v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
+            uint32_t w = 0;
+#pragma unroll
+            for (uint32_t k = 1; k < SEC_WORDS; ++k)
+                if (k == t) w = e[k];
+            if ((w >> b) & 1u) {
+                // ones before g = superblock + sector counter + whole words before t + bits of t below g
+                uint64_t rank = super[j >> SUPER_SHIFT] + e[0];
+                const uint32_t mask = (1u << b) - 1u;
+#pragma unroll
+                for (uint32_t k = 1; k < SEC_WORDS; ++k) {
+                    if (k < t) rank += __popc(e[k]);
+                    else if (k == t) rank += __popc(e[k] & mask);
+                }
+                label = rank + 1;
                 found = true;
                 break;
             }
@@ -334,6 +397,12 @@ LevelHash make_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
 hipError_t launch_zero(uint64_t* p, uint64_t nwords, hipStream_t s) {
     if (!nwords) return hipSuccess;
     hipLaunchKernelGGL(k_zero, dim3(grid_for(nwords, NT * 4)), dim3(NT), 0, s, p, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero32(uint32_t* p, uint64_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_zero32, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, p, n);
     return hipGetLastError();
 }
 
@@ -419,13 +488,30 @@ hipError_t launch_find_duplicates(const uint64_t* sorted, uint64_t n, unsigned l
     return hipGetLastError();
 }
 
+uint64_t sector_count(uint64_t total_bits) { return (total_bits + SEC_BITS - 1) / SEC_BITS; }
+uint64_t super_count(uint64_t nsec) { return (nsec >> SUPER_SHIFT) + 1; }
+
+hipError_t launch_sectors(const uint64_t* words, uint64_t total_bits, uint32_t* sec, uint64_t* super,
+                          uint32_t* tmp_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s) {
+    const uint64_t ns = sector_count(total_bits);
+    if (!ns) return hipSuccess;
+    const uint64_t nw32 = total_bits / 32;
+    hipLaunchKernelGGL(k_sector_counts, dim3(grid_for(ns, NT)), dim3(NT), 0, s, (const uint32_t*)words,
+                       nw32, ns, tmp_counts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(tmp_counts, tmp_pre, ns, tmp_tiles, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sector_write, dim3(grid_for(ns * SEC_WORDS, NT * 4)), dim3(NT), 0, s,
+                       (const uint32_t*)words, nw32, ns, tmp_pre, sec, super);
+    return hipGetLastError();
+}
+
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
-                         uint32_t nlev, const uint64_t* words, const uint64_t* rank,
-                         uint32_t rank_shift, const uint64_t* fb_keys, uint64_t nfb, uint64_t N,
-                         hipStream_t s) {
+                         uint32_t nlev, const uint32_t* sec, const uint64_t* super,
+                         const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s) {
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_lookup, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, q, n, out, lev, nlev,
-                       words, rank, rank_shift, fb_keys, nfb, N);
+                       sec, super, fb_keys, nfb, N);
     return hipGetLastError();
 }
 

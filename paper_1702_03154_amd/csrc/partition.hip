@@ -1,0 +1,514 @@
+// Position-partitioned level construction for gfx950.
+//
+// Global atomics on MI355X run at a few tens of billions per second whatever the footprint,
+// while LDS atomics and streaming reads are one to two orders of magnitude faster.  So a large
+// level is not filled with global atomics: its keys are first radix-partitioned by position
+// bucket (one or two streaming passes of at most 2^DBITS-way fan-out), then one workgroup per
+// bucket runs the level's fill, finalize and filter (Algorithms 1 and 2) entirely in LDS:
+// 2^pbits positions (A and C halves) plus the bucket's keys.  The bit arrays produced are the
+// same as with any other order of insertion, because a bit of A_d survives iff exactly one key
+// of F_d lands on it.
+//
+// Data layout of a partitioned set: "regions" of fixed capacity `cap` keys, region r starting at
+// base + r * cap, with its key count in cnt[r] (counts above cap mean the region overflowed and
+// the level has to be redone another way).  A pass writes region (bin * S + slot): bin = output
+// bucket (or coarse bin), slot = the writing workgroup's index within its group, so every
+// region has exactly one writer and no global atomic is needed.
+//
+// The last levels, once the remaining keys fit in one workgroup's LDS, are all built by one
+// workgroup in one launch (k_tail).
+#include <cmath>
+
+#include "internal.h"
+
+namespace mphfk {
+
+namespace {
+
+constexpr int PT = 512;               // threads of the partition kernel
+constexpr int PITEMS = 8;             // keys per thread per tile
+constexpr int PTILE = PT * PITEMS;    // keys per tile
+constexpr int BT = 1024;              // threads of the tail kernel
+constexpr int KT = 512;               // threads of the bucket kernel
+constexpr int POOL_WORDS = 19712;     // 154 KiB of LDS for the tail kernel's keys and bits
+constexpr int BUCKET_LDS = 49152;     // bytes of LDS for a bucket's local positions and bits
+
+// Exact floor(a * 2^64 / m) for a < m < 2^63 by binary long division (one thread).
+__device__ uint64_t div_shift64(uint64_t a, uint64_t m) {
+    uint64_t q = 0, r = a;
+    for (int i = 0; i < 64; ++i) {
+        r <<= 1;
+        q <<= 1;
+        if (r >= m) {
+            r -= m;
+            q |= 1;
+        }
+    }
+    return q;
+}
+
+// Device-side twin of make_level_hash (Granlund-Montgomery Figure 4.1 constants).
+__device__ LevelHash device_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
+    LevelHash L;
+    L.seed = seed;
+    L.m = m;
+    L.bit_off = bit_off;
+    uint32_t l = 0;
+    while (l < 63 && (1ull << l) < m) ++l;
+    if ((1ull << l) < m) l = 64;
+    L.magic = (l < 64 ? div_shift64((1ull << l) - m, m) : 0) + 1;
+    L.sh1 = l < 1 ? l : 1;
+    L.sh2 = l > 1 ? l - 1 : 0;
+    return L;
+}
+
+// The segment holding dense index i: the last s in [s0, s1) with pre[s] <= i.
+__device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pre, uint32_t s0,
+                                                 uint32_t s1, uint64_t i) {
+    uint32_t lo = s0, hi = s1;   // pre[lo] <= i < pre[hi] is kept
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- radix partition pass
+//
+// Workgroup g = group * K + slot reads the dense index range `slot` of K equal parts of its
+// group's input segments [group*SG, group*SG + SG) (segment s: keys at in + s*in_stride, count
+// pre[s+1] - pre[s]) and writes each key to output region (bin * S_out + slot), where
+// bin = (pos_d(key) >> pbits) >> out_shift.  In a second pass every group is one coarse bin of
+// the first, so its keys fall in bins (group << group_shift) + [0, 2^group_shift); otherwise
+// the bins start at 0.  Either way a workgroup sees at most 2^DBITS bins.  A tile never spans
+// two input segments, so its keys are one contiguous, coalesced read.  The final pass (LPOS)
+// also writes each key's position inside its bucket, pos & (2^pbits - 1), as 16 bits beside
+// the key, so that the bucket pass needs no hashing.
+template <int DBITS, bool LPOS>
+__global__ void __launch_bounds__(PT)
+k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
+            uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift,
+            uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
+            uint16_t* __restrict__ out_lp, uint64_t out_cap, uint32_t S_out,
+            uint32_t* __restrict__ out_cnt, unsigned long long* overflow) {
+    constexpr int NB = 1 << DBITS;
+    __shared__ uint64_t skeys[PTILE];
+    __shared__ uint16_t sdig[PTILE];
+    __shared__ uint16_t slp[LPOS ? PTILE : 1];
+    __shared__ uint32_t hist[NB];
+    __shared__ uint32_t hoff[NB];
+    __shared__ uint32_t run[NB];
+    __shared__ uint32_t wsum[PT / 64 + 1];
+
+    const uint32_t group = blockIdx.x / K;
+    const uint32_t slot = blockIdx.x % K;
+    const uint32_t s0 = group * SG, s1 = s0 + SG;
+    const uint64_t g0 = pre[s0], g1 = pre[s1];
+    const uint64_t part = (g1 - g0 + K - 1) / K;
+    const uint64_t lo = g0 + (uint64_t)slot * part < g1 ? g0 + (uint64_t)slot * part : g1;
+    const uint64_t hi = lo + part < g1 ? lo + part : g1;
+    const uint64_t bin_base = grouped ? (uint64_t)group << group_shift : 0;
+    const uint64_t pmask = (1ull << pbits) - 1;
+
+    for (int d = threadIdx.x; d < NB; d += PT) {
+        hist[d] = 0;
+        run[d] = 0;
+    }
+    __syncthreads();
+
+    uint32_t s = lo < hi ? find_segment(pre, s0, s1, lo) : s0;
+    uint64_t t0 = lo;
+    while (t0 < hi) {
+        const uint64_t sb = pre[s], se = pre[s + 1] < hi ? pre[s + 1] : hi;
+        if (t0 >= se) {
+            ++s;
+            continue;
+        }
+        const uint32_t tn = (uint32_t)(se - t0 < (uint64_t)PTILE ? se - t0 : PTILE);
+        const uint64_t* src = in + (uint64_t)s * in_stride + (t0 - sb);
+        uint64_t k[PITEMS];
+#pragma unroll
+        for (int it = 0; it < PITEMS; ++it) {
+            const uint32_t j = it * PT + threadIdx.x;
+            k[it] = j < tn ? src[j] : 0;
+        }
+        uint32_t dg[PITEMS], rk[PITEMS], lp[PITEMS];
+#pragma unroll
+        for (int it = 0; it < PITEMS; ++it) {
+            const uint32_t j = it * PT + threadIdx.x;
+            dg[it] = NB;
+            if (j < tn) {
+                const uint64_t pos = level_pos(k[it], L);
+                const uint64_t bin = (pos >> pbits) >> out_shift;
+                lp[it] = (uint32_t)(pos & pmask);
+                if (bin >= bin_base && bin - bin_base < (uint64_t)NB) {
+                    dg[it] = (uint32_t)(bin - bin_base);
+                    rk[it] = atomicAdd(&hist[dg[it]], 1u);
+                } else {
+                    atomicOr(overflow, 4ull);   // a configuration error: never silently dropped
+                }
+            }
+        }
+        __syncthreads();
+        {   // exclusive scan of the tile histogram
+            constexpr int PER = NB / PT > 0 ? NB / PT : 1;
+            uint32_t v[PER];
+            uint32_t sum = 0;
+            const int b0 = threadIdx.x * PER;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                v[q] = (b0 + q < NB) ? hist[b0 + q] : 0;
+                sum += v[q];
+            }
+            uint32_t tot;
+            uint32_t ex = block_exclusive_sum<PT>(sum, wsum, &tot);
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (b0 + q < NB) {
+                    hoff[b0 + q] = ex;
+                    ex += v[q];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < PITEMS; ++it) {
+            if (dg[it] < (uint32_t)NB) {
+                const uint32_t p = hoff[dg[it]] + rk[it];
+                skeys[p] = k[it];
+                sdig[p] = (uint16_t)dg[it];
+                if (LPOS) slp[p] = (uint16_t)lp[it];
+            }
+        }
+        __syncthreads();
+        // write the runs: position p of the sorted tile goes to its bin's region
+        for (uint32_t p = threadIdx.x; p < tn; p += PT) {
+            const uint32_t d = sdig[p];
+            const uint64_t o = (uint64_t)run[d] + (p - hoff[d]);
+            if (o < out_cap) {
+                const uint64_t r = ((bin_base + d) * S_out + slot) * out_cap + o;
+                out[r] = skeys[p];
+                if (LPOS) out_lp[r] = slp[p];
+            }
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < NB; d += PT) {
+            run[d] += hist[d];
+            hist[d] = 0;
+        }
+        __syncthreads();
+        t0 += tn;
+    }
+    // only the bins this workgroup's group owns (a second-pass group owns 2^group_shift bins;
+    // the neighbouring bins belong to other groups and must not be touched)
+    const uint32_t owned = grouped ? (1u << group_shift) : (uint32_t)NB;
+    for (int d = threadIdx.x; d < NB && (uint32_t)d < owned; d += PT) {
+        const uint64_t bin = bin_base + d;
+        if (bin < nbins) {
+            out_cnt[bin * S_out + slot] = run[d] < out_cap ? run[d] : (uint32_t)out_cap;
+            if (run[d] > out_cap) atomicOr(overflow, 1ull);
+        }
+    }
+}
+
+// The segment q < S holding index i of a bucket, from the LDS prefix off[0..S].
+__device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t S, uint32_t i) {
+    uint32_t lo = 0, hi = S;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- bucket pass
+//
+// Workgroup b owns positions [b << pbits, (b+1) << pbits) of level d.  It loads the 16-bit local
+// positions of the bucket's keys (regions b*S .. b*S+S-1) into LDS, fills A and C there with LDS
+// atomics, writes the finalized A words of its positions, and writes the keys whose A bit is 0
+// (F_{d+1}) into output region b of capacity ycap, with their number in surv[b].
+__global__ void __launch_bounds__(KT)
+k_bucket(const uint64_t* __restrict__ in, const uint16_t* __restrict__ in_lp, uint64_t in_cap,
+         const uint32_t* __restrict__ cnt, uint32_t S, uint32_t pbits, uint32_t kcap,
+         uint64_t* __restrict__ A, uint64_t* __restrict__ Cout, uint64_t level_words,
+         uint64_t* __restrict__ Y, uint64_t ycap, uint32_t* __restrict__ surv,
+         unsigned long long* overflow) {
+    __shared__ uint32_t pool[BUCKET_LDS / 4];
+    __shared__ uint32_t wsum[KT / 64 + 1];
+    __shared__ uint32_t segoff[257];
+    const uint64_t b = blockIdx.x;
+    const uint32_t P = 1u << pbits;
+    uint32_t* Abits = pool;
+    uint32_t* Cbits = pool + (P >> 5);
+    uint16_t* lps = (uint16_t*)(pool + 2 * (P >> 5));
+
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (uint32_t q = 0; q < S; ++q) {
+            segoff[q] = acc;
+            acc += cnt[b * S + q];
+        }
+        segoff[S] = acc;
+    }
+    for (uint32_t w = threadIdx.x; w < 2 * (P >> 5); w += KT) pool[w] = 0;
+    __syncthreads();
+    const uint32_t nb = segoff[S];
+    if (nb > kcap) {
+        if (threadIdx.x == 0) {
+            atomicOr(overflow, 2ull);
+            surv[b] = 0;
+        }
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < nb; i += KT) {
+        const uint32_t q = seg_of(segoff, S, i);
+        lps[i] = in_lp[(b * S + q) * in_cap + (i - segoff[q])];
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += KT) {
+        const uint32_t p = lps[i];
+        const uint32_t bit = 1u << (p & 31);
+        const uint32_t old = atomicOr(&Abits[p >> 5], bit);
+        if (old & bit) atomicOr(&Cbits[p >> 5], bit);
+    }
+    __syncthreads();
+    // finalize: A &= ~C, written as 64-bit words of the level
+    const uint64_t w0 = b << (pbits - 6);
+    for (uint32_t j = threadIdx.x; j < (P >> 6); j += KT) {
+        const uint32_t a0 = Abits[2 * j] & ~Cbits[2 * j];
+        const uint32_t a1 = Abits[2 * j + 1] & ~Cbits[2 * j + 1];
+        if (w0 + j < level_words) {
+            A[w0 + j] = (uint64_t)a0 | ((uint64_t)a1 << 32);
+            if (Cout) Cout[w0 + j] = (uint64_t)Cbits[2 * j] | ((uint64_t)Cbits[2 * j + 1] << 32);
+        }
+    }
+    __syncthreads();
+    for (uint32_t w = threadIdx.x; w < (P >> 5); w += KT) Abits[w] &= ~Cbits[w];
+    __syncthreads();
+    // filter: keys whose A bit is 0 collided and go on to F_{d+1}; chunks of KT*8 keys
+    constexpr int FI = 8;
+    uint64_t* dst = Y + b * ycap;
+    uint32_t written = 0;
+    for (uint32_t c0 = 0; c0 < nb; c0 += KT * FI) {
+        uint32_t mask = 0;
+#pragma unroll
+        for (int it = 0; it < FI; ++it) {
+            const uint32_t i = c0 + it * KT + threadIdx.x;
+            if (i < nb) {
+                const uint32_t p = lps[i];
+                if (!((Abits[p >> 5] >> (p & 31)) & 1u)) mask |= 1u << it;
+            }
+        }
+        uint64_t kk[FI];
+#pragma unroll
+        for (int it = 0; it < FI; ++it) {
+            kk[it] = 0;
+            if ((mask >> it) & 1u) {
+                const uint32_t i = c0 + it * KT + threadIdx.x;
+                const uint32_t q = seg_of(segoff, S, i);
+                kk[it] = in[(b * S + q) * in_cap + (i - segoff[q])];
+            }
+        }
+        uint32_t tot;
+        uint32_t o = written + block_exclusive_sum<KT>((uint32_t)__popc(mask), wsum, &tot);
+#pragma unroll
+        for (int it = 0; it < FI; ++it)
+            if ((mask >> it) & 1u) dst[o++] = kk[it];
+        written += tot;
+    }
+    if (threadIdx.x == 0) surv[b] = written;
+}
+
+// ---------------------------------------------------------------- small levels in one workgroup
+//
+// Builds levels d0, d0+1, ... of a set of n <= kcap keys (segments of the partitioned layout or a
+// dense array) in one workgroup: m_d = ceil(gamma n_d) in IEEE double, the level's hash
+// constants, fill, finalize and filter in LDS, A written at the running bit offset.  Stops when
+// no key is left or after level D-1; the leftover keys are written to `left`.
+__global__ void __launch_bounds__(BT)
+k_tail(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
+       uint32_t nseg, uint32_t kcap, double gamma, SeedTable seeds, uint32_t d0, uint32_t D,
+       uint64_t bit_off, uint64_t* __restrict__ A, uint64_t* __restrict__ Cout,
+       TailLevel* __restrict__ rec, uint64_t* __restrict__ left, TailSummary* __restrict__ sum) {
+    __shared__ uint64_t pool[POOL_WORDS];
+    __shared__ uint32_t wsum[BT / 64 + 1];
+    __shared__ LevelHash Ls;
+    __shared__ unsigned long long wacc;
+    uint64_t* keys = pool;
+    uint32_t* Abits = (uint32_t*)(pool + kcap);
+    const uint64_t n0 = pre[nseg];
+    // load
+    for (uint64_t i = threadIdx.x; i < n0; i += BT) {
+        const uint32_t s = find_segment(pre, 0, nseg, i);
+        keys[i] = in[(uint64_t)s * in_stride + (i - pre[s])];
+    }
+    uint64_t n = n0;
+    uint32_t d = d0;
+    uint64_t off = bit_off;
+    constexpr int FI = (POOL_WORDS + BT - 1) / BT;
+    while (n > 0 && d < D) {
+        const uint64_t m = (uint64_t)ceil(gamma * (double)n);
+        const uint32_t aw = (uint32_t)((m + 31) >> 5);   // u32 words of A (and of C)
+        uint32_t* Cbits = Abits + aw + (aw & 1);
+        if (threadIdx.x == 0) {
+            Ls = device_level_hash(seeds.s[d], m, off);
+            wacc = 0;
+        }
+        for (uint32_t w = threadIdx.x; w < 2 * aw + 2; w += BT) Abits[w] = 0;
+        __syncthreads();
+        const LevelHash L = Ls;
+        for (uint32_t i = threadIdx.x; i < n; i += BT) {
+            const uint32_t p = (uint32_t)level_pos(keys[i], L);
+            const uint32_t bit = 1u << (p & 31);
+            const uint32_t old = atomicOr(&Abits[p >> 5], bit);
+            if (old & bit) atomicOr(&Cbits[p >> 5], bit);
+        }
+        __syncthreads();
+        const uint64_t words = (m + 63) >> 6;
+        unsigned long long wt = 0;
+        for (uint32_t j = threadIdx.x; j < words; j += BT) {
+            const uint32_t a0 = Abits[2 * j] & ~Cbits[2 * j];
+            const uint32_t a1 = Abits[2 * j + 1] & ~Cbits[2 * j + 1];
+            const uint64_t a = (uint64_t)a0 | ((uint64_t)a1 << 32);
+            A[(off >> 6) + j] = a;
+            if (Cout) Cout[(off >> 6) + j] = (uint64_t)Cbits[2 * j] | ((uint64_t)Cbits[2 * j + 1] << 32);
+            wt += __popcll(a);
+        }
+        wt = wave_sum(wt);
+        if (lane_id() == 0 && wt) atomicAdd(&wacc, wt);
+        __syncthreads();
+        for (uint32_t w = threadIdx.x; w < aw; w += BT) Abits[w] &= ~Cbits[w];
+        __syncthreads();
+        // filter and compact in place
+        uint32_t mask = 0;
+        uint64_t kk[FI];
+#pragma unroll
+        for (int it = 0; it < FI; ++it) {
+            const uint32_t i = it * BT + threadIdx.x;
+            kk[it] = 0;
+            if (i < n) {
+                kk[it] = keys[i];
+                const uint32_t p = (uint32_t)level_pos(kk[it], L);
+                if (!((Abits[p >> 5] >> (p & 31)) & 1u)) mask |= 1u << it;
+            }
+        }
+        uint32_t tot;
+        uint32_t o = block_exclusive_sum<BT>((uint32_t)__popc(mask), wsum, &tot);
+#pragma unroll
+        for (int it = 0; it < FI; ++it)
+            if ((mask >> it) & 1u) keys[o++] = kk[it];
+        if (threadIdx.x == 0) {
+            rec[d].n = n;
+            rec[d].m = m;
+            rec[d].weight = wacc;
+            rec[d].offset = off;
+        }
+        __syncthreads();
+        n = tot;
+        off += 64 * words;
+        ++d;
+    }
+    for (uint64_t i = threadIdx.x; i < n; i += BT) left[i] = keys[i];
+    if (threadIdx.x == 0) {
+        sum->end_level = d;
+        sum->n_left = n;
+        sum->bit_end = off;
+    }
+}
+
+// Dense copy of a segmented set (used before falling back to the global-atomic levels).
+__global__ void k_gather(const uint64_t* __restrict__ in, uint64_t in_stride,
+                         const uint64_t* __restrict__ pre, uint32_t nseg, uint64_t* __restrict__ out) {
+    const uint64_t n = pre[nseg];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t s = find_segment(pre, 0, nseg, i);
+        out[i] = in[(uint64_t)s * in_stride + (i - pre[s])];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+uint32_t tail_capacity(double gamma) {
+    // keys (8 B each) + A and C halves (gamma * kcap / 16 bytes... in u32 words, rounded up)
+    uint32_t k = 16384;
+    while (k > 64) {
+        const double m = std::ceil(gamma * k);
+        const double aw = std::ceil(m / 32.0);
+        const double bytes = 8.0 * k + 4.0 * (2 * aw + 4);
+        if (bytes <= 8.0 * POOL_WORDS) break;
+        k -= 64;
+    }
+    return k;
+}
+
+hipError_t launch_tail(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
+                       uint32_t kcap, double gamma, const SeedTable& seeds, uint32_t d0, uint32_t D,
+                       uint64_t bit_off, uint64_t* A, uint64_t* Cout, TailLevel* rec, uint64_t* left,
+                       TailSummary* sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(BT), 0, s, in, in_stride, pre, nseg, kcap, gamma, seeds,
+                       d0, D, bit_off, A, Cout, rec, left, sum);
+    return hipGetLastError();
+}
+
+BucketGeometry bucket_geometry(double gamma) {
+    // Largest power-of-two bucket (at most 2^16 positions, so a local position fits 16 bits)
+    // whose expected keys (P / gamma, plus 8 standard deviations and a margin) fit the LDS
+    // budget together with the bucket's A and C bits.
+    BucketGeometry g{};
+    for (uint32_t pb = 16; pb >= 10; --pb) {
+        const double P = (double)(1u << pb);
+        const double mu = P / gamma;
+        const double kc = std::ceil(mu + 8.0 * std::sqrt(mu) + 128.0);
+        const double bytes = 2.0 * kc + P / 4.0;
+        if (bytes <= (double)BUCKET_LDS && mu <= 16384.0) {
+            g.pbits = pb;
+            g.kcap = (uint32_t)kc;
+            return g;
+        }
+    }
+    g.pbits = 0;
+    return g;
+}
+
+hipError_t launch_partition(int dbits, bool lpos, const uint64_t* in, uint64_t in_stride,
+                            const uint64_t* pre, uint32_t groups, uint32_t SG, uint32_t K,
+                            const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
+                            uint32_t group_shift, uint64_t nbins, uint64_t* out, uint16_t* out_lp,
+                            uint64_t out_cap, uint32_t S_out, uint32_t* out_cnt,
+                            unsigned long long* overflow, hipStream_t s) {
+    const dim3 grid(groups * K);
+    const uint32_t gr = grouped ? 1u : 0u;
+#define MPHF_PART(DB, LP)                                                                       \
+    hipLaunchKernelGGL((k_partition<DB, LP>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
+                       pbits, out_shift, gr, group_shift, nbins, out, out_lp, out_cap, S_out,     \
+                       out_cnt, overflow)
+    if (dbits <= 8) {
+        if (lpos) MPHF_PART(8, true); else MPHF_PART(8, false);
+    } else {
+        if (lpos) MPHF_PART(10, true); else MPHF_PART(10, false);
+    }
+#undef MPHF_PART
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const uint64_t* in, const uint16_t* in_lp, uint64_t in_cap, const uint32_t* cnt,
+                         uint32_t S, uint64_t nbuckets, uint32_t pbits, uint32_t kcap, uint64_t* A,
+                         uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
+                         uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
+    hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_lp, in_cap, cnt, S,
+                       pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
+                         uint64_t n, uint64_t* out, hipStream_t s) {
+    if (!n) return hipSuccess;
+    uint64_t blocks = (n + 1023) / 1024;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, s, in, in_stride, pre, nseg, out);
+    return hipGetLastError();
+}
+
+}  // namespace mphfk

@@ -45,12 +45,12 @@ class Stats(C.Structure):
                 ("level_offset", _U64L), ("level_seed", _U64L),
                 ("n_fallback", C.c_uint64), ("total_bits", C.c_uint64),
                 ("rank_entries", C.c_uint64), ("structure_bytes", C.c_uint64),
-                ("bits_per_key", C.c_double), ("peak_bytes", C.c_uint64)]
+                ("bits_per_key", C.c_double), ("peak_bytes", C.c_uint64), ("lookup_bytes", C.c_uint64)]
 
 
 class View(C.Structure):
     _fields_ = [("words", C.c_void_p), ("rank", C.c_void_p), ("fallback_keys", C.c_void_p),
-                ("total_words", C.c_uint64), ("rank_entries", C.c_uint64),
+                ("collisions", C.c_void_p), ("total_words", C.c_uint64), ("rank_entries", C.c_uint64),
                 ("n_fallback", C.c_uint64)]
 
 
@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
             "mphf_export": (st, [vp, vp, u64, vp, u64, vp, u64]),
             "mphf_export_collisions": (st, [vp, u32, vp, u64]),
             "mphf_positions": (st, [vp, u64, u64, u64, vp, vp]),
+            "mphf_trim": (st, []),
             "mphf_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -111,7 +112,7 @@ class _DeviceArray:
     """A device buffer owned by the library, seen by torch without a copy."""
 
     def __init__(self, ptr: int, n: int):
-        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i8", "data": (ptr, True),
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<i8", "data": (ptr, False),
                                          "version": 2, "strides": None}
 
 
@@ -157,7 +158,7 @@ class MPHF:
             "level_seed": list(s.level_seed[:L]), "n_fallback": s.n_fallback,
             "total_bits": s.total_bits, "rank_entries": s.rank_entries,
             "structure_bytes": s.structure_bytes, "bits_per_key": s.bits_per_key,
-            "peak_bytes": s.peak_bytes,
+            "peak_bytes": s.peak_bytes, "lookup_bytes": s.lookup_bytes,
         }
 
     def export(self) -> dict:
@@ -182,7 +183,8 @@ class MPHF:
         _check(lib().mphf_view(self._h, C.byref(v)))
         res = {}
         for name, ptr, n in (("words", v.words, v.total_words), ("rank", v.rank, v.rank_entries),
-                             ("fallback_keys", v.fallback_keys, v.n_fallback)):
+                             ("fallback_keys", v.fallback_keys, v.n_fallback),
+                             ("collisions", v.collisions, v.total_words if v.collisions else 0)):
             res[name] = (torch.as_tensor(_DeviceArray(ptr, n), device=self.device) if n
                          else torch.zeros(0, dtype=torch.int64, device=self.device))
         return res

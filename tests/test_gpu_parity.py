@@ -232,3 +232,68 @@ def test_concurrent_lookups_on_streams(M):
     torch.cuda.synchronize()
     for i, o in enumerate(outs):
         assert torch.equal(o, ref[i::4])
+
+
+# ------------------------------------------------------------ build strategies
+
+def unfmix64(y):
+    inv1 = pow(0xFF51AFD7ED558CCD, -1, 1 << 64)
+    inv2 = pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)
+    z = y ^ (y >> 33)
+    z = (z * inv2) & U64
+    z ^= z >> 33
+    z = (z * inv1) & U64
+    return z ^ (z >> 33)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 2.0])
+def test_parity_two_pass_partition(M, gamma):
+    """N = 5e6: more than 256 position buckets at level 0, so two radix passes."""
+    check_against_oracle(M, keys_np(5_000_000, seed=21), gamma)
+
+
+@pytest.mark.parametrize("n,gamma", [(1000, 2.0), (100_000, 2.0), (1_000_000, 1.0)])
+def test_parity_atomic_levels(M, n, gamma):
+    """The global-atomic build (MPHF_FLAG_ATOMIC_LEVELS) gives the same structure."""
+    k = keys_np(n, seed=8)
+    t = torch.from_numpy(k.view(np.int64)).cuda()
+    import ctypes
+    o = M.Opts(25, 512, 0, 0, 1)
+    h = ctypes.c_void_p()
+    st = M.lib().mphf_build_ex(t.data_ptr(), n, gamma, 0, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == 0
+    ha = M.MPHF(h.value, t.device)
+    hb = M.build(t, gamma, 0)
+    assert ha.stats()["level_n"] == hb.stats()["level_n"]
+    assert np.array_equal(ha.export()["words"], hb.export()["words"])
+    st_o = O.build(k, gamma, 0)
+    assert np.array_equal(ha.export()["words"], st_o.words)
+    assert np.array_equal(host(ha.lookup(t)), O.lookup(st_o, k))
+
+
+def test_bucket_overflow_falls_back_to_atomic_levels(M):
+    """Adversarial keys: 20000 of them land in the first 32768 positions of level 0, more than a
+    bucket's LDS holds, so the level is redone with global atomics; the result must not change."""
+    n, gamma = 60_000, 2.0
+    m0 = math.ceil(gamma * n)
+    s0 = O.level_seeds(0, 1)[0]
+    rng = np.random.default_rng(4)
+    pos = rng.integers(0, 32768, size=20_000)
+    hs = set()
+    out = []
+    q = 0
+    for p in pos.tolist():           # h = p + j * m0 has h mod m0 = p
+        h = p + (int(rng.integers(1, 2**40)) * m0)
+        if h not in hs and h <= U64:
+            hs.add(h)
+            out.append(unfmix64(h) ^ s0)
+    rest = keys_np(n - len(out), seed=31)
+    k = np.unique(np.concatenate([np.array(out, dtype=np.uint64), rest]))
+    assert np.sum(O.level_positions(k, s0, math.ceil(gamma * len(k))) < 32768) > 18_000
+    check_against_oracle(M, k, gamma)
+
+
+def test_tail_only_sizes(M):
+    # every size up to one workgroup's LDS is built by the single-workgroup kernel
+    for n in (7, 1000, 16_000, 16_384, 16_385, 20_000):
+        check_against_oracle(M, keys_np(n, seed=n), 2.0)
