@@ -2,6 +2,9 @@
 
     python -m paper_1702_03154_amd.profsum stats <results.db>          per-kernel durations
     python -m paper_1702_03154_amd.profsum pmc <results.db> <COUNTER>  per-kernel counter values
+    python -m paper_1702_03154_amd.profsum traffic <fetch.db> <write.db> <kernel> <queries> <out.json>
+        HBM bytes of one launch of <kernel>, each counter scaled by what it reads for the
+        1 GiB calibration copy (bench.py --calibrate-copy) run in the same process
 
 Kernel names are shortened (namespace and argument list dropped).
 """
@@ -43,10 +46,47 @@ def pmc(db: str, counter: str, out=sys.stdout):
         print(f"{short(n):60s} {k:10d} {a:14.1f} {lo:14.1f} {hi:14.1f}", file=out)
 
 
+def _per_dispatch(db: str, counter: str):
+    c = sqlite3.connect(db)
+    return c.execute("select dispatch_id, kernel_name, value from counters_collection "
+                     "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
+
+
+def _calibration(rows):
+    """The 1 GiB calibration copy: the last runtime copy kernel before the first library kernel."""
+    first = next(i for i, r in enumerate(rows) if "mphfk" in r[1])
+    cal = [r for r in rows[:first] if "copyBuffer" in r[1]]
+    return cal[-1][2]
+
+
+def traffic(fetch_db: str, write_db: str, kernel: str, queries: int, out_json: str):
+    import hashlib
+    import json
+    import os
+    f_rows = _per_dispatch(fetch_db, "FETCH_SIZE")
+    w_rows = _per_dispatch(write_db, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    fs = gib_kib / _calibration(f_rows)
+    ws = gib_kib / _calibration(w_rows)
+    fk = [r[2] for r in f_rows if short(r[1]) == kernel]
+    wk = [r[2] for r in w_rows if short(r[1]) == kernel]
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
+    res = {"kernel": kernel, "queries": queries,
+           "fetch_kib": sum(fk) / len(fk), "write_kib": sum(wk) / len(wk),
+           "fetch_scale": fs, "write_scale": ws,
+           "bytes_per_launch": (sum(fk) / len(fk) * fs + sum(wk) / len(wk) * ws) * 1024.0,
+           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(float(sys.argv[5])), sys.argv[6])
     else:
         raise SystemExit(__doc__)
