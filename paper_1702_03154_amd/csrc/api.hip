@@ -135,9 +135,8 @@ void configure_pool(int dev) {
 struct WsBufs {
     uint64_t *Z = nullptr, *X = nullptr, *Y[2] = {nullptr, nullptr}, *preZ = nullptr,
              *preY[2] = {nullptr, nullptr}, *tiles = nullptr, *host = nullptr;
-    uint16_t* Xlp = nullptr;
     uint32_t *cntZ = nullptr, *cntX = nullptr, *surv[2] = {nullptr, nullptr};
-    uint64_t capZ = 0, capX = 0, capXlp = 0, capCntZ = 0, capCntX = 0, capTiles = 0, capPreZ = 0;
+    uint64_t capZ = 0, capX = 0, capCntZ = 0, capCntX = 0, capTiles = 0, capPreZ = 0;
     uint64_t capY[2] = {0, 0}, capSurv[2] = {0, 0}, capPreY[2] = {0, 0};
 };
 
@@ -145,7 +144,7 @@ struct Workspace {
     std::mutex mu;
     WsBufs b;
     void release() {
-        void* bufs[] = {b.Z, b.X, b.Y[0], b.Y[1], b.preZ, b.preY[0], b.preY[1], b.tiles, b.Xlp, b.cntZ,
+        void* bufs[] = {b.Z, b.X, b.Y[0], b.Y[1], b.preZ, b.preY[0], b.preY[1], b.tiles, b.cntZ,
                         b.cntX, b.surv[0], b.surv[1]};
         for (void* q : bufs)
             if (q) (void)hipFree(q);
@@ -494,10 +493,9 @@ class Builder {
             W = std::max<uint64_t>(1, std::min<uint64_t>(W, 256));
             const uint64_t cap = region_cap((double)n / W * (double)P / (double)m);
             if ((st = ensure(&ws_->X, &ws_->capX, B * W * cap, "partition X")) != MPHF_OK) return st;
-            if ((st = ensure(&ws_->Xlp, &ws_->capXlp, B * W * cap, "partition X positions")) != MPHF_OK) return st;
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
-            HIP_TRY(launch_partition(B <= 256 ? 8 : 10, true, in.base, in.stride, in.pre, 1, in.nseg,
-                                     (uint32_t)W, L, pb, 0, false, 0, B, ws_->X, ws_->Xlp, cap, (uint32_t)W,
+            HIP_TRY(launch_partition(B <= 256 ? 8 : 10, false, in.base, in.stride, in.pre, 1, in.nseg,
+                                     (uint32_t)W, L, pb, 0, false, 0, B, ws_->X, cap, (uint32_t)W,
                                      ws_->cntX, ovf, s_),
                     "partition");
             xcap = cap;
@@ -513,7 +511,7 @@ class Builder {
             if ((st = ensure(&ws_->Z, &ws_->capZ, C * W * cap1, "partition Z")) != MPHF_OK) return st;
             if ((st = ensure(&ws_->cntZ, &ws_->capCntZ, C * W + 1, "counts Z")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
-                                     fb, false, 0, C, ws_->Z, nullptr, cap1, (uint32_t)W, ws_->cntZ, ovf, s_),
+                                     fb, false, 0, C, ws_->Z, cap1, (uint32_t)W, ws_->cntZ, ovf, s_),
                     "partition 1");
             HIP_TRY(launch_zero32(ws_->cntZ + C * W, 1, s_), "zero count tail");
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
@@ -524,10 +522,9 @@ class Builder {
             const double e2 = bin_keys / (double)K / (double)(1ull << fb) * (1.0 + 8.0 / std::sqrt(bin_keys));
             const uint64_t cap2 = region_cap(e2);
             if ((st = ensure(&ws_->X, &ws_->capX, B * K * cap2, "partition X")) != MPHF_OK) return st;
-            if ((st = ensure(&ws_->Xlp, &ws_->capXlp, B * K * cap2, "partition X positions")) != MPHF_OK) return st;
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, ws_->Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
-                                     (uint32_t)K, L, pb, 0, true, fb, B, ws_->X, ws_->Xlp, cap2, (uint32_t)K,
+                                     (uint32_t)K, L, pb, 0, true, fb, B, ws_->X, cap2, (uint32_t)K,
                                      ws_->cntX, ovf, s_),
                     "partition 2");
             xcap = cap2;
@@ -540,7 +537,7 @@ class Builder {
         if ((st = ensure(&ws_->surv[yp], &ws_->capSurv[yp], B + 1, "survivor counts")) != MPHF_OK) return st;
         if ((st = ensure(&ws_->preY[yp], &ws_->capPreY[yp], B + 1, "survivor prefix")) != MPHF_OK) return st;
         uint64_t* C_level = coll_ ? coll_ + off / 64 : nullptr;
-        HIP_TRY(launch_bucket(ws_->X, ws_->Xlp, xcap, ws_->cntX, S, B, pb, g.kcap, words_ + off / 64, C_level, wd,
+        HIP_TRY(launch_bucket(ws_->X, xcap, ws_->cntX, S, B, L, pb, g.kcap, words_ + off / 64, C_level, wd,
                               ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_),
                 "bucket");
         HIP_TRY(launch_zero32(ws_->surv[yp] + B, 1, s_), "zero count tail");

@@ -29,6 +29,17 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t x) {
     return x;
 }
 
+// The inverse of fmix64: each x ^= x >> 33 undoes itself on 64 bits, and the multipliers are
+// replaced by their inverses modulo 2^64.
+__device__ __forceinline__ uint64_t unfmix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0x9CB4B2F8129337DBull;   // 0xC4CEB9FE1A85EC53^-1 mod 2^64
+    x ^= x >> 33;
+    x *= 0x4F74430C22A54005ull;   // 0xFF51AFD7ED558CCD^-1 mod 2^64
+    x ^= x >> 33;
+    return x;
+}
+
 __device__ __forceinline__ uint64_t mod_invariant(uint64_t n, uint64_t m, uint64_t magic,
                                                   uint32_t sh1, uint32_t sh2) {
     uint64_t t = __umul64hi(magic, n);

@@ -42,15 +42,15 @@ struct BucketGeometry {
 BucketGeometry bucket_geometry(double gamma);
 uint32_t tail_capacity(double gamma);
 
-hipError_t launch_partition(int dbits, bool lpos, const uint64_t* in, uint64_t in_stride,
+hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t in_stride,
                             const uint64_t* pre, uint32_t groups, uint32_t SG, uint32_t K,
                             const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
-                            uint32_t group_shift, uint64_t nbins, uint64_t* out, uint16_t* out_lp,
-                            uint64_t out_cap, uint32_t S_out, uint32_t* out_cnt,
-                            unsigned long long* overflow, hipStream_t s);
-hipError_t launch_bucket(const uint64_t* in, const uint16_t* in_lp, uint64_t in_cap, const uint32_t* cnt,
-                         uint32_t S, uint64_t nbuckets, uint32_t pbits, uint32_t kcap, uint64_t* A,
-                         uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
+                            uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
+                            uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
+                            hipStream_t s);
+hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
+                         uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint32_t kcap,
+                         uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s);
 hipError_t launch_gather(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
                          uint64_t n, uint64_t* out, hipStream_t s);

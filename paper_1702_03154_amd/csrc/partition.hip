@@ -9,6 +9,10 @@
 // same as with any other order of insertion, because a bit of A_d survives iff exactly one key
 // of F_d lands on it.
 //
+// The partition passes and the bucket pass carry h_d(x) = fmix64(x ^ s_d) instead of the key x:
+// the position is h_d(x) mod m_d, and the bucket pass gets x back for the survivors with the
+// exact inverse of fmix64, so every record stays 8 bytes.
+//
 // Data layout of a partitioned set: "regions" of fixed capacity `cap` keys, region r starting at
 // base + r * cap, with its key count in cnt[r] (counts above cap mean the region overflowed and
 // the level has to be redone another way).  A pass writes region (bin * S + slot): bin = output
@@ -81,20 +85,19 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // bin = (pos_d(key) >> pbits) >> out_shift.  In a second pass every group is one coarse bin of
 // the first, so its keys fall in bins (group << group_shift) + [0, 2^group_shift); otherwise
 // the bins start at 0.  Either way a workgroup sees at most 2^DBITS bins.  A tile never spans
-// two input segments, so its keys are one contiguous, coalesced read.  The final pass (LPOS)
-// also writes each key's position inside its bucket, pos & (2^pbits - 1), as 16 bits beside
-// the key, so that the bucket pass needs no hashing.
-template <int DBITS, bool LPOS>
+// two input segments, so its values are one contiguous, coalesced read.  The input holds keys
+// (HASHED = false: h = fmix64(x ^ s_d) is computed here) or already their level hashes; the
+// output always holds the level hashes.
+template <int DBITS, bool HASHED>
 __global__ void __launch_bounds__(PT)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
             uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift,
             uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
-            uint16_t* __restrict__ out_lp, uint64_t out_cap, uint32_t S_out,
-            uint32_t* __restrict__ out_cnt, unsigned long long* overflow) {
+            uint64_t out_cap, uint32_t S_out, uint32_t* __restrict__ out_cnt,
+            unsigned long long* overflow) {
     constexpr int NB = 1 << DBITS;
     __shared__ uint64_t skeys[PTILE];
     __shared__ uint16_t sdig[PTILE];
-    __shared__ uint16_t slp[LPOS ? PTILE : 1];
     __shared__ uint32_t hist[NB];
     __shared__ uint32_t hoff[NB];
     __shared__ uint32_t run[NB];
@@ -108,7 +111,6 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     const uint64_t lo = g0 + (uint64_t)slot * part < g1 ? g0 + (uint64_t)slot * part : g1;
     const uint64_t hi = lo + part < g1 ? lo + part : g1;
     const uint64_t bin_base = grouped ? (uint64_t)group << group_shift : 0;
-    const uint64_t pmask = (1ull << pbits) - 1;
 
     for (int d = threadIdx.x; d < NB; d += PT) {
         hist[d] = 0;
@@ -132,15 +134,15 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             const uint32_t j = it * PT + threadIdx.x;
             k[it] = j < tn ? src[j] : 0;
         }
-        uint32_t dg[PITEMS], rk[PITEMS], lp[PITEMS];
+        uint32_t dg[PITEMS], rk[PITEMS];
 #pragma unroll
         for (int it = 0; it < PITEMS; ++it) {
             const uint32_t j = it * PT + threadIdx.x;
             dg[it] = NB;
             if (j < tn) {
-                const uint64_t pos = level_pos(k[it], L);
+                if (!HASHED) k[it] = fmix64(k[it] ^ L.seed);
+                const uint64_t pos = mod_invariant(k[it], L.m, L.magic, L.sh1, L.sh2);
                 const uint64_t bin = (pos >> pbits) >> out_shift;
-                lp[it] = (uint32_t)(pos & pmask);
                 if (bin >= bin_base && bin - bin_base < (uint64_t)NB) {
                     dg[it] = (uint32_t)(bin - bin_base);
                     rk[it] = atomicAdd(&hist[dg[it]], 1u);
@@ -176,7 +178,6 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                 const uint32_t p = hoff[dg[it]] + rk[it];
                 skeys[p] = k[it];
                 sdig[p] = (uint16_t)dg[it];
-                if (LPOS) slp[p] = (uint16_t)lp[it];
             }
         }
         __syncthreads();
@@ -185,9 +186,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             const uint32_t d = sdig[p];
             const uint64_t o = (uint64_t)run[d] + (p - hoff[d]);
             if (o < out_cap) {
-                const uint64_t r = ((bin_base + d) * S_out + slot) * out_cap + o;
-                out[r] = skeys[p];
-                if (LPOS) out_lp[r] = slp[p];
+                out[((bin_base + d) * S_out + slot) * out_cap + o] = skeys[p];
             }
         }
         __syncthreads();
@@ -222,16 +221,18 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t S, uint
 
 // ---------------------------------------------------------------- bucket pass
 //
-// Workgroup b owns positions [b << pbits, (b+1) << pbits) of level d.  It loads the 16-bit local
-// positions of the bucket's keys (regions b*S .. b*S+S-1) into LDS, fills A and C there with LDS
-// atomics, writes the finalized A words of its positions, and writes the keys whose A bit is 0
-// (F_{d+1}) into output region b of capacity ycap, with their number in surv[b].
+// Workgroup b owns positions [b << pbits, (b+1) << pbits) of level d.  It reads the level hashes
+// of the bucket's keys (regions b*S .. b*S+S-1) once into registers, writes their positions
+// inside the bucket to LDS, fills A and C there with LDS atomics, writes the finalized A words of
+// its positions, and writes the keys whose A bit is 0 (F_{d+1}, recovered from their hashes) into
+// output region b of capacity ycap, with their number in surv[b].
+constexpr int BI = 36;   // hashes held per thread: KT * BI >= the largest kcap
+
 __global__ void __launch_bounds__(KT)
-k_bucket(const uint64_t* __restrict__ in, const uint16_t* __restrict__ in_lp, uint64_t in_cap,
-         const uint32_t* __restrict__ cnt, uint32_t S, uint32_t pbits, uint32_t kcap,
-         uint64_t* __restrict__ A, uint64_t* __restrict__ Cout, uint64_t level_words,
-         uint64_t* __restrict__ Y, uint64_t ycap, uint32_t* __restrict__ surv,
-         unsigned long long* overflow) {
+k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __restrict__ cnt,
+         uint32_t S, LevelHash L, uint32_t pbits, uint32_t kcap, uint64_t* __restrict__ A,
+         uint64_t* __restrict__ Cout, uint64_t level_words, uint64_t* __restrict__ Y, uint64_t ycap,
+         uint32_t* __restrict__ surv, unsigned long long* overflow) {
     __shared__ uint32_t pool[BUCKET_LDS / 4];
     __shared__ uint32_t wsum[KT / 64 + 1];
     __shared__ uint32_t segoff[257];
@@ -252,23 +253,39 @@ k_bucket(const uint64_t* __restrict__ in, const uint16_t* __restrict__ in_lp, ui
     for (uint32_t w = threadIdx.x; w < 2 * (P >> 5); w += KT) pool[w] = 0;
     __syncthreads();
     const uint32_t nb = segoff[S];
-    if (nb > kcap) {
+    if (nb > kcap || nb > (uint32_t)(KT * BI)) {
         if (threadIdx.x == 0) {
             atomicOr(overflow, 2ull);
             surv[b] = 0;
         }
         return;
     }
-    for (uint32_t i = threadIdx.x; i < nb; i += KT) {
-        const uint32_t q = seg_of(segoff, S, i);
-        lps[i] = in_lp[(b * S + q) * in_cap + (i - segoff[q])];
+    const uint64_t pbase = b << pbits;
+    uint64_t h[BI];
+#pragma unroll
+    for (int it = 0; it < BI; ++it) {
+        const uint32_t i = it * KT + threadIdx.x;
+        h[it] = 0;
+        if (i < nb) {
+            const uint32_t q = seg_of(segoff, S, i);
+            h[it] = in[(b * S + q) * in_cap + (i - segoff[q])];
+        }
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += KT) {
-        const uint32_t p = lps[i];
-        const uint32_t bit = 1u << (p & 31);
-        const uint32_t old = atomicOr(&Abits[p >> 5], bit);
-        if (old & bit) atomicOr(&Cbits[p >> 5], bit);
+#pragma unroll
+    for (int it = 0; it < BI; ++it) {
+        const uint32_t i = it * KT + threadIdx.x;
+        if (i < nb) {
+            const uint64_t p = mod_invariant(h[it], L.m, L.magic, L.sh1, L.sh2) - pbase;
+            if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
+                atomicOr(overflow, 8ull);
+                lps[i] = 0;
+                continue;
+            }
+            lps[i] = (uint16_t)p;
+            const uint32_t bit = 1u << (p & 31);
+            const uint32_t old = atomicOr(&Abits[p >> 5], bit);
+            if (old & bit) atomicOr(&Cbits[p >> 5], bit);
+        }
     }
     __syncthreads();
     // finalize: A &= ~C, written as 64-bit words of the level
@@ -284,38 +301,23 @@ k_bucket(const uint64_t* __restrict__ in, const uint16_t* __restrict__ in_lp, ui
     __syncthreads();
     for (uint32_t w = threadIdx.x; w < (P >> 5); w += KT) Abits[w] &= ~Cbits[w];
     __syncthreads();
-    // filter: keys whose A bit is 0 collided and go on to F_{d+1}; chunks of KT*8 keys
-    constexpr int FI = 8;
-    uint64_t* dst = Y + b * ycap;
-    uint32_t written = 0;
-    for (uint32_t c0 = 0; c0 < nb; c0 += KT * FI) {
-        uint32_t mask = 0;
+    // filter: keys whose A bit is 0 collided and go on to F_{d+1}
+    uint64_t mask = 0;
 #pragma unroll
-        for (int it = 0; it < FI; ++it) {
-            const uint32_t i = c0 + it * KT + threadIdx.x;
-            if (i < nb) {
-                const uint32_t p = lps[i];
-                if (!((Abits[p >> 5] >> (p & 31)) & 1u)) mask |= 1u << it;
-            }
+    for (int it = 0; it < BI; ++it) {
+        const uint32_t i = it * KT + threadIdx.x;
+        if (i < nb) {
+            const uint32_t p = lps[i];
+            if (!((Abits[p >> 5] >> (p & 31)) & 1u)) mask |= 1ull << it;
         }
-        uint64_t kk[FI];
-#pragma unroll
-        for (int it = 0; it < FI; ++it) {
-            kk[it] = 0;
-            if ((mask >> it) & 1u) {
-                const uint32_t i = c0 + it * KT + threadIdx.x;
-                const uint32_t q = seg_of(segoff, S, i);
-                kk[it] = in[(b * S + q) * in_cap + (i - segoff[q])];
-            }
-        }
-        uint32_t tot;
-        uint32_t o = written + block_exclusive_sum<KT>((uint32_t)__popc(mask), wsum, &tot);
-#pragma unroll
-        for (int it = 0; it < FI; ++it)
-            if ((mask >> it) & 1u) dst[o++] = kk[it];
-        written += tot;
     }
-    if (threadIdx.x == 0) surv[b] = written;
+    uint32_t tot;
+    uint32_t o = block_exclusive_sum<KT>((uint32_t)__popcll(mask), wsum, &tot);
+    uint64_t* dst = Y + b * ycap;
+#pragma unroll
+    for (int it = 0; it < BI; ++it)
+        if ((mask >> it) & 1ull) dst[o++] = unfmix64(h[it]) ^ L.seed;
+    if (threadIdx.x == 0) surv[b] = tot;
 }
 
 // ---------------------------------------------------------------- small levels in one workgroup
@@ -462,7 +464,7 @@ BucketGeometry bucket_geometry(double gamma) {
         const double mu = P / gamma;
         const double kc = std::ceil(mu + 8.0 * std::sqrt(mu) + 128.0);
         const double bytes = 2.0 * kc + P / 4.0;
-        if (bytes <= (double)BUCKET_LDS && mu <= 16384.0) {
+        if (bytes <= (double)BUCKET_LDS && mu <= 16384.0 && kc <= (double)(KT * BI)) {
             g.pbits = pb;
             g.kcap = (uint32_t)kc;
             return g;
@@ -472,32 +474,32 @@ BucketGeometry bucket_geometry(double gamma) {
     return g;
 }
 
-hipError_t launch_partition(int dbits, bool lpos, const uint64_t* in, uint64_t in_stride,
+hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t in_stride,
                             const uint64_t* pre, uint32_t groups, uint32_t SG, uint32_t K,
                             const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
-                            uint32_t group_shift, uint64_t nbins, uint64_t* out, uint16_t* out_lp,
-                            uint64_t out_cap, uint32_t S_out, uint32_t* out_cnt,
-                            unsigned long long* overflow, hipStream_t s) {
+                            uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
+                            uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
+                            hipStream_t s) {
     const dim3 grid(groups * K);
     const uint32_t gr = grouped ? 1u : 0u;
-#define MPHF_PART(DB, LP)                                                                       \
-    hipLaunchKernelGGL((k_partition<DB, LP>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
-                       pbits, out_shift, gr, group_shift, nbins, out, out_lp, out_cap, S_out,     \
-                       out_cnt, overflow)
+#define MPHF_PART(DB, HS)                                                                       \
+    hipLaunchKernelGGL((k_partition<DB, HS>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
+                       pbits, out_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt,    \
+                       overflow)
     if (dbits <= 8) {
-        if (lpos) MPHF_PART(8, true); else MPHF_PART(8, false);
+        if (hashed) MPHF_PART(8, true); else MPHF_PART(8, false);
     } else {
-        if (lpos) MPHF_PART(10, true); else MPHF_PART(10, false);
+        if (hashed) MPHF_PART(10, true); else MPHF_PART(10, false);
     }
 #undef MPHF_PART
     return hipGetLastError();
 }
 
-hipError_t launch_bucket(const uint64_t* in, const uint16_t* in_lp, uint64_t in_cap, const uint32_t* cnt,
-                         uint32_t S, uint64_t nbuckets, uint32_t pbits, uint32_t kcap, uint64_t* A,
-                         uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
+hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
+                         uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint32_t kcap,
+                         uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
-    hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_lp, in_cap, cnt, S,
+    hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
                        pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
     return hipGetLastError();
 }
