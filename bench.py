@@ -1,8 +1,15 @@
 """Benchmark of the cascading-bit-array MPHF hot path on one MI355X.
 
-One step = one build (every level, the fallback table and the rank table) of N
-distinct 64-bit keys already resident in HBM, followed by the lookup of all N
-keys in a seeded shuffled order.  Prints one JSON line.
+Default workload (plain): one step = one build (every level, the fallback table
+and the rank table) of N distinct 64-bit keys already resident in HBM, followed
+by the lookup of all N keys in a seeded shuffled order.
+
+--workload batch: one step = one batched build of 65,536 independent sets with
+log-uniform sizes in [16, 65536] (seeded) plus the lookup of every key of every
+set, shuffled, beside the same work done by a loop of plain per-set builds and
+lookups over a seeded sample of the sets.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -67,8 +74,105 @@ def cpu_baseline(n: int, gamma: float):
             "build_keys_per_s": n / (t1 - t0), "lookup_queries_per_s": n / (t2 - t1)}
 
 
+def bench_batch(args):
+    """Batched build + lookup of many independent sets against a loop of plain per-set calls."""
+    import statistics
+
+    import torch
+
+    from paper_1702_03154_amd import inputs, mphf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nsets = int(args.sets)
+    sizes = inputs.log_uniform_sizes(nsets, 16, 65536, seed=3)
+    off_h = inputs.set_offsets(sizes)
+    total = int(off_h[-1])
+    keys = inputs.set_keys(sizes, seed=4, device=dev)
+    off = off_h.to(dev)
+    set_ids = torch.repeat_interleave(torch.arange(nsets, device=dev), sizes.to(dev))
+    pi = inputs.feistel_permutation(total, seed=2, device=dev)
+    q_ids, q_keys = set_ids[pi].contiguous(), keys[pi].contiguous()
+    del pi
+    out = torch.empty(total, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    print(f"# inputs ready: {nsets} sets, {total} keys", file=sys.stderr, flush=True)
+
+    s = torch.cuda.current_stream()
+    build_ms, lookup_ms, step_ms = [], [], []
+    tot = None
+    for it in range(args.warmup + args.steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(s)
+        b = mphf.build_batch(keys, off, args.gamma, 0)
+        e1.record(s)
+        b.lookup(q_ids, q_keys, out=out)
+        e2.record(s)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            build_ms.append(e0.elapsed_time(e1))
+            lookup_ms.append(e1.elapsed_time(e2))
+            step_ms.append(e0.elapsed_time(e2))
+        if tot is None:
+            tot = b.totals()
+        b.close()
+        print(f"# step {it}: batch build {e0.elapsed_time(e1):.3f} ms lookup {e1.elapsed_time(e2):.3f} ms",
+              file=sys.stderr, flush=True)
+    # labels of every set are a bijection onto [1, n_s]: offset + label - 1 covers [0, total)
+    g = off[q_ids] + out - 1
+    seen = torch.zeros(total, dtype=torch.int8, device=dev)
+    ok = bool(((out >= 1) & (g < off[q_ids + 1])).all())
+    seen[g] = 1
+    ok = ok and bool(seen.all())
+    del seen, g
+
+    # the same work as a loop of plain one-set-per-launch calls, over a seeded sample of the sets
+    sample = inputs.feistel_permutation(nsets, seed=6)[: int(args.plain_sample)].tolist()
+    plain_keys = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in sample:
+        a, c = int(off_h[j]), int(off_h[j + 1])
+        ks = keys[a:c]
+        h = mphf.build(ks, args.gamma, 0)
+        h.lookup(ks, out=out[a:c])
+        h.close()
+        plain_keys += c - a
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+
+    tb, tl = statistics.median(build_ms), statistics.median(lookup_ms)
+    total_ms = sum(step_ms)
+    value = total * args.steps / (total_ms / 1e3)
+    res = {
+        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "value": value, "unit": "keys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batched build + shuffled lookup of {nsets} independent sets, sizes "
+                               f"log-uniform in [16, 65536] (seed 3), keys SplitMix64 per set (seed 4), "
+                               f"gamma={args.gamma}", "sets": nsets, "keys": total, "gamma": args.gamma},
+        "build_keys_per_s": total / (tb / 1e3), "lookup_queries_per_s": total / (tl / 1e3),
+        "build_ms": tb, "lookup_ms": tl,
+        "labels_bijective_per_set": ok,
+        "bits_per_key": tot["bits_per_key"],
+        "plain_loop": {"value": plain_keys / plain_s, "unit": "keys/s", "sets": len(sample),
+                       "keys": plain_keys,
+                       "sample": "seeded Feistel sample of the sets; per set one plain build and "
+                                 "one lookup of its keys, host-timed including every launch"},
+        "batched_over_plain": value / (plain_keys / plain_s),
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["plain", "batch"], default="plain")
+    ap.add_argument("--sets", type=float, default=65536)
+    ap.add_argument("--plain-sample", type=float, default=2048)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -83,6 +187,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported on this build "
               "(the sharded design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import torch
 

@@ -147,6 +147,51 @@ mphf_status mphf_export_collisions(const mphf_t* h, uint32_t level, uint64_t* ou
 mphf_status mphf_positions(const uint64_t* keys, uint64_t n, uint64_t level_seed, uint64_t m,
                            uint64_t* out, void* stream);
 
+/* ---- Batched builds: many independent key sets built in one launch ---------------------------
+ * Set s holds the device keys keys[offsets[s] .. offsets[s+1]) (offsets: nsets+1 device u64,
+ * non-decreasing, offsets[0] = 0).  Every set is an independent function with labels 1..n_s whose
+ * levels, bits and labels are those of a standalone build of that set with the same gamma, seed
+ * and options (Section 2; the levels of a set depend only on its keys, gamma and the level seeds).
+ * A set may have at most 2^19 / gamma keys (ceil(gamma n) <= 2^19: its A and C bits live in one
+ * workgroup's LDS).  A set that keeps more than 2048 keys after its last level fails the whole
+ * batch with MPHF_E_INVALID, and duplicate keys within a set with MPHF_E_DUPLICATE_KEYS; keys
+ * of different sets may be equal.  flags must be 0, rank_sample 512; keep_collisions is ignored.  The build returns when the batch is complete on `stream`.  A batch handle owns its
+ * device memory and is immutable, like an mphf_t. */
+typedef struct mphf_batch mphf_batch_t;
+
+typedef struct mphf_set_info {
+    uint64_t n;
+    uint32_t num_levels;
+    uint32_t n_fallback;
+    uint64_t level_n[MPHF_MAX_LEVELS];
+    uint64_t level_m[MPHF_MAX_LEVELS];
+    uint64_t level_offset[MPHF_MAX_LEVELS];   /* bit offset inside the set's own bits */
+    uint64_t total_bits;                      /* the set's bits (64-bit padded levels) */
+} mphf_set_info_t;
+
+mphf_status mphf_build_batch(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets,
+                             double gamma, uint64_t seed, const mphf_opts* opts, void* stream,
+                             mphf_batch_t** out);
+
+/* Label each (set_ids[i], keys[i]) device pair into out[i] (Algorithm 3 within set set_ids[i]);
+ * a set id out of range gives 0.  Asynchronous on `stream`. */
+mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, const uint64_t* keys,
+                              uint64_t n, uint64_t* out, void* stream);
+
+/* Sizes of set `set` (host values, synchronous). */
+mphf_status mphf_batch_set_info(const mphf_batch_t* b, uint64_t set, mphf_set_info_t* info);
+
+/* Host copies of set `set`'s bits (info.total_bits / 64 words) and fallback keys (ascending). */
+mphf_status mphf_batch_export_set(const mphf_batch_t* b, uint64_t set, uint64_t* words, uint64_t nwords,
+                                  uint64_t* fallback_keys, uint64_t nfb);
+
+/* Sets, total keys, total bits and bits/key of the whole batch (structure as in mphf_stats). */
+mphf_status mphf_batch_totals(const mphf_batch_t* b, uint64_t* nsets, uint64_t* nkeys,
+                              uint64_t* total_bits, double* bits_per_key);
+
+/* Free every device buffer of b.  NULL is allowed; must not overlap a lookup on b. */
+void mphf_batch_destroy(mphf_batch_t* b);
+
 /* Free the build temporaries the library keeps per device between builds (a few times the
  * largest key set built so far).  Must not overlap a build. */
 mphf_status mphf_trim(void);

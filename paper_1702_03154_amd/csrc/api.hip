@@ -886,3 +886,243 @@ mphf_status mphf_trim(void) {
 const char* mphf_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- batched builds
+
+struct mphf_batch {
+    int device = 0;
+    uint64_t nsets = 0, nkeys = 0, total_bits = 0, nrank = 0, nsec = 0, nleft = 0;
+    double gamma = 0;
+    uint32_t D = 25;
+    SeedTable seeds{};
+    BatchSet* sets = nullptr;
+    BatchLevel* levels = nullptr;
+    uint64_t* words = nullptr;
+    uint64_t* rank = nullptr;
+    uint32_t* sec = nullptr;
+    uint64_t* super = nullptr;
+    uint64_t* left = nullptr;
+};
+
+namespace {
+
+void free_batch(mphf_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    void* bufs[] = {b->sets, b->levels, b->words, b->rank, b->sec, b->super, b->left};
+    for (void* p : bufs)
+        if (p) (void)hipFreeAsync(p, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+    delete b;
+}
+
+constexpr uint32_t BATCH_LEFT_CAP = 2048;
+constexpr uint64_t BATCH_MAX_M = 1ull << 19;   // A and C of the level in LDS: 128 KiB
+
+mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
+                             uint64_t seed, const mphf_opts& o, hipStream_t s, mphf_batch** out) {
+    if (!(gamma >= 1.0) || !std::isfinite(gamma)) return fail(MPHF_E_INVALID, "gamma must be a finite number >= 1");
+    if (!nsets) return fail(MPHF_E_INVALID, "nsets must be positive");
+    if (!offsets || !is_device_ptr(offsets)) return fail(MPHF_E_INVALID, "offsets must be device memory");
+    mphf_status st = check_opts(o);
+    if (st != MPHF_OK) return st;
+    if (o.flags) return fail(MPHF_E_INVALID, "flags are not supported for batched builds");
+    if (o.rank_sample != 512) return fail(MPHF_E_INVALID, "batched builds use rank_sample 512");
+    std::vector<uint64_t> off(nsets + 1);
+    HIP_TRY(hipMemcpy(off.data(), offsets, (nsets + 1) * 8, hipMemcpyDeviceToHost), "copy offsets");
+    if (off[0] != 0) return fail(MPHF_E_INVALID, "offsets[0] must be 0");
+    uint64_t max_n = 0;
+    for (uint64_t i = 0; i < nsets; ++i) {
+        if (off[i + 1] < off[i]) return fail(MPHF_E_INVALID, "offsets must be non-decreasing");
+        max_n = std::max(max_n, off[i + 1] - off[i]);
+    }
+    const uint64_t total = off[nsets];
+    if (total && (!keys || !is_device_ptr(keys))) return fail(MPHF_E_INVALID, "keys must be device memory");
+    const uint64_t max_m = level_size(gamma, max_n);
+    if (max_m > BATCH_MAX_M) return fail(MPHF_E_INVALID, "a set is too large for a batched build");
+
+    mphf_batch* b = new mphf_batch();
+    HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
+    configure_pool(b->device);
+    b->nsets = nsets;
+    b->nkeys = total;
+    b->gamma = gamma;
+    b->D = o.max_levels;
+    level_seeds(seed, o.max_levels, b->seeds.s);
+    Arena ar(o.mem_budget, s);
+    struct Guard {   // on failure the arena frees the buffers; only the handle itself is deleted here
+        mphf_batch* b;
+        ~Guard() { delete b; }
+    } guard{b};
+
+    // largest sets first, and a worst-case region of bits per set (every key at every level)
+    std::vector<uint32_t> order(nsets);
+    for (uint64_t i = 0; i < nsets; ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) {
+        return off[a + 1] - off[a] > off[c + 1] - off[c];
+    });
+    std::vector<uint64_t> region_bit(nsets);
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < nsets; ++i) {
+        region_bit[i] = acc;
+        const uint64_t n = off[i + 1] - off[i];
+        acc += n ? (uint64_t)o.max_levels * 64 * ((level_size(gamma, n) + 63) / 64) : 0;
+    }
+    uint32_t* d_order = nullptr;
+    uint64_t *d_rb = nullptr, *scratch = nullptr, *region = nullptr, *left_sorted = nullptr, *pre = nullptr,
+             *lpre = nullptr, *tiles = nullptr;
+    unsigned long long* next = nullptr;
+    uint32_t *bits32 = nullptr, *left32 = nullptr;
+    if ((st = ar.alloc(&d_order, nsets, "order")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&d_rb, nsets, "regions")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&scratch, total + 1, "scratch")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&region, acc / 64 + 1, "unpacked bits")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&left_sorted, total + 1, "leftovers")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&next, 1, "queue")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&bits32, nsets + 1, "bits")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&left32, nsets + 1, "leftover counts")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&pre, nsets + 1, "bit prefix")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&lpre, nsets + 1, "leftover prefix")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&tiles, scan_tmp_tiles(nsets + 1), "scan tiles")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&b->sets, nsets, "sets")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&b->levels, nsets * o.max_levels, "set levels")) != MPHF_OK) return st;
+    HIP_TRY(hipMemcpyAsync(d_order, order.data(), nsets * 4, hipMemcpyHostToDevice, s), "copy order");
+    HIP_TRY(hipMemcpyAsync(d_rb, region_bit.data(), nsets * 8, hipMemcpyHostToDevice, s), "copy regions");
+    HIP_TRY(launch_zero((uint64_t*)next, 1, s), "zero queue");
+    HIP_TRY(launch_zero((uint64_t*)b->sets, nsets * sizeof(BatchSet) / 8, s), "zero sets");
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
+    const uint64_t lds = batch_lds_bytes(max_m, BATCH_LEFT_CAP);
+    const uint32_t per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 150000 / (lds + 512)));
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(nsets, (uint64_t)cus * per_cu);
+    HIP_TRY(launch_batch_build(keys, offsets, d_order, nsets, next, scratch, d_rb, gamma, b->seeds,
+                               o.max_levels, BATCH_LEFT_CAP, region, b->sets, b->levels, left_sorted, bits32,
+                               max_m, grid, s),
+            "batch build");
+    // statuses, bit counts and leftover counts
+    HIP_TRY(launch_u32_from_sets(b->sets, nsets, 1, left32, s), "leftover counts");
+    HIP_TRY(launch_zero32(bits32 + nsets, 1, s), "zero tail");
+    HIP_TRY(launch_exclusive_scan(bits32, pre, nsets + 1, tiles, s), "bit prefix");
+    HIP_TRY(launch_exclusive_scan(left32, lpre, nsets + 1, tiles, s), "leftover prefix");
+    std::vector<BatchSet> hs(nsets);
+    HIP_TRY(hipMemcpyAsync(hs.data(), b->sets, nsets * sizeof(BatchSet), hipMemcpyDeviceToHost, s), "copy sets");
+    uint64_t tb = 0, tl = 0;
+    HIP_TRY(hipMemcpyAsync(&tb, pre + nsets, 8, hipMemcpyDeviceToHost, s), "copy total");
+    HIP_TRY(hipMemcpyAsync(&tl, lpre + nsets, 8, hipMemcpyDeviceToHost, s), "copy total");
+    HIP_TRY(hipStreamSynchronize(s), "batch sync");
+    for (uint64_t i = 0; i < nsets; ++i) {
+        if (hs[i].status & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(i));
+        if (hs[i].status & 2u)
+            return fail(MPHF_E_INVALID, "set " + std::to_string(i) +
+                                            " keeps more than 2048 keys after its last level (duplicates, or too few levels)");
+    }
+    b->total_bits = tb;
+    b->nleft = tl;
+    if ((st = ar.alloc(&b->words, tb / 64 + 1, "A")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&b->left, tl + 1, "fallback keys")) != MPHF_OK) return st;
+    HIP_TRY(launch_batch_pack(region, d_rb, b->sets, nsets, pre, lpre, left_sorted, offsets, b->words, b->left, s),
+            "pack");
+    // rank table (Section 3.1) and the lookup sectors over the packed bits
+    b->nrank = (tb + 511) / 512;
+    if (b->nrank) {
+        uint32_t* rc = nullptr;
+        uint64_t* rt = nullptr;
+        if ((st = ar.alloc(&b->rank, b->nrank, "rank")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&rc, b->nrank, "rank counts")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&rt, scan_tmp_tiles(b->nrank), "rank tiles")) != MPHF_OK) return st;
+        HIP_TRY(launch_rank(b->words, tb / 64, 512, b->rank, b->nrank, rc, rt, s), "rank");
+        HIP_TRY(launch_batch_ones_before(b->sets, b->words, b->rank, 9, nsets, s), "ones before");
+        b->nsec = sector_count(tb);
+        uint32_t* cnt = nullptr;
+        uint64_t *spre = nullptr, *stiles = nullptr;
+        if ((st = ar.alloc(&b->sec, b->nsec * 16, "lookup sectors")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&b->super, super_count(b->nsec), "lookup superblocks")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&cnt, b->nsec, "sector counts")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&spre, b->nsec, "sector prefix")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&stiles, scan_tmp_tiles(b->nsec), "sector tiles")) != MPHF_OK) return st;
+        HIP_TRY(launch_sectors(b->words, tb, b->sec, b->super, cnt, spre, stiles, s), "sectors");
+    }
+    HIP_TRY(hipStreamSynchronize(s), "batch final sync");
+    void* keep[] = {b->sets, b->levels, b->words, b->rank, b->sec, b->super, b->left};
+    for (void* p : keep) ar.keep(p);
+    guard.b = nullptr;
+    *out = b;
+    return MPHF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mphf_status mphf_build_batch(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
+                             uint64_t seed, const mphf_opts* opts, void* stream, mphf_batch_t** out) {
+    if (!out) return fail(MPHF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    mphf_opts o;
+    if (opts) o = *opts;
+    else mphf_default_opts(&o);
+    return build_batch_impl(keys, offsets, nsets, gamma, seed, o, (hipStream_t)stream, out);
+}
+
+mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, const uint64_t* keys,
+                              uint64_t n, uint64_t* out, void* stream) {
+    if (!b) return fail(MPHF_E_INVALID, "handle is NULL");
+    if (!n) return MPHF_OK;
+    if (!set_ids || !keys || !out || !is_device_ptr(set_ids) || !is_device_ptr(keys) || !is_device_ptr(out))
+        return fail(MPHF_E_INVALID, "set_ids, keys and out must be device memory");
+    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->sets, b->levels, b->D, b->nsets, b->sec, b->super,
+                                b->left, b->seeds, (hipStream_t)stream),
+            "batch lookup");
+    return MPHF_OK;
+}
+
+mphf_status mphf_batch_set_info(const mphf_batch_t* b, uint64_t set, mphf_set_info_t* info) {
+    if (!b || !info) return fail(MPHF_E_INVALID, "NULL argument");
+    if (set >= b->nsets) return fail(MPHF_E_INVALID, "no such set");
+    BatchSet bs;
+    std::vector<BatchLevel> lv(b->D);
+    HIP_TRY(hipMemcpy(&bs, b->sets + set, sizeof(bs), hipMemcpyDeviceToHost), "copy set");
+    HIP_TRY(hipMemcpy(lv.data(), b->levels + set * b->D, sizeof(BatchLevel) * b->D, hipMemcpyDeviceToHost),
+            "copy levels");
+    std::memset(info, 0, sizeof(*info));
+    info->n = bs.n;
+    info->num_levels = bs.nlev;
+    info->n_fallback = bs.nleft;
+    info->total_bits = bs.bits;
+    for (uint32_t d = 0; d < bs.nlev; ++d) {
+        info->level_n[d] = lv[d].n;
+        info->level_m[d] = lv[d].m;
+        info->level_offset[d] = lv[d].off;
+    }
+    return MPHF_OK;
+}
+
+mphf_status mphf_batch_export_set(const mphf_batch_t* b, uint64_t set, uint64_t* words, uint64_t nwords,
+                                  uint64_t* fallback_keys, uint64_t nfb) {
+    if (!b) return fail(MPHF_E_INVALID, "handle is NULL");
+    if (set >= b->nsets) return fail(MPHF_E_INVALID, "no such set");
+    BatchSet bs;
+    HIP_TRY(hipMemcpy(&bs, b->sets + set, sizeof(bs), hipMemcpyDeviceToHost), "copy set");
+    if ((words && nwords != bs.bits / 64) || (fallback_keys && nfb != bs.nleft))
+        return fail(MPHF_E_INVALID, "export sizes differ from the set's");
+    if (words && nwords)
+        HIP_TRY(hipMemcpy(words, b->words + bs.start_bit / 64, nwords * 8, hipMemcpyDeviceToHost), "copy bits");
+    if (fallback_keys && nfb)
+        HIP_TRY(hipMemcpy(fallback_keys, b->left + bs.left_off, nfb * 8, hipMemcpyDeviceToHost), "copy fallback");
+    return MPHF_OK;
+}
+
+mphf_status mphf_batch_totals(const mphf_batch_t* b, uint64_t* nsets, uint64_t* nkeys, uint64_t* total_bits,
+                              double* bits_per_key) {
+    if (!b) return fail(MPHF_E_INVALID, "handle is NULL");
+    if (nsets) *nsets = b->nsets;
+    if (nkeys) *nkeys = b->nkeys;
+    if (total_bits) *total_bits = b->total_bits;
+    if (bits_per_key)
+        *bits_per_key = b->nkeys ? (double)(b->total_bits + 64 * b->nrank + 64 * b->nleft) / (double)b->nkeys : 0.0;
+    return MPHF_OK;
+}
+
+void mphf_batch_destroy(mphf_batch_t* b) { free_batch(b); }
+
+}  // extern "C"

@@ -51,6 +51,75 @@ __device__ __forceinline__ uint64_t level_pos(uint64_t key, const LevelHash& L) 
     return mod_invariant(fmix64(key ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
 }
 
+// Exact floor(a * 2^64 / m) for a < m < 2^63 by binary long division (one thread).
+__device__ inline uint64_t div_shift64(uint64_t a, uint64_t m) {
+    uint64_t q = 0, r = a;
+    for (int i = 0; i < 64; ++i) {
+        r <<= 1;
+        q <<= 1;
+        if (r >= m) {
+            r -= m;
+            q |= 1;
+        }
+    }
+    return q;
+}
+
+// Device-side twin of make_level_hash (Granlund-Montgomery Figure 4.1 constants).
+__device__ inline LevelHash device_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
+    LevelHash L;
+    L.seed = seed;
+    L.m = m;
+    L.bit_off = bit_off;
+    uint32_t l = 0;
+    while (l < 63 && (1ull << l) < m) ++l;
+    if ((1ull << l) < m) l = 64;
+    L.magic = (l < 64 ? div_shift64((1ull << l) - m, m) : 0) + 1;
+    L.sh1 = l < 1 ? l : 1;
+    L.sh2 = l > 1 ? l - 1 : 0;
+    return L;
+}
+
+// ---------------------------------------------------------------- lookup sectors
+//
+// The lookup reads A through a copy laid out in 64-byte sectors: u32 word 0 of sector s holds the
+// ones of A before bit 480*s counted from the start of its superblock of 2^21 sectors, u32 words
+// 1..15 hold bits [480*s, 480*s + 480) of A, and super[s >> 21] holds the ones before the
+// superblock.  A probe reads the aligned 64 bytes of one sector (four 16-byte loads).
+constexpr uint64_t SEC_BITS = 480;
+constexpr uint32_t SEC_WORDS = 16;
+constexpr uint32_t SUPER_SHIFT = 21;
+
+// If bit g of A is set: *rank = the ones of A before g, and true.
+__device__ __forceinline__ bool sector_rank(const uint32_t* __restrict__ sec,
+                                            const uint64_t* __restrict__ super, uint64_t g,
+                                            uint64_t* rank) {
+    const uint64_t j = g / SEC_BITS;
+    const uint32_t r = (uint32_t)(g - j * SEC_BITS);
+    const uint32_t t = 1 + (r >> 5), b = r & 31u;   // the bit's u32 word in the sector
+    const uint4* s4 = (const uint4*)(sec + j * SEC_WORDS);
+    uint4 v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = s4[c];
+    const uint32_t e[16] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
+                            v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
+    uint32_t w = 0;
+#pragma unroll
+    for (uint32_t k = 1; k < SEC_WORDS; ++k)
+        if (k == t) w = e[k];
+    if (!((w >> b) & 1u)) return false;
+    // superblock + sector counter + whole words before t + bits of t below g
+    uint64_t acc = super[j >> SUPER_SHIFT] + e[0];
+    const uint32_t mask = (1u << b) - 1u;
+#pragma unroll
+    for (uint32_t k = 1; k < SEC_WORDS; ++k) {
+        if (k < t) acc += __popc(e[k]);
+        else if (k == t) acc += __popc(e[k] & mask);
+    }
+    *rank = acc;
+    return true;
+}
+
 // ---------------------------------------------------------------- wave64 / block helpers
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }

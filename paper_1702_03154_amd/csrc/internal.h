@@ -34,6 +34,26 @@ struct TailSummary {
     uint64_t bit_end;     // bit offset after the last level built
 };
 
+// Batched builds: per set and per (set, level) records.
+struct BatchSet {
+    uint64_t n;            // keys of the set
+    uint64_t start_bit;    // first bit of the set in the packed A
+    uint64_t bits;         // bits of the set's levels (64-bit padded)
+    uint64_t ones_before;  // ones of the packed A before start_bit
+    uint64_t left_off;     // first of the set's fallback keys in the packed fallback array
+    uint32_t nlev;
+    uint32_t nleft;
+    uint32_t status;       // bit 0: duplicate keys; bit 1: too many leftovers for the batch kernel
+    uint32_t pad;
+};
+struct BatchLevel {
+    uint64_t m;
+    uint64_t magic;
+    uint64_t off;          // bit offset of the level inside the set
+    uint32_t n;            // keys of the set at this level
+    uint32_t sh;           // sh1 | sh2 << 8
+};
+
 // Bucket size of the partitioned levels: 2^pbits positions and room for kcap keys in LDS.
 struct BucketGeometry {
     uint32_t pbits;
@@ -91,5 +111,25 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);
 hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
                             hipStream_t s);
+
+hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
+                              uint64_t nsets, unsigned long long* next, uint64_t* scratch,
+                              const uint64_t* region_bit, double gamma, const SeedTable& seeds,
+                              uint32_t D, uint32_t left_cap, uint64_t* region, BatchSet* sets,
+                              BatchLevel* levels, uint64_t* left_sorted, uint32_t* bits32,
+                              uint64_t max_m, uint32_t grid, hipStream_t s);
+uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap);
+hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_bit, BatchSet* sets,
+                             uint64_t nsets, const uint64_t* bit_pre, const uint64_t* left_pre,
+                             const uint64_t* left_sorted, const uint64_t* offsets, uint64_t* words,
+                             uint64_t* left, hipStream_t s);
+hipError_t launch_batch_ones_before(BatchSet* sets, const uint64_t* words, const uint64_t* rank,
+                                    uint32_t rank_shift, uint64_t nsets, hipStream_t s);
+hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
+                               const BatchSet* sets, const BatchLevel* levels, uint32_t D, uint64_t nsets,
+                               const uint32_t* sec, const uint64_t* super, const uint64_t* left,
+                               const SeedTable& seeds, hipStream_t s);
+hipError_t launch_u32_from_sets(const BatchSet* sets, uint64_t nsets, int field, uint32_t* out,
+                                hipStream_t s);
 
 }  // namespace mphfk

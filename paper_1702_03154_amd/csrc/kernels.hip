@@ -269,18 +269,10 @@ __global__ void k_find_duplicates(const uint64_t* __restrict__ s, uint64_t n,
 
 // ---------------------------------------------------------------- lookup layout
 //
-// The lookup reads A through a copy laid out in 64-byte sectors.  A random read on gfx950 moves
-// one 128-byte line from HBM whatever its width, and the L1/L2 request rate caps how many 16-byte
-// pieces a lane may load per probe, so a probe should touch one small aligned unit that holds both
-// the probed bit and what its rank needs: u32 word 0 of sector s holds the ones of A before bit
-// 480*s, counted from the start of its superblock of 2^21 sectors; u32 words 1..15 hold bits
-// [480*s, 480*s + 480) of A.  super[s >> 21] holds the ones before the superblock.  The probe of a
-// level and, when its bit is set, the rank of that bit (Section 3.1's counters, here one 32-bit
-// counter per 480 positions plus the superblocks) come from one sector: four 16-byte loads.
-constexpr uint64_t SEC_BITS = 480;
-constexpr uint32_t SEC_WORDS = 16;
-constexpr uint32_t SUPER_SHIFT = 21;
-
+// A random read on gfx950 moves one 128-byte line from HBM whatever its width, and the L1/L2
+// request rate caps how many 16-byte pieces a lane may load per probe, so a probe should touch one
+// small aligned unit holding both the probed bit and what its rank needs: the 64-byte sectors of
+// device.h (Section 3.1's counters, here one 32-bit counter per 480 positions plus superblocks).
 __global__ void k_sector_counts(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec,
                                 uint32_t* __restrict__ counts) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -327,28 +319,8 @@ __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* _
         for (uint32_t d = 0; d < nlev; ++d) {
             const DevLevel L = lev[d];
             const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
-            const uint64_t j = g / SEC_BITS;
-            const uint32_t r = (uint32_t)(g - j * SEC_BITS);
-            const uint32_t t = 1 + (r >> 5), b = r & 31u;   // the bit's u32 word in the sector
-            const uint4* s4 = (const uint4*)(sec + j * SEC_WORDS);
-            uint4 v[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = s4[c];
-            const uint32_t e[16] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
-                                    v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
-            uint32_t w = 0;
-#pragma unroll
-            for (uint32_t k = 1; k < SEC_WORDS; ++k)
-                if (k == t) w = e[k];
-            if ((w >> b) & 1u) {
-                // ones before g = superblock + sector counter + whole words before t + bits of t below g
-                uint64_t rank = super[j >> SUPER_SHIFT] + e[0];
-                const uint32_t mask = (1u << b) - 1u;
-#pragma unroll
-                for (uint32_t k = 1; k < SEC_WORDS; ++k) {
-                    if (k < t) rank += __popc(e[k]);
-                    else if (k == t) rank += __popc(e[k] & mask);
-                }
+            uint64_t rank;
+            if (sector_rank(sec, super, g, &rank)) {
                 label = rank + 1;
                 found = true;
                 break;

@@ -37,35 +37,6 @@ constexpr int KT = 512;               // threads of the bucket kernel
 constexpr int POOL_WORDS = 19712;     // 154 KiB of LDS for the tail kernel's keys and bits
 constexpr int BUCKET_LDS = 49152;     // bytes of LDS for a bucket's local positions and bits
 
-// Exact floor(a * 2^64 / m) for a < m < 2^63 by binary long division (one thread).
-__device__ uint64_t div_shift64(uint64_t a, uint64_t m) {
-    uint64_t q = 0, r = a;
-    for (int i = 0; i < 64; ++i) {
-        r <<= 1;
-        q <<= 1;
-        if (r >= m) {
-            r -= m;
-            q |= 1;
-        }
-    }
-    return q;
-}
-
-// Device-side twin of make_level_hash (Granlund-Montgomery Figure 4.1 constants).
-__device__ LevelHash device_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
-    LevelHash L;
-    L.seed = seed;
-    L.m = m;
-    L.bit_off = bit_off;
-    uint32_t l = 0;
-    while (l < 63 && (1ull << l) < m) ++l;
-    if ((1ull << l) < m) l = 64;
-    L.magic = (l < 64 ? div_shift64((1ull << l) - m, m) : 0) + 1;
-    L.sh1 = l < 1 ? l : 1;
-    L.sh2 = l > 1 ? l - 1 : 0;
-    return L;
-}
-
 // The segment holding dense index i: the last s in [s0, s1) with pre[s] <= i.
 __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pre, uint32_t s0,
                                                  uint32_t s1, uint64_t i) {

@@ -8,6 +8,10 @@ arrays, no rank.  It only produces the workloads the paper measures on:
   SplitMix64 stream (Steele, Lea and Flood, OOPSLA 2014).  Output i of the
   stream is a bijective mix of ``seed + (i + 1) * golden``, so the first N
   outputs are distinct for any N below 2^64 and no de-duplication is needed;
+* many independent key sets of log-uniform sizes (the batched workload): the
+  size of set j is floor(lo * (hi/lo)^u_j) with u_j the top 53 bits of output
+  j of a SplitMix64 stream over 2^53, and set j holds the first size_j outputs
+  of the SplitMix64 stream seeded with output j of a second stream;
 * a seeded permutation of [0, N) for the shuffled query order: a 4-round
   balanced Feistel network on 2h bits (2^(2h) >= N) with cycle walking
   (Black and Rogaway, CT-RSA 2002), so it is a bijection of [0, N).
@@ -104,3 +108,39 @@ def shuffled_queries(k: torch.Tensor, seed: int = 2) -> torch.Tensor:
     """The keys of ``k`` in a seeded Feistel-shuffled order."""
     pi = feistel_permutation(k.numel(), seed, device=k.device)
     return k[pi]
+
+
+def log_uniform_sizes(nsets: int, lo: int = 16, hi: int = 65536, seed: int = 3) -> torch.Tensor:
+    """Set sizes floor(lo * (hi/lo)^u_j), u_j = (output j of SplitMix64(seed)) >> 11 over 2^53.
+
+    Computed on the CPU in float64 (int64 tensor); a size never exceeds ``hi``."""
+    z = splitmix64(seed, nsets)
+    u = _srl(z, 11).to(torch.float64) / float(1 << 53)
+    sizes = torch.floor(float(lo) * torch.pow(torch.tensor(float(hi) / float(lo), dtype=torch.float64), u))
+    return sizes.to(torch.int64).clamp_(max=hi)
+
+
+def set_offsets(sizes: torch.Tensor) -> torch.Tensor:
+    """Exclusive prefix of the set sizes, nsets + 1 entries, int64 on the sizes' device."""
+    off = torch.zeros(sizes.numel() + 1, dtype=torch.int64, device=sizes.device)
+    torch.cumsum(sizes, 0, out=off[1:])
+    return off
+
+
+def set_keys(sizes: torch.Tensor, seed: int = 4, device="cpu", chunk: int = 1 << 26) -> torch.Tensor:
+    """Concatenated keys of the sets: set j is the first sizes[j] outputs of SplitMix64 seeded
+    with output j of SplitMix64(seed), so each set's keys are distinct."""
+    sizes = sizes.to(device)
+    nsets = sizes.numel()
+    set_seeds = splitmix64(seed, nsets, device=device)
+    off = set_offsets(sizes)
+    total = int(off[-1])
+    out = torch.empty(total, dtype=torch.int64, device=device)
+    set_of = torch.repeat_interleave(torch.arange(nsets, device=device), sizes)
+    for lo in range(0, total, chunk):
+        hi = min(total, lo + chunk)
+        j = set_of[lo:hi]
+        i = torch.arange(lo, hi, dtype=torch.int64, device=device) - off[j]
+        z = (i + 1) * _s64(_GOLDEN) + set_seeds[j]
+        out[lo:hi] = _mix(z)
+    return out

@@ -48,6 +48,12 @@ class Stats(C.Structure):
                 ("bits_per_key", C.c_double), ("peak_bytes", C.c_uint64), ("lookup_bytes", C.c_uint64)]
 
 
+class SetInfo(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("num_levels", C.c_uint32), ("n_fallback", C.c_uint32),
+                ("level_n", _U64L), ("level_m", _U64L), ("level_offset", _U64L),
+                ("total_bits", C.c_uint64)]
+
+
 class View(C.Structure):
     _fields_ = [("words", C.c_void_p), ("rank", C.c_void_p), ("fallback_keys", C.c_void_p),
                 ("collisions", C.c_void_p), ("total_words", C.c_uint64), ("rank_entries", C.c_uint64),
@@ -78,6 +84,13 @@ def lib() -> C.CDLL:
             "mphf_export_collisions": (st, [vp, u32, vp, u64]),
             "mphf_positions": (st, [vp, u64, u64, u64, vp, vp]),
             "mphf_trim": (st, []),
+            "mphf_build_batch": (st, [vp, vp, u64, C.c_double, u64, C.POINTER(Opts), vp, C.POINTER(vp)]),
+            "mphf_batch_lookup": (st, [vp, vp, vp, u64, vp, vp]),
+            "mphf_batch_set_info": (st, [vp, u64, C.POINTER(SetInfo)]),
+            "mphf_batch_export_set": (st, [vp, u64, vp, u64, vp, u64]),
+            "mphf_batch_totals": (st, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                       C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
+            "mphf_batch_destroy": (None, [vp]),
             "mphf_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -199,6 +212,71 @@ class MPHF:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Many independent functions built in one launch (mphf_build_batch); owns its device memory."""
+
+    def __init__(self, handle: int, device: torch.device):
+        self._h = handle
+        self.device = device
+
+    @classmethod
+    def build(cls, keys: torch.Tensor, offsets: torch.Tensor, gamma: float = 2.0, seed: int = 0,
+              max_levels: int = 25, stream=None) -> "Batch":
+        L = lib()
+        o = Opts(max_levels, 512, 0, 0, 0)
+        h = C.c_void_p()
+        kp = _dev(keys, "keys") if keys.numel() else keys.data_ptr()
+        with torch.cuda.device(keys.device):
+            _check(L.mphf_build_batch(kp, _dev(offsets, "offsets"), offsets.numel() - 1, float(gamma),
+                                      seed & (2**64 - 1), C.byref(o), _stream(stream), C.byref(h)))
+        return cls(h.value, keys.device)
+
+    def lookup(self, set_ids: torch.Tensor, queries: torch.Tensor, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(queries.numel(), dtype=torch.int64, device=queries.device)
+        if queries.numel():
+            _check(lib().mphf_batch_lookup(self._h, _dev(set_ids, "set_ids"), _dev(queries, "queries"),
+                                           queries.numel(), _dev(out, "out"), _stream(stream)))
+        return out
+
+    def set_info(self, s: int) -> dict:
+        i = SetInfo()
+        _check(lib().mphf_batch_set_info(self._h, s, C.byref(i)))
+        L = i.num_levels
+        return {"n": i.n, "num_levels": L, "n_fallback": i.n_fallback,
+                "level_n": list(i.level_n[:L]), "level_m": list(i.level_m[:L]),
+                "level_offset": list(i.level_offset[:L]), "total_bits": i.total_bits}
+
+    def export_set(self, s: int) -> dict:
+        info = self.set_info(s)
+        w = np.zeros(info["total_bits"] // 64, dtype=np.uint64)
+        f = np.zeros(info["n_fallback"], dtype=np.uint64)
+        _check(lib().mphf_batch_export_set(self._h, s, w.ctypes.data, len(w), f.ctypes.data, len(f)))
+        return {"words": w, "fallback_keys": f}
+
+    def totals(self) -> dict:
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        d = C.c_double()
+        _check(lib().mphf_batch_totals(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"nsets": a.value, "nkeys": b.value, "total_bits": c.value, "bits_per_key": d.value}
+
+    def close(self):
+        if self._h:
+            lib().mphf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_batch(keys: torch.Tensor, offsets: torch.Tensor, gamma: float = 2.0, seed: int = 0, **kw) -> Batch:
+    return Batch.build(keys, offsets, gamma, seed, **kw)
 
 
 def build(keys: torch.Tensor, gamma: float = 2.0, seed: int = 0, **kw) -> MPHF:

@@ -1,0 +1,180 @@
+"""GPU parity of the batched build: every set of a batch against the oracle built on that set
+alone, bit for bit (level sizes and offsets, the set's A words, its fallback keys, every label),
+and against a standalone build of the same set through the plain entry point.
+
+Sets are independent functions (Section 2: the levels of a key set depend only on its keys,
+gamma and the level seeds), so a batch must reproduce each standalone result exactly."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mphf_oracle as O
+from paper_1702_03154_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_03154_amd import mphf
+    mphf.lib()
+    return mphf
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make_sets(sizes, seed=4):
+    sizes = torch.as_tensor(sizes, dtype=torch.int64)
+    return sizes, I.set_keys(sizes, seed), I.set_offsets(sizes)
+
+
+def check_set(b, s, ks, gamma, seed, max_levels, labels):
+    st = O.build(ks, gamma, seed, max_levels=max_levels)
+    info = b.set_info(s)
+    assert info["n"] == len(ks)
+    assert info["num_levels"] == st.num_levels, s
+    assert info["level_n"] == [l.n for l in st.levels], s
+    assert info["level_m"] == [l.m for l in st.levels], s
+    assert info["level_offset"] == [l.offset for l in st.levels], s
+    assert info["total_bits"] == st.total_bits, s
+    assert info["n_fallback"] == len(st.fallback_keys), s
+    ex = b.export_set(s)
+    assert np.array_equal(ex["words"], st.words), s
+    assert np.array_equal(ex["fallback_keys"], st.fallback_keys), s
+    assert np.array_equal(labels, O.lookup(st, ks)), s
+    return st
+
+
+def check_batch(M, sizes, gamma, seed=0, max_levels=25, check=None, absent=True):
+    sizes, keys, off = make_sets(sizes)
+    nsets = sizes.numel()
+    b = M.build_batch(keys.cuda(), off.cuda(), gamma, seed, max_levels=max_levels)
+    set_ids = torch.repeat_interleave(torch.arange(nsets), sizes)
+    lab = host(b.lookup(set_ids.cuda(), keys.cuda()))
+    knp = keys.numpy().view(np.uint64)
+    offn = off.numpy()
+    sets = range(nsets) if check is None else check
+    for s in sets:
+        ks = knp[offn[s]:offn[s + 1]]
+        st = check_set(b, s, ks, gamma, seed, max_levels, lab[offn[s]:offn[s + 1]])
+        if absent and len(ks):
+            q = I.splitmix64(1000 + s, 300).numpy().view(np.uint64)
+            got = host(b.lookup(torch.full((300,), s, dtype=torch.int64).cuda(),
+                                torch.from_numpy(q.view(np.int64)).cuda()))
+            assert np.array_equal(got, O.lookup(st, q)), s
+    # every set's labels are a bijection onto [1, n_s]
+    g = off[set_ids].numpy() + lab.astype(np.int64) - 1
+    assert np.all(lab >= 1)
+    assert np.array_equal(np.sort(g), np.arange(int(off[-1])))
+    return b, keys, off
+
+
+def test_batch_small_mixed_sizes(M):
+    sizes = [0, 1, 2, 3, 16, 63, 64, 65, 100, 511, 512, 513, 1000, 4097, 20000, 0, 7, 65536]
+    check_batch(M, sizes, 2.0)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 1.5, 2.0, 3.7])
+def test_batch_log_uniform(M, gamma):
+    sizes = I.log_uniform_sizes(400, 16, 8192, seed=30 + int(gamma * 10))
+    check_batch(M, sizes, gamma, seed=0x1234)
+
+
+def test_batch_more_sets_than_workgroups(M):
+    # far more sets than the persistent grid: the work queue must hand every one out once
+    sizes = I.log_uniform_sizes(6000, 1, 64, seed=5)
+    check_batch(M, sizes, 2.0, seed=9, check=range(0, 6000, 37))
+
+
+@pytest.mark.parametrize("max_levels", [1, 2, 3])
+def test_batch_fallback_tables(M, max_levels):
+    # few levels leave keys for every set's fallback table (sorted, labels n - |L| + 1 ..)
+    sizes = [0, 1, 5, 50, 300, 1500, 2000, 999]
+    check_batch(M, sizes, 2.0, seed=7, max_levels=max_levels)
+
+
+def test_batch_largest_set_in_lds(M):
+    # ceil(gamma n) = 2^19 exactly: A and C take 128 KiB of LDS
+    check_batch(M, [1 << 18, 10, 1 << 17], 2.0, seed=11, absent=False)
+
+
+def test_batch_equals_standalone_builds(M):
+    sizes, keys, off = make_sets(I.log_uniform_sizes(64, 16, 65536, seed=12))
+    b = M.build_batch(keys.cuda(), off.cuda(), 2.0, 77)
+    for s in range(0, 64, 5):
+        ks = keys[int(off[s]):int(off[s + 1])].cuda()
+        h = M.build(ks, 2.0, 77)
+        st = h.stats()
+        info = b.set_info(s)
+        assert info["level_n"] == st["level_n"][:st["num_levels"]]
+        assert info["level_m"] == st["level_m"][:st["num_levels"]]
+        ex, exb = h.export(), b.export_set(s)
+        assert np.array_equal(ex["words"], exb["words"])
+        assert np.array_equal(ex["fallback_keys"], exb["fallback_keys"])
+        ids = torch.full((ks.numel(),), s, dtype=torch.int64, device="cuda")
+        assert torch.equal(b.lookup(ids, ks), h.lookup(ks))
+        h.close()
+
+
+def test_batch_equal_keys_across_sets(M):
+    # the same keys in two sets are two independent functions
+    k = I.keys(3000, 21)
+    keys = torch.cat([k, k[:1000], k])
+    off = torch.tensor([0, 3000, 4000, 7000], dtype=torch.int64)
+    b = M.build_batch(keys.cuda(), off.cuda(), 2.0, 3)
+    e0, e2 = b.export_set(0), b.export_set(2)
+    assert np.array_equal(e0["words"], e2["words"])
+    ids = torch.repeat_interleave(torch.arange(3), torch.tensor([3000, 1000, 3000])).cuda()
+    lab = host(b.lookup(ids, keys.cuda()))
+    assert np.array_equal(lab[:3000], lab[4000:])
+    st = O.build(k.numpy().view(np.uint64), 2.0, 3)
+    assert np.array_equal(lab[:3000], O.lookup(st, k.numpy().view(np.uint64)))
+
+
+def test_batch_set_id_out_of_range_gives_zero(M):
+    sizes, keys, off = make_sets([100, 200])
+    b = M.build_batch(keys.cuda(), off.cuda(), 2.0, 0)
+    ids = torch.tensor([2, 5, -1], dtype=torch.int64).cuda()
+    assert host(b.lookup(ids, keys[:3].cuda())).tolist() == [0, 0, 0]
+
+
+def test_batch_duplicate_keys_rejected(M):
+    k = I.keys(500, 5)
+    keys = torch.cat([I.keys(100, 6), k, k[10:11]])
+    off = torch.tensor([0, 100, 601], dtype=torch.int64)
+    with pytest.raises(M.DuplicateKeysError):
+        M.build_batch(keys.cuda(), off.cuda(), 2.0, 0)
+
+
+def test_batch_rejects_bad_arguments(M):
+    sizes, keys, off = make_sets([10, 20])
+    with pytest.raises(M.MphfError):   # offsets not non-decreasing
+        M.build_batch(keys.cuda(), torch.tensor([0, 20, 10], dtype=torch.int64).cuda(), 2.0, 0)
+    with pytest.raises(M.MphfError):   # offsets[0] != 0
+        M.build_batch(keys.cuda(), torch.tensor([1, 10, 30], dtype=torch.int64).cuda(), 2.0, 0)
+    with pytest.raises(M.MphfError):   # gamma < 1
+        M.build_batch(keys.cuda(), off.cuda(), 0.5, 0)
+    big = I.keys((1 << 18) + 1, 8)
+    with pytest.raises(M.MphfError):   # ceil(2 n) > 2^19
+        M.build_batch(big.cuda(), torch.tensor([0, big.numel()], dtype=torch.int64).cuda(), 2.0, 0)
+    many = I.keys(10000, 8)
+    with pytest.raises(M.MphfError):   # one level leaves far more than 2048 keys
+        M.build_batch(many.cuda(), torch.tensor([0, 10000], dtype=torch.int64).cuda(), 2.0, 0,
+                      max_levels=1)
+    with pytest.raises(ValueError):
+        M.build_batch(keys.cuda(), off, 2.0, 0)   # host offsets
+
+
+def test_batch_repeat_is_deterministic(M):
+    sizes, keys, off = make_sets(I.log_uniform_sizes(300, 16, 4096, seed=13))
+    kc, oc = keys.cuda(), off.cuda()
+    b1 = M.build_batch(kc, oc, 2.0, 5)
+    b2 = M.build_batch(kc, oc, 2.0, 5)
+    for s in range(0, 300, 17):
+        assert np.array_equal(b1.export_set(s)["words"], b2.export_set(s)["words"])
+    ids = torch.repeat_interleave(torch.arange(300), sizes).cuda()
+    assert torch.equal(b1.lookup(ids, kc), b2.lookup(ids, kc))
