@@ -25,7 +25,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 LINE_BYTES = 128               # a random read on gfx950 moves one 128-byte line from HBM (measured)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lookup_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_03154_amd", "csrc", "kernels.hip")
 
 
 def mean_probes(st) -> float:
@@ -42,11 +41,11 @@ def mean_probes(st) -> float:
 def measured_traffic(n_queries: int):
     """HBM bytes of one k_lookup launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel source and the same workload; else None."""
-    import hashlib
+    from paper_1702_03154_amd.profsum import source_digest
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = source_digest()
     except (OSError, ValueError):
         return None
     if t.get("source_sha256") != sha or t.get("queries") != n_queries:
@@ -72,6 +71,16 @@ def cpu_baseline(n: int, gamma: float):
     return {"value": n / (t2 - t0), "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} keys, gamma={gamma}: build + lookup of all keys (shuffled)",
             "build_keys_per_s": n / (t1 - t0), "lookup_queries_per_s": n / (t2 - t1)}
+
+
+def calibrate_copy():
+    """One plain 1 GiB device-to-device copy: a kernel of known traffic for scaling HBM counters."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def bench_batch(args):
@@ -187,6 +196,8 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported on this build "
               "(the sharded design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
     if args.workload == "batch":
         bench_batch(args)
         return
@@ -203,13 +214,6 @@ def main():
     out = torch.empty(n, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     print(f"# inputs ready: {n} keys", file=sys.stderr, flush=True)
-
-    if args.calibrate_copy:
-        src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     s = torch.cuda.current_stream()
     build_ms, lookup_ms, step_ms = [], [], []

@@ -154,6 +154,22 @@ struct Workspace {
 };
 Workspace g_ws[64];
 
+// The batched build's temporaries (slot 0: per-set queue and prefixes; slot 1: survivors, unpacked
+// bits and per-set counts), kept per device like the single build's workspace.
+struct BatchWorkspace {
+    std::mutex mu;
+    void* buf[2] = {nullptr, nullptr};
+    uint64_t cap[2] = {0, 0};
+    void release() {
+        for (int i = 0; i < 2; ++i) {
+            if (buf[i]) (void)hipFree(buf[i]);
+            buf[i] = nullptr;
+            cap[i] = 0;
+        }
+    }
+};
+BatchWorkspace g_bws[64];
+
 // Device memory of one build: every buffer is released when the builder goes out of scope
 // unless it was handed to the finished function.  Tracks the bytes held against mem_budget.
 class Arena {
@@ -874,10 +890,14 @@ mphf_status mphf_trim(void) {
     (void)hipGetDevice(&cur);
     for (int d = 0; d < 64; ++d) {
         std::lock_guard<std::mutex> g(g_ws[d].mu);
-        if (!g_ws[d].b.host && !g_ws[d].b.Z && !g_ws[d].b.X && !g_ws[d].b.Y[0] && !g_ws[d].b.tiles) continue;
+        std::lock_guard<std::mutex> gb(g_bws[d].mu);
+        if (!g_ws[d].b.host && !g_ws[d].b.Z && !g_ws[d].b.X && !g_ws[d].b.Y[0] && !g_ws[d].b.tiles &&
+            !g_bws[d].buf[0] && !g_bws[d].buf[1])
+            continue;
         if (hipSetDevice(d) != hipSuccess) continue;
         (void)hipDeviceSynchronize();
         g_ws[d].release();
+        g_bws[d].release();
     }
     (void)hipSetDevice(cur);
     return MPHF_OK;
@@ -895,8 +915,11 @@ struct mphf_batch {
     double gamma = 0;
     uint32_t D = 25;
     SeedTable seeds{};
+    void* mem[2] = {nullptr, nullptr};   // the two device allocations every pointer below lives in
     BatchSet* sets = nullptr;
     BatchLevel* levels = nullptr;
+    BatchHead* heads = nullptr;
+    BatchLev* lev = nullptr;
     uint64_t* words = nullptr;
     uint64_t* rank = nullptr;
     uint32_t* sec = nullptr;
@@ -909,8 +932,7 @@ namespace {
 void free_batch(mphf_batch* b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
-    void* bufs[] = {b->sets, b->levels, b->words, b->rank, b->sec, b->super, b->left};
-    for (void* p : bufs)
+    for (void* p : b->mem)
         if (p) (void)hipFreeAsync(p, nullptr);
     (void)hipStreamSynchronize(nullptr);
     delete b;
@@ -919,132 +941,254 @@ void free_batch(mphf_batch* b) {
 constexpr uint32_t BATCH_LEFT_CAP = 2048;
 constexpr uint64_t BATCH_MAX_M = 1ull << 19;   // A and C of the level in LDS: 128 KiB
 
+// A small pinned host buffer per thread and device for the batched build's read-backs.
+uint64_t* batch_pinned(int dev) {
+    thread_local uint64_t* buf[64] = {};
+    if (dev < 0 || dev >= 64) return nullptr;
+    if (!buf[dev] && hipHostMalloc((void**)&buf[dev], 256, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        buf[dev] = nullptr;
+    }
+    return buf[dev];
+}
+
+// Lays typed arrays out in one byte range, each 256-byte aligned.  With a null base it only
+// measures (the pointers it returns are then offsets and must not be used).
+struct Carver {
+    uint8_t* base;
+    uint64_t off = 0;
+    template <typename T>
+    T* take(uint64_t count) {
+        off = (off + 255) & ~uint64_t(255);
+        T* p = (T*)(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+// The batch temporaries: from the device's cached workspace when this build can take it, else
+// from the arena (always so with a memory budget, so that the budget counts them).
+class BatchTemps {
+  public:
+    BatchTemps(Arena& ar, int dev, bool cache) : ar_(ar) {
+        if (!cache || dev < 0 || dev >= 64) return;
+        std::unique_lock<std::mutex> lk(g_bws[dev].mu, std::try_to_lock);
+        if (!lk.owns_lock()) return;
+        lock_ = std::move(lk);
+        ws_ = &g_bws[dev];
+    }
+    mphf_status get(int slot, uint64_t bytes, uint8_t** p) {
+        if (!ws_) return ar_.alloc(p, bytes + 256, "batch temporaries");
+        if (ws_->cap[slot] < bytes) {
+            if (ws_->buf[slot]) {
+                HIP_TRY(hipDeviceSynchronize(), "workspace sync");
+                (void)hipFree(ws_->buf[slot]);
+                ws_->buf[slot] = nullptr;
+                ws_->cap[slot] = 0;
+            }
+            const uint64_t want = bytes + bytes / 8 + 4096;
+            const hipError_t e = hipMalloc(&ws_->buf[slot], want);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                ws_->buf[slot] = nullptr;
+                return hip_fail(e, "batch workspace");
+            }
+            ws_->cap[slot] = want;
+        }
+        *p = (uint8_t*)ws_->buf[slot];
+        return MPHF_OK;
+    }
+
+  private:
+    Arena& ar_;
+    BatchWorkspace* ws_ = nullptr;
+    std::unique_lock<std::mutex> lock_;
+};
+
 mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
                              uint64_t seed, const mphf_opts& o, hipStream_t s, mphf_batch** out) {
     if (!(gamma >= 1.0) || !std::isfinite(gamma)) return fail(MPHF_E_INVALID, "gamma must be a finite number >= 1");
     if (!nsets) return fail(MPHF_E_INVALID, "nsets must be positive");
+    if (nsets >= (1ull << 32)) return fail(MPHF_E_INVALID, "at most 2^32 - 1 sets");
     if (!offsets || !is_device_ptr(offsets)) return fail(MPHF_E_INVALID, "offsets must be device memory");
     mphf_status st = check_opts(o);
     if (st != MPHF_OK) return st;
     if (o.flags) return fail(MPHF_E_INVALID, "flags are not supported for batched builds");
     if (o.rank_sample != 512) return fail(MPHF_E_INVALID, "batched builds use rank_sample 512");
-    std::vector<uint64_t> off(nsets + 1);
-    HIP_TRY(hipMemcpy(off.data(), offsets, (nsets + 1) * 8, hipMemcpyDeviceToHost), "copy offsets");
-    if (off[0] != 0) return fail(MPHF_E_INVALID, "offsets[0] must be 0");
-    uint64_t max_n = 0;
-    for (uint64_t i = 0; i < nsets; ++i) {
-        if (off[i + 1] < off[i]) return fail(MPHF_E_INVALID, "offsets must be non-decreasing");
-        max_n = std::max(max_n, off[i + 1] - off[i]);
-    }
-    const uint64_t total = off[nsets];
-    if (total && (!keys || !is_device_ptr(keys))) return fail(MPHF_E_INVALID, "keys must be device memory");
-    const uint64_t max_m = level_size(gamma, max_n);
-    if (max_m > BATCH_MAX_M) return fail(MPHF_E_INVALID, "a set is too large for a batched build");
 
+    Trace tr(s);
     mphf_batch* b = new mphf_batch();
-    HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
-    configure_pool(b->device);
-    b->nsets = nsets;
-    b->nkeys = total;
-    b->gamma = gamma;
-    b->D = o.max_levels;
-    level_seeds(seed, o.max_levels, b->seeds.s);
-    Arena ar(o.mem_budget, s);
     struct Guard {   // on failure the arena frees the buffers; only the handle itself is deleted here
         mphf_batch* b;
         ~Guard() { delete b; }
     } guard{b};
+    HIP_TRY(hipGetDevice(&b->device), "hipGetDevice");
+    configure_pool(b->device);
+    uint64_t* pin = batch_pinned(b->device);
+    if (!pin) return fail(MPHF_E_NOMEM, "pinned read-back buffer");
+    b->nsets = nsets;
+    b->gamma = gamma;
+    b->D = o.max_levels;
+    level_seeds(seed, o.max_levels, b->seeds.s);
+    Arena ar(o.mem_budget, s);
+    BatchTemps temps(ar, b->device, o.mem_budget == 0);
+    const uint32_t ncls = batch_classes();
+    const uint64_t S1 = nsets + 1;
 
-    // largest sets first, and a worst-case region of bits per set (every key at every level)
-    std::vector<uint32_t> order(nsets);
-    for (uint64_t i = 0; i < nsets; ++i) order[i] = (uint32_t)i;
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) {
-        return off[a + 1] - off[a] > off[c + 1] - off[c];
-    });
-    std::vector<uint64_t> region_bit(nsets);
-    uint64_t acc = 0;
-    for (uint64_t i = 0; i < nsets; ++i) {
-        region_bit[i] = acc;
-        const uint64_t n = off[i + 1] - off[i];
-        acc += n ? (uint64_t)o.max_levels * 64 * ((level_size(gamma, n) + 63) / 64) : 0;
+    // 1. offsets checked, region sizes, size-ordered work queue (all on the device)
+    uint32_t *order, *bound, *hist, *fail32;
+    uint64_t *region_w, *tiles;
+    unsigned long long* info;   // [0] largest set, [1] offset flags, [2] queue head
+    auto lay1 = [&](Carver& c) {
+        order = c.take<uint32_t>(nsets);
+        bound = c.take<uint32_t>(S1);
+        region_w = c.take<uint64_t>(S1);
+        hist = c.take<uint32_t>(2 * ncls + 2);
+        info = c.take<unsigned long long>(4);
+        tiles = c.take<uint64_t>(scan_tmp_tiles(S1));
+    };
+    {
+        Carver m{nullptr};
+        lay1(m);
+        uint8_t* p = nullptr;
+        if ((st = temps.get(0, m.off, &p)) != MPHF_OK) return st;
+        Carver c{p};
+        lay1(c);
     }
-    uint32_t* d_order = nullptr;
-    uint64_t *d_rb = nullptr, *scratch = nullptr, *region = nullptr, *left_sorted = nullptr, *pre = nullptr,
-             *lpre = nullptr, *tiles = nullptr;
-    unsigned long long* next = nullptr;
-    uint32_t *bits32 = nullptr, *left32 = nullptr;
-    if ((st = ar.alloc(&d_order, nsets, "order")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&d_rb, nsets, "regions")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&scratch, total + 1, "scratch")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&region, acc / 64 + 1, "unpacked bits")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&left_sorted, total + 1, "leftovers")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&next, 1, "queue")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&bits32, nsets + 1, "bits")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&left32, nsets + 1, "leftover counts")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&pre, nsets + 1, "bit prefix")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&lpre, nsets + 1, "leftover prefix")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&tiles, scan_tmp_tiles(nsets + 1), "scan tiles")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&b->sets, nsets, "sets")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&b->levels, nsets * o.max_levels, "set levels")) != MPHF_OK) return st;
-    HIP_TRY(hipMemcpyAsync(d_order, order.data(), nsets * 4, hipMemcpyHostToDevice, s), "copy order");
-    HIP_TRY(hipMemcpyAsync(d_rb, region_bit.data(), nsets * 8, hipMemcpyHostToDevice, s), "copy regions");
-    HIP_TRY(launch_zero((uint64_t*)next, 1, s), "zero queue");
-    HIP_TRY(launch_zero((uint64_t*)b->sets, nsets * sizeof(BatchSet) / 8, s), "zero sets");
+    fail32 = hist + 2 * ncls;
+    HIP_TRY(launch_zero32(hist, 2 * ncls + 2, s), "zero classes");
+    HIP_TRY(launch_zero((uint64_t*)info, 4, s), "zero counters");
+    HIP_TRY(hipMemsetAsync(fail32 + 1, 0xFF, 4, s), "first-bad init");
+    HIP_TRY(launch_batch_prepare(offsets, nsets, gamma, o.max_levels, BATCH_MAX_M, bound, hist, info, s), "prepare");
+    HIP_TRY(launch_exclusive_scan(bound, region_w, S1, tiles, s), "region prefix");
+    HIP_TRY(launch_batch_order(offsets, nsets, hist, hist + ncls, order, s), "order");
+    HIP_TRY(hipMemcpyAsync(pin, info, 16, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 2, offsets + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 3, region_w + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipStreamSynchronize(s), "batch sync");
+    const uint64_t max_n = pin[0], flags = pin[1], total = pin[2], region_words = pin[3];
+    if (flags & 2) return fail(MPHF_E_INVALID, "offsets[0] must be 0");
+    if (flags & 1) return fail(MPHF_E_INVALID, "offsets must be non-decreasing");
+    if (flags & 4) return fail(MPHF_E_INVALID, "a set is too large for a batched build (ceil(gamma n) > 2^19)");
+    if (total && (!keys || !is_device_ptr(keys))) return fail(MPHF_E_INVALID, "keys must be device memory");
+    b->nkeys = total;
+    const uint64_t max_m = level_size(gamma, max_n);
+    tr.mark("batch prepare", (long)total);
+
+    // 2. every set's levels in one persistent launch; survivors and then the sorted fallback keys of
+    // set s stay in scratch[offsets[s] ..]
+    uint64_t *scratch, *region, *pre, *lpre, *levpre;
+    uint32_t *bits32, *left32, *lev32;
+    auto lay2 = [&](Carver& c) {
+        scratch = c.take<uint64_t>(total + 1);
+        region = c.take<uint64_t>(region_words + 1);
+        bits32 = c.take<uint32_t>(S1);
+        left32 = c.take<uint32_t>(S1);
+        lev32 = c.take<uint32_t>(S1);
+        pre = c.take<uint64_t>(S1);
+        lpre = c.take<uint64_t>(S1);
+        levpre = c.take<uint64_t>(S1);
+    };
+    {
+        Carver m{nullptr};
+        lay2(m);
+        uint8_t* p = nullptr;
+        if ((st = temps.get(1, m.off, &p)) != MPHF_OK) return st;
+        Carver c{p};
+        lay2(c);
+    }
+    {
+        Carver m{nullptr};
+        m.take<BatchSet>(nsets);
+        m.take<BatchLevel>(nsets * o.max_levels);
+        uint8_t* p = nullptr;
+        if ((st = ar.alloc(&p, m.off, "set records")) != MPHF_OK) return st;
+        b->mem[0] = p;
+        Carver c{p};
+        b->sets = c.take<BatchSet>(nsets);
+        b->levels = c.take<BatchLevel>(nsets * o.max_levels);
+    }
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
     const uint64_t lds = batch_lds_bytes(max_m, BATCH_LEFT_CAP);
-    const uint32_t per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 150000 / (lds + 512)));
+    const uint32_t per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 155000 / (lds + 1024)));
     const uint32_t grid = (uint32_t)std::min<uint64_t>(nsets, (uint64_t)cus * per_cu);
-    HIP_TRY(launch_batch_build(keys, offsets, d_order, nsets, next, scratch, d_rb, gamma, b->seeds,
-                               o.max_levels, BATCH_LEFT_CAP, region, b->sets, b->levels, left_sorted, bits32,
-                               max_m, grid, s),
+    tr.mark("batch alloc");
+    HIP_TRY(launch_batch_build(keys, offsets, order, nsets, info + 2, scratch, region_w, gamma, b->seeds,
+                               o.max_levels, BATCH_LEFT_CAP, region, b->sets, b->levels, bits32, max_m, grid, s),
             "batch build");
-    // statuses, bit counts and leftover counts
-    HIP_TRY(launch_u32_from_sets(b->sets, nsets, 1, left32, s), "leftover counts");
-    HIP_TRY(launch_zero32(bits32 + nsets, 1, s), "zero tail");
-    HIP_TRY(launch_exclusive_scan(bits32, pre, nsets + 1, tiles, s), "bit prefix");
-    HIP_TRY(launch_exclusive_scan(left32, lpre, nsets + 1, tiles, s), "leftover prefix");
-    std::vector<BatchSet> hs(nsets);
-    HIP_TRY(hipMemcpyAsync(hs.data(), b->sets, nsets * sizeof(BatchSet), hipMemcpyDeviceToHost, s), "copy sets");
-    uint64_t tb = 0, tl = 0;
-    HIP_TRY(hipMemcpyAsync(&tb, pre + nsets, 8, hipMemcpyDeviceToHost, s), "copy total");
-    HIP_TRY(hipMemcpyAsync(&tl, lpre + nsets, 8, hipMemcpyDeviceToHost, s), "copy total");
+    tr.mark("batch levels", (long)grid);
+    HIP_TRY(launch_batch_tally(b->sets, nsets, left32, lev32, bits32, fail32, s), "tally");
+    HIP_TRY(launch_exclusive_scan(bits32, pre, S1, tiles, s), "bit prefix");
+    HIP_TRY(launch_exclusive_scan(left32, lpre, S1, tiles, s), "leftover prefix");
+    HIP_TRY(launch_exclusive_scan(lev32, levpre, S1, tiles, s), "level prefix");
+    HIP_TRY(hipMemcpyAsync(pin + 4, fail32, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 5, pre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 6, lpre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 7, levpre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
     HIP_TRY(hipStreamSynchronize(s), "batch sync");
-    for (uint64_t i = 0; i < nsets; ++i) {
-        if (hs[i].status & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(i));
-        if (hs[i].status & 2u)
-            return fail(MPHF_E_INVALID, "set " + std::to_string(i) +
-                                            " keeps more than 2048 keys after its last level (duplicates, or too few levels)");
-    }
+    const uint32_t bad = (uint32_t)pin[4], first_bad = (uint32_t)(pin[4] >> 32);
+    if (bad & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(first_bad));
+    if (bad & 2u)
+        return fail(MPHF_E_INVALID, "set " + std::to_string(first_bad) +
+                                        " keeps more than 2048 keys after its last level (duplicates, or too few levels)");
+    const uint64_t tb = pin[5], tl = pin[6], tlev = pin[7];
     b->total_bits = tb;
     b->nleft = tl;
-    if ((st = ar.alloc(&b->words, tb / 64 + 1, "A")) != MPHF_OK) return st;
-    if ((st = ar.alloc(&b->left, tl + 1, "fallback keys")) != MPHF_OK) return st;
-    HIP_TRY(launch_batch_pack(region, d_rb, b->sets, nsets, pre, lpre, left_sorted, offsets, b->words, b->left, s),
-            "pack");
-    // rank table (Section 3.1) and the lookup sectors over the packed bits
     b->nrank = (tb + 511) / 512;
+    b->nsec = sector_count(tb);
+    tr.mark("batch tally", (long)tb);
+
+    // 3. packed A, fallback keys, rank table (Section 3.1), lookup records and sectors
+    {
+        Carver m{nullptr};
+        m.take<BatchHead>(nsets);
+        m.take<BatchLev>(tlev + 1);
+        m.take<uint64_t>(tb / 64 + 1);
+        m.take<uint64_t>(tl + 1);
+        m.take<uint64_t>(b->nrank + 1);
+        m.take<uint32_t>(b->nsec * 16 + 16);
+        m.take<uint64_t>(super_count(b->nsec));
+        uint8_t* p = nullptr;
+        if ((st = ar.alloc(&p, m.off, "batch structure")) != MPHF_OK) return st;
+        b->mem[1] = p;
+        Carver c{p};
+        b->heads = c.take<BatchHead>(nsets);
+        b->lev = c.take<BatchLev>(tlev + 1);
+        b->words = c.take<uint64_t>(tb / 64 + 1);
+        b->left = c.take<uint64_t>(tl + 1);
+        b->rank = c.take<uint64_t>(b->nrank + 1);
+        b->sec = c.take<uint32_t>(b->nsec * 16 + 16);
+        b->super = c.take<uint64_t>(super_count(b->nsec));
+    }
+    HIP_TRY(launch_batch_pack(region, region_w, b->sets, nsets, pre, lpre, scratch, offsets, b->words, b->left, s),
+            "pack");
     if (b->nrank) {
-        uint32_t* rc = nullptr;
-        uint64_t* rt = nullptr;
-        if ((st = ar.alloc(&b->rank, b->nrank, "rank")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&rc, b->nrank, "rank counts")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&rt, scan_tmp_tiles(b->nrank), "rank tiles")) != MPHF_OK) return st;
+        // temporaries of the rank and sector scans, in the survivors' space (dead after the pack)
+        uint32_t *rc, *cnt;
+        uint64_t *rt, *spre, *stiles;
+        auto lay3 = [&](Carver& c) {
+            rc = c.take<uint32_t>(b->nrank);
+            rt = c.take<uint64_t>(scan_tmp_tiles(b->nrank));
+            cnt = c.take<uint32_t>(b->nsec);
+            spre = c.take<uint64_t>(b->nsec);
+            stiles = c.take<uint64_t>(scan_tmp_tiles(b->nsec));
+        };
+        Carver m{nullptr};
+        lay3(m);
+        uint8_t* p = (uint8_t*)scratch;
+        if (m.off > (total + 1) * 8 && (st = ar.alloc(&p, m.off, "rank temporaries")) != MPHF_OK) return st;
+        Carver c{p};
+        lay3(c);
         HIP_TRY(launch_rank(b->words, tb / 64, 512, b->rank, b->nrank, rc, rt, s), "rank");
-        HIP_TRY(launch_batch_ones_before(b->sets, b->words, b->rank, 9, nsets, s), "ones before");
-        b->nsec = sector_count(tb);
-        uint32_t* cnt = nullptr;
-        uint64_t *spre = nullptr, *stiles = nullptr;
-        if ((st = ar.alloc(&b->sec, b->nsec * 16, "lookup sectors")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&b->super, super_count(b->nsec), "lookup superblocks")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&cnt, b->nsec, "sector counts")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&spre, b->nsec, "sector prefix")) != MPHF_OK) return st;
-        if ((st = ar.alloc(&stiles, scan_tmp_tiles(b->nsec), "sector tiles")) != MPHF_OK) return st;
         HIP_TRY(launch_sectors(b->words, tb, b->sec, b->super, cnt, spre, stiles, s), "sectors");
     }
+    HIP_TRY(launch_batch_heads(b->sets, b->levels, o.max_levels, b->words, b->rank, 9, levpre, nsets, b->heads,
+                               b->lev, s),
+            "heads");
     HIP_TRY(hipStreamSynchronize(s), "batch final sync");
-    void* keep[] = {b->sets, b->levels, b->words, b->rank, b->sec, b->super, b->left};
-    for (void* p : keep) ar.keep(p);
+    tr.mark("batch structure");
+    for (void* p : b->mem) ar.keep(p);
     guard.b = nullptr;
     *out = b;
     return MPHF_OK;
@@ -1070,8 +1214,8 @@ mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, co
     if (!n) return MPHF_OK;
     if (!set_ids || !keys || !out || !is_device_ptr(set_ids) || !is_device_ptr(keys) || !is_device_ptr(out))
         return fail(MPHF_E_INVALID, "set_ids, keys and out must be device memory");
-    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->sets, b->levels, b->D, b->nsets, b->sec, b->super,
-                                b->left, b->seeds, (hipStream_t)stream),
+    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->heads, b->lev, b->nsets, b->sec, b->super, b->left,
+                                b->seeds, (hipStream_t)stream),
             "batch lookup");
     return MPHF_OK;
 }

@@ -1,15 +1,16 @@
 // Batched construction: many independent key sets built in one persistent launch.
 //
-// Each workgroup takes sets from an atomic work queue (largest first) and builds every level of
-// its set by itself (Algorithms 1 and 2): the level's A and C bits live in LDS, the keys of the
-// level are streamed from global memory (the set's own keys at level 0, its survivors in a scratch
-// region after that, compacted in place), and the finalized A words go to the set's region of an
-// unpacked bit buffer whose size per set is the worst case (every key surviving every level).
-// A second kernel packs the sets' bits into one concatenated array; the rank table and the lookup
-// sectors are then built over it like for a single function.  Set s gets labels 1..n_s: the ones of
-// A before the key's bit minus the ones before the set's first bit, plus one.  Every set's levels,
-// bits and labels equal those of a standalone build of that set, since the levels depend only on
-// the set's keys, gamma and the level seeds.
+// A preparation pass checks the set offsets, sizes each set's worst-case region of bits (every key
+// surviving every level) and orders the sets by size class, largest first.  Each workgroup of the
+// build kernel then takes sets from an atomic work queue in that order and builds every level of
+// its set by itself (Algorithms 1 and 2): the level's A and C bits live in LDS, the keys of the level
+// are streamed from global memory (the set's own keys at level 0, its survivors in a scratch region
+// after that, compacted in place), and the finalized A words go to the set's region of an unpacked
+// bit buffer.  A second kernel packs the sets' bits into one concatenated array in set order; the rank
+// table and the lookup sectors are then built over it like for a single function.  Set s gets labels
+// 1..n_s: the ones of A before the key's bit minus the ones before the set's first bit, plus one.
+// Every set's levels, bits and labels equal those of a standalone build of that set, since the levels
+// depend only on the set's keys, gamma and the level seeds.
 #include <cmath>
 
 #include "internal.h"
@@ -18,22 +19,115 @@ namespace mphfk {
 
 namespace {
 
-constexpr int BW = 256;   // threads per set-building workgroup
+constexpr int BW = 256;             // threads per set-building workgroup
+constexpr int NWAVE = BW / 64;
+constexpr int FI = 8;               // keys per thread in flight in the level passes
+constexpr int NCLASS = 65;          // size classes: 0 for an empty set, else floor(log2 n) + 1
+constexpr int PT = 256;             // threads of the preparation kernels
 
-// One workgroup builds set s.
+__device__ __forceinline__ uint32_t size_class(uint64_t n) { return n ? 64u - (uint32_t)__clzll(n) : 0u; }
+
+// Lanes below this one whose bit is set in mask.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Per set: worst-case region words, size class histogram, offset checks and the largest set.
+// info[0]: largest n (atomicMax); info[1]: flags (1 offsets decrease, 2 offsets[0] != 0, 4 a set too
+// large for the LDS levels).
+__global__ void __launch_bounds__(PT)
+k_batch_prepare(const uint64_t* __restrict__ offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
+                uint32_t* __restrict__ bound, uint32_t* __restrict__ hist, unsigned long long* __restrict__ info) {
+    __shared__ uint32_t lh[NCLASS];
+    __shared__ unsigned long long smax;
+    __shared__ uint32_t sflags;
+    if (threadIdx.x < NCLASS) lh[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        smax = 0;
+        sflags = 0;
+    }
+    __syncthreads();
+    uint64_t my_max = 0;
+    uint32_t flags = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * PT;
+    for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s <= nsets; s += stride) {
+        if (s == nsets) {
+            bound[s] = 0;
+            continue;
+        }
+        const uint64_t a = offsets[s], b = offsets[s + 1];
+        if (s == 0 && a != 0) flags |= 2;
+        if (b < a) flags |= 1;
+        const uint64_t n = b >= a ? b - a : 0;
+        const double dm = ceil(gamma * (double)n);
+        uint32_t w = 0;
+        if (dm > (double)max_m) flags |= 4;
+        else if (n) w = D * (uint32_t)(((uint64_t)dm + 63) >> 6);
+        bound[s] = w;
+        my_max = n > my_max ? n : my_max;
+        atomicAdd(&lh[size_class(n)], 1u);
+    }
+    atomicMax(&smax, (unsigned long long)my_max);
+    if (flags) atomicOr(&sflags, flags);
+    __syncthreads();
+    if (threadIdx.x < NCLASS && lh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], lh[threadIdx.x]);
+    if (threadIdx.x == 0) {
+        atomicMax(&info[0], smax);
+        if (sflags) atomicOr(&info[1], (unsigned long long)sflags);
+    }
+}
+
+// The work queue: set indices in descending size class (any order within a class; the result does
+// not depend on the order in which sets are built, only the load balance does).
+__global__ void __launch_bounds__(PT)
+k_batch_order(const uint64_t* __restrict__ offsets, uint64_t nsets, const uint32_t* __restrict__ hist,
+              uint32_t* __restrict__ cursor, uint32_t* __restrict__ order) {
+    __shared__ uint32_t gbase[NCLASS], lcnt[NCLASS], lbase[NCLASS];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int c = NCLASS - 1; c >= 0; --c) {
+            gbase[c] = acc;
+            acc += hist[c];
+        }
+    }
+    const uint64_t chunks = (nsets + PT - 1) / PT;
+    for (uint64_t ch = blockIdx.x; ch < chunks; ch += gridDim.x) {
+        if (threadIdx.x < NCLASS) lcnt[threadIdx.x] = 0;
+        __syncthreads();
+        const uint64_t s = ch * PT + threadIdx.x;
+        uint32_t c = 0, r = 0;
+        if (s < nsets) {
+            const uint64_t a = offsets[s], b = offsets[s + 1];
+            c = size_class(b >= a ? b - a : 0);
+            r = atomicAdd(&lcnt[c], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < NCLASS && lcnt[threadIdx.x])
+            lbase[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], lcnt[threadIdx.x]);
+        __syncthreads();
+        if (s < nsets) order[gbase[c] + lbase[c] + r] = (uint32_t)s;
+        __syncthreads();
+    }
+}
+
+// One workgroup builds one set at a time.
 __global__ void __launch_bounds__(BW)
 k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ offsets,
               const uint32_t* __restrict__ order, uint64_t nsets, unsigned long long* next,
-              uint64_t* __restrict__ scratch, const uint64_t* __restrict__ region_bit, double gamma,
+              uint64_t* __restrict__ scratch, const uint64_t* __restrict__ region_w, double gamma,
               SeedTable seeds, uint32_t D, uint32_t left_cap, uint64_t* __restrict__ region,
-              BatchSet* __restrict__ sets, BatchLevel* __restrict__ levels,
-              uint64_t* __restrict__ left_sorted, uint32_t* __restrict__ bits32) {
+              BatchSet* __restrict__ sets, BatchLevel* __restrict__ levels, uint32_t* __restrict__ bits32) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[BW / 64 + 1];
+    __shared__ uint32_t wsum[NWAVE];
     __shared__ unsigned long long s_item;
+    __shared__ uint32_t s_status;
     __shared__ LevelHash s_L;
+    const uint32_t wave = threadIdx.x >> 6;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(next, 1ull);
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(next, 1ull);
+            s_status = 0;
+        }
         __syncthreads();
         const uint64_t item = s_item;
         __syncthreads();
@@ -43,7 +137,7 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
         uint64_t n = offsets[s + 1] - k0;
         const uint64_t* F = keys + k0;
         uint64_t* scr = scratch + k0;
-        uint64_t* A = region + region_bit[s] / 64;
+        uint64_t* A = region + region_w[s];
         uint64_t off = 0;
         uint32_t d = 0;
         while (n > 0 && d < D) {
@@ -55,11 +149,23 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
             for (uint32_t w = threadIdx.x; w < 2 * aw + 2; w += BW) lds[w] = 0;
             __syncthreads();
             const LevelHash L = s_L;
-            for (uint64_t i = threadIdx.x; i < n; i += BW) {
-                const uint32_t p = (uint32_t)level_pos(F[i], L);
-                const uint32_t bit = 1u << (p & 31);
-                const uint32_t old = atomicOr(&Ab[p >> 5], bit);
-                if (old & bit) atomicOr(&Cb[p >> 5], bit);
+            // fill: FI loads in flight per thread, then the LDS test-and-set of each
+            for (uint64_t c0 = 0; c0 < n; c0 += BW * FI) {
+                uint64_t kk[FI];
+#pragma unroll
+                for (int it = 0; it < FI; ++it) {
+                    const uint64_t i = c0 + it * BW + threadIdx.x;
+                    kk[it] = i < n ? F[i] : 0;
+                }
+#pragma unroll
+                for (int it = 0; it < FI; ++it) {
+                    if (c0 + it * BW + threadIdx.x < n) {
+                        const uint32_t p = (uint32_t)level_pos(kk[it], L);
+                        const uint32_t bit = 1u << (p & 31);
+                        const uint32_t old = atomicOr(&Ab[p >> 5], bit);
+                        if (old & bit) atomicOr(&Cb[p >> 5], bit);
+                    }
+                }
             }
             __syncthreads();
             const uint64_t words = (m + 63) >> 6;
@@ -71,28 +177,45 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
             __syncthreads();
             for (uint32_t w = threadIdx.x; w < aw; w += BW) Ab[w] &= ~Cb[w];
             __syncthreads();
-            // filter, compacted in place into the set's scratch region: each chunk is read into
-            // registers before any of its survivors is written, and survivors only move left
-            constexpr int FI = 8;
+            // filter, compacted in place into the set's scratch region in key order: a chunk is read
+            // into registers before any of its survivors is written, and survivors only move left
             uint64_t out = 0;
             for (uint64_t c0 = 0; c0 < n; c0 += BW * FI) {
                 uint64_t kk[FI];
-                uint32_t mask = 0;
+                uint32_t sv = 0;
 #pragma unroll
                 for (int it = 0; it < FI; ++it) {
                     const uint64_t i = c0 + it * BW + threadIdx.x;
-                    kk[it] = 0;
-                    if (i < n) {
-                        kk[it] = F[i];
-                        const uint32_t p = (uint32_t)level_pos(kk[it], L);
-                        if (!((Ab[p >> 5] >> (p & 31)) & 1u)) mask |= 1u << it;
-                    }
+                    kk[it] = i < n ? F[i] : 0;
                 }
-                uint32_t tot;
-                uint64_t o = out + block_exclusive_sum<BW>((uint32_t)__popc(mask), wsum, &tot);
+                uint32_t wc = 0;
 #pragma unroll
-                for (int it = 0; it < FI; ++it)
-                    if ((mask >> it) & 1u) scr[o++] = kk[it];
+                for (int it = 0; it < FI; ++it) {
+                    bool keep = false;
+                    if (c0 + it * BW + threadIdx.x < n) {
+                        const uint32_t p = (uint32_t)level_pos(kk[it], L);
+                        keep = !((Ab[p >> 5] >> (p & 31)) & 1u);
+                    }
+                    sv |= (uint32_t)keep << it;
+                    wc += (uint32_t)__popcll(__ballot(keep));
+                }
+                if (lane_id() == 0) wsum[wave] = wc;
+                __syncthreads();
+                uint64_t base = out;
+                uint32_t tot = 0;
+#pragma unroll
+                for (int w = 0; w < NWAVE; ++w) {
+                    const uint32_t v = wsum[w];
+                    if (w < (int)wave) base += v;
+                    tot += v;
+                }
+#pragma unroll
+                for (int it = 0; it < FI; ++it) {
+                    const bool keep = (sv >> it) & 1u;
+                    const uint64_t bal = __ballot(keep);
+                    if (keep) scr[base + lanes_below(bal)] = kk[it];
+                    base += (uint32_t)__popcll(bal);
+                }
                 out += tot;
                 __syncthreads();
             }
@@ -109,12 +232,10 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
             F = scr;
             ++d;
         }
-        // leftovers: sorted ascending by counting, in place of a general sort (there are almost
-        // never more than a few; above left_cap the set is reported for a standalone build)
-        uint32_t status = 0;
-        if (n > left_cap) {
-            status = 2;
-        } else if (n > 0) {
+        // leftovers: sorted ascending by counting, back into the front of the set's scratch region
+        // (there are almost never more than a few; above left_cap the set is reported and the batch
+        // fails)
+        if (n > 0 && n <= left_cap) {
             uint64_t* lk = (uint64_t*)lds;   // at most left_cap keys
             for (uint64_t i = threadIdx.x; i < n; i += BW) lk[i] = scr[i];
             __syncthreads();
@@ -127,25 +248,53 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
                     r += (y < x) || (y == x && j < i);
                     dup |= (y == x && j != i);
                 }
-                left_sorted[k0 + r] = x;
-                if (dup) atomicOr((unsigned int*)&sets[s].status, 1u);
+                scr[r] = x;
+                if (dup) atomicOr(&s_status, 1u);
             }
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            sets[s].n = offsets[s + 1] - k0;
-            sets[s].nlev = d;
-            sets[s].nleft = (uint32_t)n;
-            sets[s].bits = off;
+            BatchSet& st = sets[s];
+            st.n = offsets[s + 1] - k0;
+            st.start_bit = 0;
+            st.bits = off;
+            st.ones_before = 0;
+            st.left_off = 0;
+            st.nlev = d;
+            st.nleft = (uint32_t)n;
+            st.status = s_status | (n > left_cap ? 2u : 0u);
+            st.pad = 0;
             bits32[s] = (uint32_t)off;
-            if (status) atomicOr((unsigned int*)&sets[s].status, status);
         }
         __syncthreads();
     }
 }
 
+// Per set: leftover count and count of levels past the second (inputs of two prefix scans), and the
+// OR of the statuses with the first failing set.  fail[0]: OR of statuses; fail[1]: first bad set.
+__global__ void __launch_bounds__(PT)
+k_batch_tally(const BatchSet* __restrict__ sets, uint64_t nsets, uint32_t* __restrict__ left32,
+              uint32_t* __restrict__ lev32, uint32_t* __restrict__ bits32, uint32_t* __restrict__ fail) {
+    const uint64_t stride = (uint64_t)gridDim.x * PT;
+    for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s <= nsets; s += stride) {
+        if (s == nsets) {
+            left32[s] = 0;
+            lev32[s] = 0;
+            bits32[s] = 0;
+            continue;
+        }
+        const BatchSet st = sets[s];
+        left32[s] = st.nleft;
+        lev32[s] = st.nlev > 2 ? st.nlev - 2 : 0;
+        if (st.status) {
+            atomicOr(&fail[0], st.status);
+            atomicMin(&fail[1], (uint32_t)s);
+        }
+    }
+}
+
 // Packs every set's bits and fallback keys at their packed offsets; one workgroup per set.
-__global__ void k_batch_pack(const uint64_t* __restrict__ region, const uint64_t* __restrict__ region_bit,
+__global__ void k_batch_pack(const uint64_t* __restrict__ region, const uint64_t* __restrict__ region_w,
                              BatchSet* __restrict__ sets, const uint64_t* __restrict__ bit_pre,
                              const uint64_t* __restrict__ left_pre, const uint64_t* __restrict__ left_sorted,
                              const uint64_t* __restrict__ offsets, uint64_t* __restrict__ words,
@@ -153,7 +302,7 @@ __global__ void k_batch_pack(const uint64_t* __restrict__ region, const uint64_t
     const uint64_t s = blockIdx.x;
     const uint64_t start = bit_pre[s];
     const uint64_t nw = sets[s].bits / 64;
-    const uint64_t* src = region + region_bit[s] / 64;
+    const uint64_t* src = region + region_w[s];
     uint64_t* dst = words + start / 64;
     for (uint64_t j = threadIdx.x; j < nw; j += blockDim.x) dst[j] = src[j];
     const uint32_t nl = sets[s].nleft;
@@ -164,78 +313,133 @@ __global__ void k_batch_pack(const uint64_t* __restrict__ region, const uint64_t
     }
 }
 
-// u32 copy of one field of every set (0: bits, 1: nleft), the input of a prefix scan.
-__global__ void k_u32_from_sets(const BatchSet* __restrict__ sets, uint64_t nsets, int field,
-                                uint32_t* __restrict__ out) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s <= nsets; s += stride)
-        out[s] = s < nsets ? (field == 0 ? (uint32_t)sets[s].bits : sets[s].nleft) : 0u;
-}
-
-__global__ void k_batch_ones_before(BatchSet* __restrict__ sets, const uint64_t* __restrict__ words,
-                                    const uint64_t* __restrict__ rank, uint32_t rank_shift, uint64_t nsets) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nsets; s += stride) {
-        const uint64_t g = sets[s].start_bit;   // a multiple of 64
-        const uint64_t b = g >> rank_shift;
-        uint64_t r = sets[s].bits ? rank[b] : 0;
-        if (sets[s].bits)
+// Per set: the ones of A before the set (from the rank table, sampled every 2^rank_shift bits) and
+// the lookup records: the 64-byte head with levels 0 and 1, then levels 2.. in the compact array.
+__global__ void __launch_bounds__(PT)
+k_batch_heads(BatchSet* __restrict__ sets, const BatchLevel* __restrict__ levels, uint32_t D,
+              const uint64_t* __restrict__ words, const uint64_t* __restrict__ rank, uint32_t rank_shift,
+              const uint64_t* __restrict__ lev_pre, uint64_t nsets, BatchHead* __restrict__ heads,
+              BatchLev* __restrict__ lev) {
+    const uint64_t stride = (uint64_t)gridDim.x * PT;
+    for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s < nsets; s += stride) {
+        const BatchSet st = sets[s];
+        uint64_t r = 0;
+        if (st.bits) {
+            const uint64_t g = st.start_bit;   // a multiple of 64
+            const uint64_t b = g >> rank_shift;
+            r = rank[b];
             for (uint64_t k = (b << rank_shift) >> 6; k < (g >> 6); ++k) r += __popcll(words[k]);
-        if (!sets[s].bits) {
-            // an empty set has no bits; the value is never used
-            r = 0;
         }
         sets[s].ones_before = r;
+        BatchHead h;
+        h.start_bit = st.start_bit;
+        h.ones_before = r;
+        h.left_off = st.left_off;
+        h.n = (uint32_t)st.n;
+        h.nleft = (uint16_t)st.nleft;
+        h.nlev = (uint8_t)st.nlev;
+        h.pad = 0;
+        const BatchLevel* L = levels + s * D;
+        h.m0 = st.nlev > 0 ? (uint32_t)L[0].m : 0;
+        h.m1 = st.nlev > 1 ? (uint32_t)L[1].m : 0;
+        h.magic0 = st.nlev > 0 ? L[0].magic : 0;
+        h.magic1 = st.nlev > 1 ? L[1].magic : 0;
+        h.lev_idx = (uint32_t)lev_pre[s];
+        h.pad2 = 0;
+        heads[s] = h;
+        for (uint32_t d = 2; d < st.nlev; ++d) {
+            BatchLev e;
+            e.m = (uint32_t)L[d].m;
+            e.off = (uint32_t)L[d].off;
+            e.magic = L[d].magic;
+            lev[lev_pre[s] + d - 2] = e;
+        }
     }
 }
 
 // Lookup of (set, key) pairs: Algorithm 3 within the set, ranks through the sector layout.
-__global__ void k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict__ q, uint64_t n,
-                               uint64_t* __restrict__ out, const BatchSet* __restrict__ sets,
-                               const BatchLevel* __restrict__ levels, uint32_t D, uint64_t nsets,
-                               const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
-                               const uint64_t* __restrict__ left, SeedTable seeds) {
+__global__ void __launch_bounds__(256)
+k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict__ q, uint64_t n,
+               uint64_t* __restrict__ out, const BatchHead* __restrict__ heads, const BatchLev* __restrict__ lev,
+               uint64_t nsets, const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
+               const uint64_t* __restrict__ left, SeedTable seeds) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t s = set_ids[i];
         const uint64_t x = q[i];
         uint64_t label = 0;
         if (s < nsets) {
-            const BatchSet st = sets[s];
+            const BatchHead h = heads[s];
             bool found = false;
-            for (uint32_t d = 0; d < st.nlev; ++d) {
-                const BatchLevel bl = levels[s * D + d];
-                const uint64_t pos = mod_invariant(fmix64(x ^ seeds.s[d]), bl.m, bl.magic, bl.sh & 255u, bl.sh >> 8);
-                const uint64_t g = st.start_bit + bl.off + pos;
+            for (uint32_t d = 0; d < h.nlev; ++d) {
+                uint32_t m, off;
+                uint64_t magic;
+                if (d == 0) {
+                    m = h.m0;
+                    magic = h.magic0;
+                    off = 0;
+                } else if (d == 1) {
+                    m = h.m1;
+                    magic = h.magic1;
+                    off = (h.m0 + 63u) & ~63u;
+                } else {
+                    const BatchLev e = lev[h.lev_idx + d - 2];
+                    m = e.m;
+                    magic = e.magic;
+                    off = e.off;
+                }
+                const uint32_t l = 32u - (uint32_t)__clz(m - 1u);   // ceil(log2 m); 0 for m = 1
+                const uint64_t pos =
+                    mod_invariant(fmix64(x ^ seeds.s[d]), m, magic, l < 1 ? l : 1, l > 1 ? l - 1 : 0);
                 uint64_t rank;
-                if (sector_rank(sec, super, g, &rank)) {
-                    label = rank - st.ones_before + 1;
+                if (sector_rank(sec, super, h.start_bit + off + pos, &rank)) {
+                    label = rank - h.ones_before + 1;
                     found = true;
                     break;
                 }
             }
-            if (!found && st.nleft) {
-                const uint64_t* L = left + st.left_off;
-                uint64_t lo = 0, hi = st.nleft;
+            if (!found && h.nleft) {
+                const uint64_t* L = left + h.left_off;
+                uint32_t lo = 0, hi = h.nleft;
                 while (lo < hi) {
-                    const uint64_t mid = (lo + hi) >> 1;
+                    const uint32_t mid = (lo + hi) >> 1;
                     if (L[mid] < x) lo = mid + 1; else hi = mid;
                 }
-                if (lo < st.nleft && L[lo] == x) label = st.n - st.nleft + 1 + lo;
+                if (lo < h.nleft && L[lo] == x) label = h.n - h.nleft + 1 + lo;
             }
         }
         out[i] = label;
     }
 }
 
+uint32_t prep_grid(uint64_t items) {
+    const uint64_t g = (items + PT - 1) / PT;
+    return (uint32_t)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
+
 }  // namespace
+
+uint32_t batch_classes() { return NCLASS; }
+
+hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
+                                uint32_t* bound, uint32_t* hist, unsigned long long* info, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_prepare, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, offsets, nsets, gamma, D,
+                       max_m, bound, hist, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_order(const uint64_t* offsets, uint64_t nsets, const uint32_t* hist, uint32_t* cursor,
+                              uint32_t* order, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_order, dim3(prep_grid(nsets)), dim3(PT), 0, s, offsets, nsets, hist, cursor, order);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
                               uint64_t nsets, unsigned long long* next, uint64_t* scratch,
-                              const uint64_t* region_bit, double gamma, const SeedTable& seeds,
+                              const uint64_t* region_w, double gamma, const SeedTable& seeds,
                               uint32_t D, uint32_t left_cap, uint64_t* region, BatchSet* sets,
-                              BatchLevel* levels, uint64_t* left_sorted, uint32_t* bits32,
-                              uint64_t max_m, uint32_t grid, hipStream_t s) {
+                              BatchLevel* levels, uint32_t* bits32, uint64_t max_m, uint32_t grid,
+                              hipStream_t s) {
     const uint64_t lds = batch_lds_bytes(max_m, left_cap);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute((const void*)k_batch_build,
@@ -243,8 +447,7 @@ hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, con
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_batch_build, dim3(grid), dim3(BW), (unsigned)lds, s, keys, offsets, order, nsets,
-                       next, scratch, region_bit, gamma, seeds, D, left_cap, region, sets, levels,
-                       left_sorted, bits32);
+                       next, scratch, region_w, gamma, seeds, D, left_cap, region, sets, levels, bits32);
     return hipGetLastError();
 }
 
@@ -255,40 +458,41 @@ uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap) {
     return lds;
 }
 
-hipError_t launch_u32_from_sets(const BatchSet* sets, uint64_t nsets, int field, uint32_t* out,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_u32_from_sets, dim3((unsigned)((nsets + 256) / 256)), dim3(256), 0, s, sets, nsets,
-                       field, out);
+hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* lev32,
+                              uint32_t* bits32, uint32_t* fail, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_tally, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, sets, nsets, left32, lev32,
+                       bits32, fail);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_bit, BatchSet* sets,
+hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_w, BatchSet* sets,
                              uint64_t nsets, const uint64_t* bit_pre, const uint64_t* left_pre,
                              const uint64_t* left_sorted, const uint64_t* offsets, uint64_t* words,
                              uint64_t* left, hipStream_t s) {
     if (!nsets) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_pack, dim3((unsigned)nsets), dim3(256), 0, s, region, region_bit, sets, bit_pre,
+    hipLaunchKernelGGL(k_batch_pack, dim3((unsigned)nsets), dim3(256), 0, s, region, region_w, sets, bit_pre,
                        left_pre, left_sorted, offsets, words, left);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_ones_before(BatchSet* sets, const uint64_t* words, const uint64_t* rank,
-                                    uint32_t rank_shift, uint64_t nsets, hipStream_t s) {
+hipError_t launch_batch_heads(BatchSet* sets, const BatchLevel* levels, uint32_t D, const uint64_t* words,
+                              const uint64_t* rank, uint32_t rank_shift, const uint64_t* lev_pre, uint64_t nsets,
+                              BatchHead* heads, BatchLev* lev, hipStream_t s) {
     if (!nsets) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_ones_before, dim3((unsigned)((nsets + 255) / 256)), dim3(256), 0, s, sets,
-                       words, rank, rank_shift, nsets);
+    hipLaunchKernelGGL(k_batch_heads, dim3(prep_grid(nsets)), dim3(PT), 0, s, sets, levels, D, words, rank,
+                       rank_shift, lev_pre, nsets, heads, lev);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
-                               const BatchSet* sets, const BatchLevel* levels, uint32_t D, uint64_t nsets,
-                               const uint32_t* sec, const uint64_t* super, const uint64_t* left,
-                               const SeedTable& seeds, hipStream_t s) {
+                               const BatchHead* heads, const BatchLev* lev, uint64_t nsets, const uint32_t* sec,
+                               const uint64_t* super, const uint64_t* left, const SeedTable& seeds,
+                               hipStream_t s) {
     if (!n) return hipSuccess;
     uint64_t blocks = (n + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_batch_lookup, dim3((unsigned)blocks), dim3(256), 0, s, set_ids, q, n, out, sets,
-                       levels, D, nsets, sec, super, left, seeds);
+    hipLaunchKernelGGL(k_batch_lookup, dim3((unsigned)blocks), dim3(256), 0, s, set_ids, q, n, out, heads, lev,
+                       nsets, sec, super, left, seeds);
     return hipGetLastError();
 }
 

@@ -53,6 +53,12 @@ __device__ __forceinline__ uint64_t level_pos(uint64_t key, const LevelHash& L) 
 
 // Exact floor(a * 2^64 / m) for a < m < 2^63 by binary long division (one thread).
 __device__ inline uint64_t div_shift64(uint64_t a, uint64_t m) {
+    if ((m >> 32) == 0) {   // two base-2^32 digits of the long division, each a 64-bit quotient
+        const uint64_t t1 = a << 32;
+        const uint64_t q1 = t1 / m;
+        const uint64_t t2 = (t1 - q1 * m) << 32;
+        return (q1 << 32) | (t2 / m);
+    }
     uint64_t q = 0, r = a;
     for (int i = 0; i < 64; ++i) {
         r <<= 1;

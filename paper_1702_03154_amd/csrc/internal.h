@@ -54,6 +54,29 @@ struct BatchLevel {
     uint32_t sh;           // sh1 | sh2 << 8
 };
 
+// What a batched lookup reads first for set s: one aligned 64-byte record with the set's place in
+// the packed A and its levels 0 and 1 (most queries stop there); levels 2.. are BatchLev records at
+// lev_idx.  Level 1 starts at bit (m0 + 63) & ~63 of the set.
+struct __attribute__((aligned(64))) BatchHead {
+    uint64_t start_bit;
+    uint64_t ones_before;
+    uint64_t left_off;
+    uint32_t n;
+    uint16_t nleft;
+    uint8_t nlev;
+    uint8_t pad;
+    uint32_t m0, m1;
+    uint64_t magic0, magic1;
+    uint32_t lev_idx;
+    uint32_t pad2;
+};
+static_assert(sizeof(BatchHead) == 64, "one 64-byte record per set");
+struct BatchLev {
+    uint32_t m;
+    uint32_t off;          // bit offset of the level inside the set
+    uint64_t magic;
+};
+
 // Bucket size of the partitioned levels: 2^pbits positions and room for kcap keys in LDS.
 struct BucketGeometry {
     uint32_t pbits;
@@ -112,24 +135,30 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
 hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
                             hipStream_t s);
 
+uint32_t batch_classes();
+hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
+                                uint32_t* bound, uint32_t* hist, unsigned long long* info, hipStream_t s);
+hipError_t launch_batch_order(const uint64_t* offsets, uint64_t nsets, const uint32_t* hist, uint32_t* cursor,
+                              uint32_t* order, hipStream_t s);
 hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
                               uint64_t nsets, unsigned long long* next, uint64_t* scratch,
-                              const uint64_t* region_bit, double gamma, const SeedTable& seeds,
+                              const uint64_t* region_w, double gamma, const SeedTable& seeds,
                               uint32_t D, uint32_t left_cap, uint64_t* region, BatchSet* sets,
-                              BatchLevel* levels, uint64_t* left_sorted, uint32_t* bits32,
-                              uint64_t max_m, uint32_t grid, hipStream_t s);
+                              BatchLevel* levels, uint32_t* bits32, uint64_t max_m, uint32_t grid,
+                              hipStream_t s);
 uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap);
-hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_bit, BatchSet* sets,
+hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* lev32,
+                              uint32_t* bits32, uint32_t* fail, hipStream_t s);
+hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_w, BatchSet* sets,
                              uint64_t nsets, const uint64_t* bit_pre, const uint64_t* left_pre,
                              const uint64_t* left_sorted, const uint64_t* offsets, uint64_t* words,
                              uint64_t* left, hipStream_t s);
-hipError_t launch_batch_ones_before(BatchSet* sets, const uint64_t* words, const uint64_t* rank,
-                                    uint32_t rank_shift, uint64_t nsets, hipStream_t s);
+hipError_t launch_batch_heads(BatchSet* sets, const BatchLevel* levels, uint32_t D, const uint64_t* words,
+                              const uint64_t* rank, uint32_t rank_shift, const uint64_t* lev_pre, uint64_t nsets,
+                              BatchHead* heads, BatchLev* lev, hipStream_t s);
 hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
-                               const BatchSet* sets, const BatchLevel* levels, uint32_t D, uint64_t nsets,
-                               const uint32_t* sec, const uint64_t* super, const uint64_t* left,
-                               const SeedTable& seeds, hipStream_t s);
-hipError_t launch_u32_from_sets(const BatchSet* sets, uint64_t nsets, int field, uint32_t* out,
-                                hipStream_t s);
+                               const BatchHead* heads, const BatchLev* lev, uint64_t nsets, const uint32_t* sec,
+                               const uint64_t* super, const uint64_t* left, const SeedTable& seeds,
+                               hipStream_t s);
 
 }  // namespace mphfk

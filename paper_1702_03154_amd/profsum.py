@@ -46,6 +46,21 @@ def pmc(db: str, counter: str, out=sys.stdout):
         print(f"{short(n):60s} {k:10d} {a:14.1f} {lo:14.1f} {hi:14.1f}", file=out)
 
 
+SOURCES = ("kernels.hip", "device.h")   # the lookup kernel and the device helpers it inlines
+
+
+def source_digest() -> str:
+    """SHA-256 over the sources the lookup kernel is built from."""
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def _per_dispatch(db: str, counter: str):
     c = sqlite3.connect(db)
     return c.execute("select dispatch_id, kernel_name, value from counters_collection "
@@ -53,10 +68,11 @@ def _per_dispatch(db: str, counter: str):
 
 
 def _calibration(rows):
-    """The 1 GiB calibration copy: the last runtime copy kernel before the first library kernel."""
+    """The 1 GiB calibration copy: the largest runtime copy kernel before the first library kernel
+    (the library's own small host-to-device copies also run as copy kernels)."""
     first = next(i for i, r in enumerate(rows) if "mphfk" in r[1])
     cal = [r for r in rows[:first] if "copyBuffer" in r[1]]
-    return cal[-1][2]
+    return max(r[2] for r in cal)
 
 
 def traffic(fetch_db: str, write_db: str, kernel: str, queries: int, out_json: str):
@@ -70,12 +86,11 @@ def traffic(fetch_db: str, write_db: str, kernel: str, queries: int, out_json: s
     ws = gib_kib / _calibration(w_rows)
     fk = [r[2] for r in f_rows if short(r[1]) == kernel]
     wk = [r[2] for r in w_rows if short(r[1]) == kernel]
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "kernels.hip")
     res = {"kernel": kernel, "queries": queries,
            "fetch_kib": sum(fk) / len(fk), "write_kib": sum(wk) / len(wk),
            "fetch_scale": fs, "write_scale": ws,
            "bytes_per_launch": (sum(fk) / len(fk) * fs + sum(wk) / len(wk) * ws) * 1024.0,
-           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+           "source_sha256": source_digest()}
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
