@@ -920,6 +920,7 @@ struct mphf_batch {
     BatchLevel* levels = nullptr;
     BatchHead* heads = nullptr;
     BatchLev* lev = nullptr;
+    BatchAux* aux = nullptr;
     uint64_t* words = nullptr;
     uint64_t* rank = nullptr;
     uint32_t* sec = nullptr;
@@ -1077,17 +1078,15 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
 
     // 2. every set's levels in one persistent launch; survivors and then the sorted fallback keys of
     // set s stay in scratch[offsets[s] ..]
-    uint64_t *scratch, *region, *pre, *lpre, *levpre;
-    uint32_t *bits32, *left32, *lev32;
+    uint64_t *scratch, *region, *pre, *lpre;
+    uint32_t *bits32, *left32;
     auto lay2 = [&](Carver& c) {
         scratch = c.take<uint64_t>(total + 1);
         region = c.take<uint64_t>(region_words + 1);
         bits32 = c.take<uint32_t>(S1);
         left32 = c.take<uint32_t>(S1);
-        lev32 = c.take<uint32_t>(S1);
         pre = c.take<uint64_t>(S1);
         lpre = c.take<uint64_t>(S1);
-        levpre = c.take<uint64_t>(S1);
     };
     {
         Carver m{nullptr};
@@ -1118,21 +1117,22 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
                                o.max_levels, BATCH_LEFT_CAP, region, b->sets, b->levels, bits32, max_m, grid, s),
             "batch build");
     tr.mark("batch levels", (long)grid);
-    HIP_TRY(launch_batch_tally(b->sets, nsets, left32, lev32, bits32, fail32, s), "tally");
+    HIP_TRY(launch_batch_tally(b->sets, nsets, left32, bits32, fail32, s), "tally");
     HIP_TRY(launch_exclusive_scan(bits32, pre, S1, tiles, s), "bit prefix");
     HIP_TRY(launch_exclusive_scan(left32, lpre, S1, tiles, s), "leftover prefix");
-    HIP_TRY(launch_exclusive_scan(lev32, levpre, S1, tiles, s), "level prefix");
     HIP_TRY(hipMemcpyAsync(pin + 4, fail32, 8, hipMemcpyDeviceToHost, s), "read back");
     HIP_TRY(hipMemcpyAsync(pin + 5, pre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
     HIP_TRY(hipMemcpyAsync(pin + 6, lpre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipMemcpyAsync(pin + 7, levpre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
     HIP_TRY(hipStreamSynchronize(s), "batch sync");
     const uint32_t bad = (uint32_t)pin[4], first_bad = (uint32_t)(pin[4] >> 32);
     if (bad & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(first_bad));
     if (bad & 2u)
         return fail(MPHF_E_INVALID, "set " + std::to_string(first_bad) +
                                         " keeps more than 2048 keys after its last level (duplicates, or too few levels)");
-    const uint64_t tb = pin[5], tl = pin[6], tlev = pin[7];
+    const uint64_t tb = pin[5], tl = pin[6];
+    const uint64_t lev_slots = o.max_levels > 2 ? nsets * (o.max_levels - 2) : 0;
+    if (tb >= (1ull << HEAD_START_BITS) || total >= (1ull << HEAD_ONES_BITS))
+        return fail(MPHF_E_INVALID, "batch too large for the lookup records");
     b->total_bits = tb;
     b->nleft = tl;
     b->nrank = (tb + 511) / 512;
@@ -1143,7 +1143,8 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
     {
         Carver m{nullptr};
         m.take<BatchHead>(nsets);
-        m.take<BatchLev>(tlev + 1);
+        m.take<BatchLev>(lev_slots + 1);
+        m.take<BatchAux>(nsets);
         m.take<uint64_t>(tb / 64 + 1);
         m.take<uint64_t>(tl + 1);
         m.take<uint64_t>(b->nrank + 1);
@@ -1154,7 +1155,8 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
         b->mem[1] = p;
         Carver c{p};
         b->heads = c.take<BatchHead>(nsets);
-        b->lev = c.take<BatchLev>(tlev + 1);
+        b->lev = c.take<BatchLev>(lev_slots + 1);
+        b->aux = c.take<BatchAux>(nsets);
         b->words = c.take<uint64_t>(tb / 64 + 1);
         b->left = c.take<uint64_t>(tl + 1);
         b->rank = c.take<uint64_t>(b->nrank + 1);
@@ -1183,8 +1185,8 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
         HIP_TRY(launch_rank(b->words, tb / 64, 512, b->rank, b->nrank, rc, rt, s), "rank");
         HIP_TRY(launch_sectors(b->words, tb, b->sec, b->super, cnt, spre, stiles, s), "sectors");
     }
-    HIP_TRY(launch_batch_heads(b->sets, b->levels, o.max_levels, b->words, b->rank, 9, levpre, nsets, b->heads,
-                               b->lev, s),
+    HIP_TRY(launch_batch_heads(b->sets, b->levels, o.max_levels, b->words, b->rank, 9, nsets, b->heads, b->lev,
+                               b->aux, s),
             "heads");
     HIP_TRY(hipStreamSynchronize(s), "batch final sync");
     tr.mark("batch structure");
@@ -1214,8 +1216,8 @@ mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, co
     if (!n) return MPHF_OK;
     if (!set_ids || !keys || !out || !is_device_ptr(set_ids) || !is_device_ptr(keys) || !is_device_ptr(out))
         return fail(MPHF_E_INVALID, "set_ids, keys and out must be device memory");
-    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->heads, b->lev, b->nsets, b->sec, b->super, b->left,
-                                b->seeds, (hipStream_t)stream),
+    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->heads, b->lev, b->aux, b->D, b->nsets, b->sec, b->super,
+                                b->left, b->seeds, (hipStream_t)stream),
             "batch lookup");
     return MPHF_OK;
 }

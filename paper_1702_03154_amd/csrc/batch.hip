@@ -270,22 +270,20 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
     }
 }
 
-// Per set: leftover count and count of levels past the second (inputs of two prefix scans), and the
-// OR of the statuses with the first failing set.  fail[0]: OR of statuses; fail[1]: first bad set.
+// Per set: the leftover count (input of a prefix scan; the bit counts are already in bits32), and
+// the OR of the statuses with the first failing set.  fail[0]: OR of statuses; fail[1]: first bad set.
 __global__ void __launch_bounds__(PT)
 k_batch_tally(const BatchSet* __restrict__ sets, uint64_t nsets, uint32_t* __restrict__ left32,
-              uint32_t* __restrict__ lev32, uint32_t* __restrict__ bits32, uint32_t* __restrict__ fail) {
+              uint32_t* __restrict__ bits32, uint32_t* __restrict__ fail) {
     const uint64_t stride = (uint64_t)gridDim.x * PT;
     for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s <= nsets; s += stride) {
         if (s == nsets) {
             left32[s] = 0;
-            lev32[s] = 0;
             bits32[s] = 0;
             continue;
         }
         const BatchSet st = sets[s];
         left32[s] = st.nleft;
-        lev32[s] = st.nlev > 2 ? st.nlev - 2 : 0;
         if (st.status) {
             atomicOr(&fail[0], st.status);
             atomicMin(&fail[1], (uint32_t)s);
@@ -314,12 +312,11 @@ __global__ void k_batch_pack(const uint64_t* __restrict__ region, const uint64_t
 }
 
 // Per set: the ones of A before the set (from the rank table, sampled every 2^rank_shift bits) and
-// the lookup records: the 64-byte head with levels 0 and 1, then levels 2.. in the compact array.
+// the lookup records: the 16-byte head, levels 2.. in the set's D - 2 slots, the fallback record.
 __global__ void __launch_bounds__(PT)
 k_batch_heads(BatchSet* __restrict__ sets, const BatchLevel* __restrict__ levels, uint32_t D,
               const uint64_t* __restrict__ words, const uint64_t* __restrict__ rank, uint32_t rank_shift,
-              const uint64_t* __restrict__ lev_pre, uint64_t nsets, BatchHead* __restrict__ heads,
-              BatchLev* __restrict__ lev) {
+              uint64_t nsets, BatchHead* __restrict__ heads, BatchLev* __restrict__ lev, BatchAux* __restrict__ aux) {
     const uint64_t stride = (uint64_t)gridDim.x * PT;
     for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s < nsets; s += stride) {
         const BatchSet st = sets[s];
@@ -331,38 +328,49 @@ k_batch_heads(BatchSet* __restrict__ sets, const BatchLevel* __restrict__ levels
             for (uint64_t k = (b << rank_shift) >> 6; k < (g >> 6); ++k) r += __popcll(words[k]);
         }
         sets[s].ones_before = r;
-        BatchHead h;
-        h.start_bit = st.start_bit;
-        h.ones_before = r;
-        h.left_off = st.left_off;
-        h.n = (uint32_t)st.n;
-        h.nleft = (uint16_t)st.nleft;
-        h.nlev = (uint8_t)st.nlev;
-        h.pad = 0;
         const BatchLevel* L = levels + s * D;
-        h.m0 = st.nlev > 0 ? (uint32_t)L[0].m : 0;
-        h.m1 = st.nlev > 1 ? (uint32_t)L[1].m : 0;
-        h.magic0 = st.nlev > 0 ? L[0].magic : 0;
-        h.magic1 = st.nlev > 1 ? L[1].magic : 0;
-        h.lev_idx = (uint32_t)lev_pre[s];
-        h.pad2 = 0;
+        const uint64_t m0 = st.nlev > 0 ? L[0].m : 0, m1 = st.nlev > 1 ? L[1].m : 0;
+        BatchHead h;
+        h.a = st.start_bit | (m0 << HEAD_START_BITS);
+        h.b = r | (m1 << HEAD_ONES_BITS) | ((uint64_t)st.nlev << (HEAD_ONES_BITS + HEAD_M_BITS));
         heads[s] = h;
+        BatchAux x;
+        x.left_off = st.left_off;
+        x.n = (uint32_t)st.n;
+        x.nleft = st.nleft;
+        aux[s] = x;
         for (uint32_t d = 2; d < st.nlev; ++d) {
             BatchLev e;
             e.m = (uint32_t)L[d].m;
             e.off = (uint32_t)L[d].off;
-            e.magic = L[d].magic;
-            lev[lev_pre[s] + d - 2] = e;
+            lev[s * (D - 2) + d - 2] = e;
         }
     }
+}
+
+// h mod m for 1 <= m < 2^20, exactly: two base-2^32 digits of the long division, each quotient
+// estimated with the fp64 reciprocal rm = 1/m (error far below one unit) and corrected by one step.
+// All intermediate remainders lie in (-m, 2m), so 32-bit wrapping arithmetic holds them exactly.
+__device__ __forceinline__ uint32_t mod_small(uint64_t h, uint32_t m, double rm) {
+    const uint32_t hi = (uint32_t)(h >> 32), lo = (uint32_t)h;
+    uint32_t q = (uint32_t)((double)hi * rm);
+    int32_t r = (int32_t)(hi - q * m);
+    r += r < 0 ? (int32_t)m : 0;
+    r -= r >= (int32_t)m ? (int32_t)m : 0;
+    const double x = fma((double)(uint32_t)r, 4294967296.0, (double)lo);   // r * 2^32 + lo < 2^52
+    q = (uint32_t)(x * rm);
+    r = (int32_t)(lo - q * m);
+    r += r < 0 ? (int32_t)m : 0;
+    r -= r >= (int32_t)m ? (int32_t)m : 0;
+    return (uint32_t)r;
 }
 
 // Lookup of (set, key) pairs: Algorithm 3 within the set, ranks through the sector layout.
 __global__ void __launch_bounds__(256)
 k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict__ q, uint64_t n,
                uint64_t* __restrict__ out, const BatchHead* __restrict__ heads, const BatchLev* __restrict__ lev,
-               uint64_t nsets, const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
-               const uint64_t* __restrict__ left, SeedTable seeds) {
+               const BatchAux* __restrict__ aux, uint32_t D, uint64_t nsets, const uint32_t* __restrict__ sec,
+               const uint64_t* __restrict__ super, const uint64_t* __restrict__ left, SeedTable seeds) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t s = set_ids[i];
@@ -370,42 +378,45 @@ k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict_
         uint64_t label = 0;
         if (s < nsets) {
             const BatchHead h = heads[s];
+            const uint64_t start = h.a & ((1ull << HEAD_START_BITS) - 1);
+            const uint32_t m0 = (uint32_t)(h.a >> HEAD_START_BITS);
+            const uint64_t ones = h.b & ((1ull << HEAD_ONES_BITS) - 1);
+            const uint32_t m1 = (uint32_t)(h.b >> HEAD_ONES_BITS) & ((1u << HEAD_M_BITS) - 1);
+            const uint32_t nlev = (uint32_t)(h.b >> (HEAD_ONES_BITS + HEAD_M_BITS));
             bool found = false;
-            for (uint32_t d = 0; d < h.nlev; ++d) {
+            for (uint32_t d = 0; d < nlev; ++d) {
                 uint32_t m, off;
-                uint64_t magic;
                 if (d == 0) {
-                    m = h.m0;
-                    magic = h.magic0;
+                    m = m0;
                     off = 0;
                 } else if (d == 1) {
-                    m = h.m1;
-                    magic = h.magic1;
-                    off = (h.m0 + 63u) & ~63u;
+                    m = m1;
+                    off = (m0 + 63u) & ~63u;
                 } else {
-                    const BatchLev e = lev[h.lev_idx + d - 2];
+                    const BatchLev e = lev[s * (D - 2) + d - 2];
                     m = e.m;
-                    magic = e.magic;
                     off = e.off;
                 }
-                const uint32_t l = 32u - (uint32_t)__clz(m - 1u);   // ceil(log2 m); 0 for m = 1
-                const uint64_t pos =
-                    mod_invariant(fmix64(x ^ seeds.s[d]), m, magic, l < 1 ? l : 1, l > 1 ? l - 1 : 0);
+                const uint32_t pos = mod_small(fmix64(x ^ seeds.s[d]), m, 1.0 / (double)m);
                 uint64_t rank;
-                if (sector_rank(sec, super, h.start_bit + off + pos, &rank)) {
-                    label = rank - h.ones_before + 1;
+                const uint64_t g = start + off + pos;
+                if (sector_rank(sec, super, g, &rank)) {
+                    label = rank - ones + 1;
                     found = true;
                     break;
                 }
             }
-            if (!found && h.nleft) {
-                const uint64_t* L = left + h.left_off;
-                uint32_t lo = 0, hi = h.nleft;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (L[mid] < x) lo = mid + 1; else hi = mid;
+            if (!found) {
+                const BatchAux ax = aux[s];
+                if (ax.nleft) {
+                    const uint64_t* L = left + ax.left_off;
+                    uint32_t lo = 0, hi = ax.nleft;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (L[mid] < x) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo < ax.nleft && L[lo] == x) label = ax.n - ax.nleft + 1 + lo;
                 }
-                if (lo < h.nleft && L[lo] == x) label = h.n - h.nleft + 1 + lo;
             }
         }
         out[i] = label;
@@ -458,10 +469,10 @@ uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap) {
     return lds;
 }
 
-hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* lev32,
-                              uint32_t* bits32, uint32_t* fail, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_tally, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, sets, nsets, left32, lev32,
-                       bits32, fail);
+hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* bits32,
+                              uint32_t* fail, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_tally, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, sets, nsets, left32, bits32,
+                       fail);
     return hipGetLastError();
 }
 
@@ -476,23 +487,23 @@ hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_w, B
 }
 
 hipError_t launch_batch_heads(BatchSet* sets, const BatchLevel* levels, uint32_t D, const uint64_t* words,
-                              const uint64_t* rank, uint32_t rank_shift, const uint64_t* lev_pre, uint64_t nsets,
-                              BatchHead* heads, BatchLev* lev, hipStream_t s) {
+                              const uint64_t* rank, uint32_t rank_shift, uint64_t nsets, BatchHead* heads,
+                              BatchLev* lev, BatchAux* aux, hipStream_t s) {
     if (!nsets) return hipSuccess;
     hipLaunchKernelGGL(k_batch_heads, dim3(prep_grid(nsets)), dim3(PT), 0, s, sets, levels, D, words, rank,
-                       rank_shift, lev_pre, nsets, heads, lev);
+                       rank_shift, nsets, heads, lev, aux);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
-                               const BatchHead* heads, const BatchLev* lev, uint64_t nsets, const uint32_t* sec,
-                               const uint64_t* super, const uint64_t* left, const SeedTable& seeds,
-                               hipStream_t s) {
+                               const BatchHead* heads, const BatchLev* lev, const BatchAux* aux, uint32_t D,
+                               uint64_t nsets, const uint32_t* sec, const uint64_t* super, const uint64_t* left,
+                               const SeedTable& seeds, hipStream_t s) {
     if (!n) return hipSuccess;
     uint64_t blocks = (n + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_batch_lookup, dim3((unsigned)blocks), dim3(256), 0, s, set_ids, q, n, out, heads, lev,
-                       nsets, sec, super, left, seeds);
+    hipLaunchKernelGGL(k_batch_lookup, dim3((unsigned)blocks), dim3(256), 0, s, set_ids, q, n, out, heads, lev, aux,
+                       D, nsets, sec, super, left, seeds);
     return hipGetLastError();
 }
 

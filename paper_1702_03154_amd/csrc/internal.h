@@ -54,27 +54,22 @@ struct BatchLevel {
     uint32_t sh;           // sh1 | sh2 << 8
 };
 
-// What a batched lookup reads first for set s: one aligned 64-byte record with the set's place in
-// the packed A and its levels 0 and 1 (most queries stop there); levels 2.. are BatchLev records at
-// lev_idx.  Level 1 starts at bit (m0 + 63) & ~63 of the set.
-struct __attribute__((aligned(64))) BatchHead {
-    uint64_t start_bit;
-    uint64_t ones_before;
-    uint64_t left_off;
-    uint32_t n;
-    uint16_t nleft;
-    uint8_t nlev;
-    uint8_t pad;
-    uint32_t m0, m1;
-    uint64_t magic0, magic1;
-    uint32_t lev_idx;
-    uint32_t pad2;
+// What a batched lookup reads first for set s: 16 bytes with the set's first bit in the packed A
+// (44 bits) and m0 (20 bits) in word a, and the ones before the set (37 bits), m1 (20 bits) and the
+// level count (7 bits) in word b.  Level 1 starts at bit (m0 + 63) & ~63 of the set; levels 2.. are
+// BatchLev records in D - 2 slots per set, and the fallback table is described by BatchAux.
+struct __attribute__((aligned(16))) BatchHead {
+    uint64_t a, b;
 };
-static_assert(sizeof(BatchHead) == 64, "one 64-byte record per set");
+constexpr uint32_t HEAD_START_BITS = 44, HEAD_ONES_BITS = 37, HEAD_M_BITS = 20;
 struct BatchLev {
     uint32_t m;
     uint32_t off;          // bit offset of the level inside the set
-    uint64_t magic;
+};
+struct BatchAux {
+    uint64_t left_off;     // first of the set's fallback keys in the packed fallback array
+    uint32_t n;
+    uint32_t nleft;
 };
 
 // Bucket size of the partitioned levels: 2^pbits positions and room for kcap keys in LDS.
@@ -147,18 +142,18 @@ hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, con
                               BatchLevel* levels, uint32_t* bits32, uint64_t max_m, uint32_t grid,
                               hipStream_t s);
 uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap);
-hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* lev32,
-                              uint32_t* bits32, uint32_t* fail, hipStream_t s);
+hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* bits32,
+                              uint32_t* fail, hipStream_t s);
 hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_w, BatchSet* sets,
                              uint64_t nsets, const uint64_t* bit_pre, const uint64_t* left_pre,
                              const uint64_t* left_sorted, const uint64_t* offsets, uint64_t* words,
                              uint64_t* left, hipStream_t s);
 hipError_t launch_batch_heads(BatchSet* sets, const BatchLevel* levels, uint32_t D, const uint64_t* words,
-                              const uint64_t* rank, uint32_t rank_shift, const uint64_t* lev_pre, uint64_t nsets,
-                              BatchHead* heads, BatchLev* lev, hipStream_t s);
+                              const uint64_t* rank, uint32_t rank_shift, uint64_t nsets, BatchHead* heads,
+                              BatchLev* lev, BatchAux* aux, hipStream_t s);
 hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
-                               const BatchHead* heads, const BatchLev* lev, uint64_t nsets, const uint32_t* sec,
-                               const uint64_t* super, const uint64_t* left, const SeedTable& seeds,
-                               hipStream_t s);
+                               const BatchHead* heads, const BatchLev* lev, const BatchAux* aux, uint32_t D,
+                               uint64_t nsets, const uint32_t* sec, const uint64_t* super, const uint64_t* left,
+                               const SeedTable& seeds, hipStream_t s);
 
 }  // namespace mphfk
