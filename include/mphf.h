@@ -155,8 +155,9 @@ mphf_status mphf_positions(const uint64_t* keys, uint64_t n, uint64_t level_seed
  * A set may have at most 2^19 / gamma keys (ceil(gamma n) <= 2^19: its A and C bits live in one
  * workgroup's LDS).  A set that keeps more than 2048 keys after its last level fails the whole
  * batch with MPHF_E_INVALID, and duplicate keys within a set with MPHF_E_DUPLICATE_KEYS; keys
- * of different sets may be equal.  flags must be 0, rank_sample 512; keep_collisions is ignored.  The build returns when the batch is complete on `stream`.  A batch handle owns its
- * device memory and is immutable, like an mphf_t. */
+ * of different sets may be equal.  flags must be 0, rank_sample 512; keep_collisions is ignored.
+ * A batch handle owns its device memory and is immutable between builds; lookups follow the
+ * rules of mphf_lookup_ex. */
 typedef struct mphf_batch mphf_batch_t;
 
 typedef struct mphf_set_info {
@@ -169,9 +170,28 @@ typedef struct mphf_set_info {
     uint64_t total_bits;                      /* the set's bits (64-bit padded levels) */
 } mphf_set_info_t;
 
+/* One-shot batched build on `stream`; returns when the batch is complete.  The structure is
+ * packed: each set's lookup sectors (64 bytes per 480 bits of the set, with a 32-bit count of the
+ * set's ones before them), a 16-byte head per set and the sets' fallback keys. */
 mphf_status mphf_build_batch(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets,
                              double gamma, uint64_t seed, const mphf_opts* opts, void* stream,
                              mphf_batch_t** out);
+
+/* A planned batch for repeated builds of sets of these sizes: checks the offsets (copied) and
+ * allocates, for the worst case of these sizes (every key surviving every level), every buffer a
+ * build needs.  Synchronous.  The handle holds no function until mphf_batch_rebuild. */
+mphf_status mphf_batch_plan(const uint64_t* offsets, uint64_t nsets, double gamma, uint64_t seed,
+                            const mphf_opts* opts, void* stream, mphf_batch_t** out);
+
+/* Build a planned batch from `keys` (laid out by the plan's offsets): only kernel launches on
+ * `stream`, with no allocation and no host synchronization, so the call can be captured in a HIP
+ * graph and replayed (the graph keeps the keys pointer).  The function is ready when the stream
+ * reaches this point; a failed build (duplicate keys, a set with too many leftovers) is reported
+ * by mphf_batch_status.  MPHF_E_INVALID for a handle that was not planned. */
+mphf_status mphf_batch_rebuild(mphf_batch_t* b, const uint64_t* keys, void* stream);
+
+/* Wait for `stream` and report the last build of a planned batch (MPHF_OK for a one-shot one). */
+mphf_status mphf_batch_status(mphf_batch_t* b, void* stream);
 
 /* Label each (set_ids[i], keys[i]) device pair into out[i] (Algorithm 3 within set set_ids[i]);
  * a set id out of range gives 0.  Asynchronous on `stream`. */
@@ -181,15 +201,21 @@ mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, co
 /* Sizes of set `set` (host values, synchronous). */
 mphf_status mphf_batch_set_info(const mphf_batch_t* b, uint64_t set, mphf_set_info_t* info);
 
-/* Host copies of set `set`'s bits (info.total_bits / 64 words) and fallback keys (ascending). */
+/* Host copies of set `set`'s bits (info.total_bits / 64 words, laid out like mphf_export's A) and
+ * fallback keys (ascending). */
 mphf_status mphf_batch_export_set(const mphf_batch_t* b, uint64_t set, uint64_t* words, uint64_t nwords,
                                   uint64_t* fallback_keys, uint64_t nfb);
 
-/* Sets, total keys, total bits and bits/key of the whole batch (structure as in mphf_stats). */
+/* Host copy of set `set`'s lookup sectors: ceil(total_bits / 480) sectors of 16 u32, word 0 the
+ * ones of the set before the sector, words 1..15 the next 480 bits of the set. */
+mphf_status mphf_batch_export_sectors(const mphf_batch_t* b, uint64_t set, uint32_t* sectors,
+                                      uint64_t nsectors);
+
+/* Sets, total keys, total bits of the sets' levels and bits/key of the packed structure. */
 mphf_status mphf_batch_totals(const mphf_batch_t* b, uint64_t* nsets, uint64_t* nkeys,
                               uint64_t* total_bits, double* bits_per_key);
 
-/* Free every device buffer of b.  NULL is allowed; must not overlap a lookup on b. */
+/* Free every device buffer of b.  NULL is allowed; must not overlap a lookup or build on b. */
 void mphf_batch_destroy(mphf_batch_t* b);
 
 /* Free the build temporaries the library keeps per device between builds (a few times the

@@ -911,21 +911,33 @@ const char* mphf_last_error(void) { return g_err.c_str(); }
 
 struct mphf_batch {
     int device = 0;
-    uint64_t nsets = 0, nkeys = 0, total_bits = 0, nrank = 0, nsec = 0, nleft = 0;
+    bool planned = false;
+    uint64_t nsets = 0, nkeys = 0, total_bits = 0, nsec = 0, nleft = 0;
+    uint64_t used_sec = 0, used_left = 0;   // sectors and fallback keys the sets use (packed sizes)
     double gamma = 0;
     uint32_t D = 25;
     SeedTable seeds{};
-    void* mem[2] = {nullptr, nullptr};   // the two device allocations every pointer below lives in
+    std::vector<void*> mem;     // device allocations owned by the handle
+    // per set (valid after a build)
     BatchSet* sets = nullptr;
     BatchLevel* levels = nullptr;
     BatchHead* heads = nullptr;
     BatchLev* lev = nullptr;
     BatchAux* aux = nullptr;
-    uint64_t* words = nullptr;
-    uint64_t* rank = nullptr;
-    uint32_t* sec = nullptr;
-    uint64_t* super = nullptr;
-    uint64_t* left = nullptr;
+    uint32_t* sec = nullptr;    // lookup sectors: dense, or the worst-case region of a planned batch
+    uint64_t* left = nullptr;   // fallback keys: packed, or in the survivors' scratch of a planned batch
+    // what a planned batch keeps for its rebuilds
+    uint64_t* offsets = nullptr;
+    uint32_t* order = nullptr;
+    uint64_t* region_w = nullptr;
+    uint64_t* sreg_base = nullptr;
+    unsigned long long* queue = nullptr;
+    uint32_t* fail32 = nullptr;
+    uint32_t *left32 = nullptr, *sec32 = nullptr;
+    uint64_t* scratch = nullptr;
+    uint64_t* region = nullptr;
+    uint64_t max_m = 0;
+    uint32_t grid = 0;
 };
 
 namespace {
@@ -967,19 +979,55 @@ struct Carver {
     }
 };
 
-// The batch temporaries: from the device's cached workspace when this build can take it, else
-// from the arena (always so with a memory budget, so that the budget counts them).
-class BatchTemps {
+// Device memory for a batch: the handle's own allocations (kept), or temporaries from the device's
+// cached workspace when this build can take it, else from the arena (always so with a memory budget,
+// so that the budget counts them).
+class BatchMem {
   public:
-    BatchTemps(Arena& ar, int dev, bool cache) : ar_(ar) {
+    BatchMem(Arena& ar, int dev, bool cache) : ar_(ar) {
         if (!cache || dev < 0 || dev >= 64) return;
         std::unique_lock<std::mutex> lk(g_bws[dev].mu, std::try_to_lock);
         if (!lk.owns_lock()) return;
         lock_ = std::move(lk);
         ws_ = &g_bws[dev];
     }
-    mphf_status get(int slot, uint64_t bytes, uint8_t** p) {
-        if (!ws_) return ar_.alloc(p, bytes + 256, "batch temporaries");
+    template <typename F>
+    mphf_status temp(int slot, F lay) {
+        Carver m{nullptr};
+        lay(m);
+        uint8_t* p = nullptr;
+        mphf_status st = ws_ ? ws_get(slot, m.off, &p) : ar_.alloc(&p, m.off + 256, "batch temporaries");
+        if (st != MPHF_OK) return st;
+        Carver c{p};
+        lay(c);
+        return MPHF_OK;
+    }
+    template <typename F>
+    mphf_status transient(F lay, const char* what) {   // freed when the build returns
+        Carver m{nullptr};
+        lay(m);
+        uint8_t* p = nullptr;
+        mphf_status st = ar_.alloc(&p, m.off + 256, what);
+        if (st != MPHF_OK) return st;
+        Carver c{p};
+        lay(c);
+        return MPHF_OK;
+    }
+    template <typename F>
+    mphf_status own(mphf_batch* b, F lay, const char* what) {
+        Carver m{nullptr};
+        lay(m);
+        uint8_t* p = nullptr;
+        mphf_status st = ar_.alloc(&p, m.off + 256, what);
+        if (st != MPHF_OK) return st;
+        b->mem.push_back(p);
+        Carver c{p};
+        lay(c);
+        return MPHF_OK;
+    }
+
+  private:
+    mphf_status ws_get(int slot, uint64_t bytes, uint8_t** p) {
         if (ws_->cap[slot] < bytes) {
             if (ws_->buf[slot]) {
                 HIP_TRY(hipDeviceSynchronize(), "workspace sync");
@@ -999,15 +1047,12 @@ class BatchTemps {
         *p = (uint8_t*)ws_->buf[slot];
         return MPHF_OK;
     }
-
-  private:
     Arena& ar_;
     BatchWorkspace* ws_ = nullptr;
     std::unique_lock<std::mutex> lock_;
 };
 
-mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
-                             uint64_t seed, const mphf_opts& o, hipStream_t s, mphf_batch** out) {
+mphf_status check_batch_args(const uint64_t* offsets, uint64_t nsets, double gamma, const mphf_opts& o) {
     if (!(gamma >= 1.0) || !std::isfinite(gamma)) return fail(MPHF_E_INVALID, "gamma must be a finite number >= 1");
     if (!nsets) return fail(MPHF_E_INVALID, "nsets must be positive");
     if (nsets >= (1ull << 32)) return fail(MPHF_E_INVALID, "at most 2^32 - 1 sets");
@@ -1016,7 +1061,121 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
     if (st != MPHF_OK) return st;
     if (o.flags) return fail(MPHF_E_INVALID, "flags are not supported for batched builds");
     if (o.rank_sample != 512) return fail(MPHF_E_INVALID, "batched builds use rank_sample 512");
+    return MPHF_OK;
+}
 
+// Offsets checked, worst-case regions sized, size-ordered work queue, and every buffer a build needs.
+// `keep` = a planned batch: everything lives in the handle; else the temporaries are borrowed.
+mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
+                        uint64_t seed, const mphf_opts& o, bool keep, hipStream_t s, BatchMem& mem, uint64_t* pin) {
+    mphf_status st;
+    b->nsets = nsets;
+    b->gamma = gamma;
+    b->D = o.max_levels;
+    b->planned = keep;
+    level_seeds(seed, o.max_levels, b->seeds.s);
+    const uint32_t ncls = batch_classes();
+    const uint64_t S1 = nsets + 1;
+    uint32_t *bound, *sbound, *hist;
+    uint64_t *tiles, *off_copy;
+    unsigned long long* info;   // [0] largest set, [1] offset flags, [2] queue head
+    auto lay1 = [&](Carver& c) {
+        b->order = c.take<uint32_t>(nsets);
+        b->region_w = c.take<uint64_t>(S1);
+        b->sreg_base = c.take<uint64_t>(S1);
+        info = c.take<unsigned long long>(4);
+        hist = c.take<uint32_t>(2 * ncls + 2);
+        bound = c.take<uint32_t>(S1);
+        sbound = c.take<uint32_t>(S1);
+        tiles = c.take<uint64_t>(scan_tmp_tiles(S1));
+        b->left32 = c.take<uint32_t>(S1);
+        b->sec32 = c.take<uint32_t>(S1);
+        off_copy = keep ? c.take<uint64_t>(S1) : nullptr;
+    };
+    if ((st = keep ? mem.own(b, lay1, "batch plan") : mem.temp(0, lay1)) != MPHF_OK) return st;
+    b->queue = info + 2;
+    b->fail32 = hist + 2 * ncls;
+    if (keep) {
+        HIP_TRY(hipMemcpyAsync(off_copy, offsets, S1 * 8, hipMemcpyDeviceToDevice, s), "copy offsets");
+        b->offsets = off_copy;
+    } else {
+        b->offsets = const_cast<uint64_t*>(offsets);
+    }
+    HIP_TRY(launch_zero32(hist, 2 * ncls + 2, s), "zero classes");
+    HIP_TRY(launch_zero((uint64_t*)info, 4, s), "zero counters");
+    HIP_TRY(launch_batch_prepare(b->offsets, nsets, gamma, o.max_levels, BATCH_MAX_M, bound, sbound, hist, info, s),
+            "prepare");
+    HIP_TRY(launch_exclusive_scan(bound, b->region_w, S1, tiles, s), "region prefix");
+    HIP_TRY(launch_exclusive_scan(sbound, b->sreg_base, S1, tiles, s), "sector prefix");
+    HIP_TRY(launch_batch_order(b->offsets, nsets, hist, hist + ncls, b->order, s), "order");
+    HIP_TRY(hipMemcpyAsync(pin, info, 16, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 2, b->offsets + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 3, b->region_w + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipMemcpyAsync(pin + 4, b->sreg_base + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipStreamSynchronize(s), "batch sync");
+    const uint64_t max_n = pin[0], flags = pin[1], total = pin[2], region_words = pin[3], sreg_total = pin[4];
+    if (flags & 2) return fail(MPHF_E_INVALID, "offsets[0] must be 0");
+    if (flags & 1) return fail(MPHF_E_INVALID, "offsets must be non-decreasing");
+    if (flags & 4) return fail(MPHF_E_INVALID, "a set is too large for a batched build (ceil(gamma n) > 2^19)");
+    if (keys && total && !is_device_ptr(keys)) return fail(MPHF_E_INVALID, "keys must be device memory");
+    if (sreg_total >= (1ull << HEAD_BASE_BITS)) return fail(MPHF_E_INVALID, "batch too large for the lookup records");
+    b->nkeys = total;
+    b->max_m = level_size(gamma, max_n);
+
+    // survivors (then fallback keys), staged bits and worst-case sectors: the planned batch keeps them
+    auto lay2 = [&](Carver& c) {
+        b->scratch = c.take<uint64_t>(total + 1);
+        b->region = c.take<uint64_t>(region_words + 1);
+        b->sec = c.take<uint32_t>((sreg_total + 1) * SEC_WORDS);
+    };
+    if ((st = keep ? mem.own(b, lay2, "batch survivors and sectors") : mem.temp(1, lay2)) != MPHF_OK) return st;
+    const uint64_t lev_slots = o.max_levels > 2 ? nsets * (o.max_levels - 2) : 0;
+    auto lay3 = [&](Carver& c) {
+        b->sets = c.take<BatchSet>(nsets);
+        b->levels = c.take<BatchLevel>(nsets * o.max_levels);
+        b->heads = c.take<BatchHead>(nsets);
+        b->lev = c.take<BatchLev>(lev_slots + 1);
+        b->aux = c.take<BatchAux>(nsets);
+    };
+    if ((st = mem.own(b, lay3, "set records")) != MPHF_OK) return st;
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
+    HIP_TRY(batch_kernel_setup(b->max_m, BATCH_LEFT_CAP), "batch kernel LDS size");
+    const uint64_t lds = batch_lds_bytes(b->max_m, BATCH_LEFT_CAP);
+    const uint32_t per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 155000 / (lds + 1024)));
+    b->grid = (uint32_t)std::min<uint64_t>(nsets, (uint64_t)cus * per_cu);
+    if (keep) {
+        b->left = b->scratch;
+        b->nsec = sreg_total;
+    }
+    return MPHF_OK;
+}
+
+// Every set's levels, sectors and status: a fixed sequence of launches, no allocation and no host
+// synchronization (capturable).
+hipError_t batch_levels(const mphf_batch* b, const uint64_t* keys, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_batch_reset(b->queue, b->fail32, s)) != hipSuccess) return e;
+    if ((e = launch_batch_build(keys, b->offsets, b->order, b->nsets, b->queue, b->scratch, b->region_w, b->gamma,
+                                b->seeds, b->D, BATCH_LEFT_CAP, b->region, b->sec, b->sreg_base, b->sets, b->levels,
+                                b->max_m, b->grid, s)) != hipSuccess)
+        return e;
+    return launch_batch_tally(b->sets, b->nsets, b->left32, b->sec32, b->fail32, s);
+}
+
+mphf_status batch_failure(uint64_t word) {
+    const uint32_t bad = (uint32_t)word, first_bad = (uint32_t)(word >> 32);
+    if (bad & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(first_bad));
+    if (bad & 2u)
+        return fail(MPHF_E_INVALID, "set " + std::to_string(first_bad) +
+                                        " keeps more than 2048 keys after its last level (duplicates, or too few levels)");
+    return MPHF_OK;
+}
+
+mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
+                             uint64_t seed, const mphf_opts& o, bool planned, hipStream_t s, mphf_batch** out) {
+    mphf_status st = check_batch_args(offsets, nsets, gamma, o);
+    if (st != MPHF_OK) return st;
     Trace tr(s);
     mphf_batch* b = new mphf_batch();
     struct Guard {   // on failure the arena frees the buffers; only the handle itself is deleted here
@@ -1027,172 +1186,74 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
     configure_pool(b->device);
     uint64_t* pin = batch_pinned(b->device);
     if (!pin) return fail(MPHF_E_NOMEM, "pinned read-back buffer");
-    b->nsets = nsets;
-    b->gamma = gamma;
-    b->D = o.max_levels;
-    level_seeds(seed, o.max_levels, b->seeds.s);
     Arena ar(o.mem_budget, s);
-    BatchTemps temps(ar, b->device, o.mem_budget == 0);
-    const uint32_t ncls = batch_classes();
-    const uint64_t S1 = nsets + 1;
-
-    // 1. offsets checked, region sizes, size-ordered work queue (all on the device)
-    uint32_t *order, *bound, *hist, *fail32;
-    uint64_t *region_w, *tiles;
-    unsigned long long* info;   // [0] largest set, [1] offset flags, [2] queue head
-    auto lay1 = [&](Carver& c) {
-        order = c.take<uint32_t>(nsets);
-        bound = c.take<uint32_t>(S1);
-        region_w = c.take<uint64_t>(S1);
-        hist = c.take<uint32_t>(2 * ncls + 2);
-        info = c.take<unsigned long long>(4);
-        tiles = c.take<uint64_t>(scan_tmp_tiles(S1));
-    };
-    {
-        Carver m{nullptr};
-        lay1(m);
-        uint8_t* p = nullptr;
-        if ((st = temps.get(0, m.off, &p)) != MPHF_OK) return st;
-        Carver c{p};
-        lay1(c);
-    }
-    fail32 = hist + 2 * ncls;
-    HIP_TRY(launch_zero32(hist, 2 * ncls + 2, s), "zero classes");
-    HIP_TRY(launch_zero((uint64_t*)info, 4, s), "zero counters");
-    HIP_TRY(hipMemsetAsync(fail32 + 1, 0xFF, 4, s), "first-bad init");
-    HIP_TRY(launch_batch_prepare(offsets, nsets, gamma, o.max_levels, BATCH_MAX_M, bound, hist, info, s), "prepare");
-    HIP_TRY(launch_exclusive_scan(bound, region_w, S1, tiles, s), "region prefix");
-    HIP_TRY(launch_batch_order(offsets, nsets, hist, hist + ncls, order, s), "order");
-    HIP_TRY(hipMemcpyAsync(pin, info, 16, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipMemcpyAsync(pin + 2, offsets + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipMemcpyAsync(pin + 3, region_w + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipStreamSynchronize(s), "batch sync");
-    const uint64_t max_n = pin[0], flags = pin[1], total = pin[2], region_words = pin[3];
-    if (flags & 2) return fail(MPHF_E_INVALID, "offsets[0] must be 0");
-    if (flags & 1) return fail(MPHF_E_INVALID, "offsets must be non-decreasing");
-    if (flags & 4) return fail(MPHF_E_INVALID, "a set is too large for a batched build (ceil(gamma n) > 2^19)");
-    if (total && (!keys || !is_device_ptr(keys))) return fail(MPHF_E_INVALID, "keys must be device memory");
-    b->nkeys = total;
-    const uint64_t max_m = level_size(gamma, max_n);
-    tr.mark("batch prepare", (long)total);
-
-    // 2. every set's levels in one persistent launch; survivors and then the sorted fallback keys of
-    // set s stay in scratch[offsets[s] ..]
-    uint64_t *scratch, *region, *pre, *lpre;
-    uint32_t *bits32, *left32;
-    auto lay2 = [&](Carver& c) {
-        scratch = c.take<uint64_t>(total + 1);
-        region = c.take<uint64_t>(region_words + 1);
-        bits32 = c.take<uint32_t>(S1);
-        left32 = c.take<uint32_t>(S1);
-        pre = c.take<uint64_t>(S1);
-        lpre = c.take<uint64_t>(S1);
-    };
-    {
-        Carver m{nullptr};
-        lay2(m);
-        uint8_t* p = nullptr;
-        if ((st = temps.get(1, m.off, &p)) != MPHF_OK) return st;
-        Carver c{p};
-        lay2(c);
-    }
-    {
-        Carver m{nullptr};
-        m.take<BatchSet>(nsets);
-        m.take<BatchLevel>(nsets * o.max_levels);
-        uint8_t* p = nullptr;
-        if ((st = ar.alloc(&p, m.off, "set records")) != MPHF_OK) return st;
-        b->mem[0] = p;
-        Carver c{p};
-        b->sets = c.take<BatchSet>(nsets);
-        b->levels = c.take<BatchLevel>(nsets * o.max_levels);
-    }
-    int cus = 0;
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
-    const uint64_t lds = batch_lds_bytes(max_m, BATCH_LEFT_CAP);
-    const uint32_t per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 155000 / (lds + 1024)));
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(nsets, (uint64_t)cus * per_cu);
-    tr.mark("batch alloc");
-    HIP_TRY(launch_batch_build(keys, offsets, order, nsets, info + 2, scratch, region_w, gamma, b->seeds,
-                               o.max_levels, BATCH_LEFT_CAP, region, b->sets, b->levels, bits32, max_m, grid, s),
-            "batch build");
-    tr.mark("batch levels", (long)grid);
-    HIP_TRY(launch_batch_tally(b->sets, nsets, left32, bits32, fail32, s), "tally");
-    HIP_TRY(launch_exclusive_scan(bits32, pre, S1, tiles, s), "bit prefix");
-    HIP_TRY(launch_exclusive_scan(left32, lpre, S1, tiles, s), "leftover prefix");
-    HIP_TRY(hipMemcpyAsync(pin + 4, fail32, 8, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipMemcpyAsync(pin + 5, pre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipMemcpyAsync(pin + 6, lpre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
-    HIP_TRY(hipStreamSynchronize(s), "batch sync");
-    const uint32_t bad = (uint32_t)pin[4], first_bad = (uint32_t)(pin[4] >> 32);
-    if (bad & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(first_bad));
-    if (bad & 2u)
-        return fail(MPHF_E_INVALID, "set " + std::to_string(first_bad) +
-                                        " keeps more than 2048 keys after its last level (duplicates, or too few levels)");
-    const uint64_t tb = pin[5], tl = pin[6];
-    const uint64_t lev_slots = o.max_levels > 2 ? nsets * (o.max_levels - 2) : 0;
-    if (tb >= (1ull << HEAD_START_BITS) || total >= (1ull << HEAD_ONES_BITS))
-        return fail(MPHF_E_INVALID, "batch too large for the lookup records");
-    b->total_bits = tb;
-    b->nleft = tl;
-    b->nrank = (tb + 511) / 512;
-    b->nsec = sector_count(tb);
-    tr.mark("batch tally", (long)tb);
-
-    // 3. packed A, fallback keys, rank table (Section 3.1), lookup records and sectors
-    {
-        Carver m{nullptr};
-        m.take<BatchHead>(nsets);
-        m.take<BatchLev>(lev_slots + 1);
-        m.take<BatchAux>(nsets);
-        m.take<uint64_t>(tb / 64 + 1);
-        m.take<uint64_t>(tl + 1);
-        m.take<uint64_t>(b->nrank + 1);
-        m.take<uint32_t>(b->nsec * 16 + 16);
-        m.take<uint64_t>(super_count(b->nsec));
-        uint8_t* p = nullptr;
-        if ((st = ar.alloc(&p, m.off, "batch structure")) != MPHF_OK) return st;
-        b->mem[1] = p;
-        Carver c{p};
-        b->heads = c.take<BatchHead>(nsets);
-        b->lev = c.take<BatchLev>(lev_slots + 1);
-        b->aux = c.take<BatchAux>(nsets);
-        b->words = c.take<uint64_t>(tb / 64 + 1);
-        b->left = c.take<uint64_t>(tl + 1);
-        b->rank = c.take<uint64_t>(b->nrank + 1);
-        b->sec = c.take<uint32_t>(b->nsec * 16 + 16);
-        b->super = c.take<uint64_t>(super_count(b->nsec));
-    }
-    HIP_TRY(launch_batch_pack(region, region_w, b->sets, nsets, pre, lpre, scratch, offsets, b->words, b->left, s),
-            "pack");
-    if (b->nrank) {
-        // temporaries of the rank and sector scans, in the survivors' space (dead after the pack)
-        uint32_t *rc, *cnt;
-        uint64_t *rt, *spre, *stiles;
-        auto lay3 = [&](Carver& c) {
-            rc = c.take<uint32_t>(b->nrank);
-            rt = c.take<uint64_t>(scan_tmp_tiles(b->nrank));
-            cnt = c.take<uint32_t>(b->nsec);
-            spre = c.take<uint64_t>(b->nsec);
-            stiles = c.take<uint64_t>(scan_tmp_tiles(b->nsec));
+    BatchMem mem(ar, b->device, !planned && o.mem_budget == 0);
+    if ((st = batch_setup(b, keys, offsets, nsets, gamma, seed, o, planned, s, mem, pin)) != MPHF_OK) return st;
+    tr.mark("batch setup", (long)b->nkeys);
+    if (!planned) {
+        if (b->nkeys && !keys) return fail(MPHF_E_INVALID, "keys is NULL");
+        HIP_TRY(batch_levels(b, keys, s), "batch levels");
+        const uint64_t S1 = nsets + 1;
+        uint64_t *spre, *lpre, *tiles;
+        auto lay = [&](Carver& c) {
+            spre = c.take<uint64_t>(S1);
+            lpre = c.take<uint64_t>(S1);
+            tiles = c.take<uint64_t>(scan_tmp_tiles(S1));
         };
-        Carver m{nullptr};
-        lay3(m);
-        uint8_t* p = (uint8_t*)scratch;
-        if (m.off > (total + 1) * 8 && (st = ar.alloc(&p, m.off, "rank temporaries")) != MPHF_OK) return st;
-        Carver c{p};
-        lay3(c);
-        HIP_TRY(launch_rank(b->words, tb / 64, 512, b->rank, b->nrank, rc, rt, s), "rank");
-        HIP_TRY(launch_sectors(b->words, tb, b->sec, b->super, cnt, spre, stiles, s), "sectors");
+        if ((st = mem.transient(lay, "pack prefixes")) != MPHF_OK) return st;
+        HIP_TRY(launch_exclusive_scan(b->sec32, spre, S1, tiles, s), "sector prefix");
+        HIP_TRY(launch_exclusive_scan(b->left32, lpre, S1, tiles, s), "fallback prefix");
+        HIP_TRY(hipMemcpyAsync(pin + 5, b->fail32, 8, hipMemcpyDeviceToHost, s), "read back");
+        HIP_TRY(hipMemcpyAsync(pin + 6, spre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+        HIP_TRY(hipMemcpyAsync(pin + 7, lpre + nsets, 8, hipMemcpyDeviceToHost, s), "read back");
+        HIP_TRY(hipStreamSynchronize(s), "batch sync");
+        tr.mark("batch levels", (long)b->grid);
+        if ((st = batch_failure(pin[5])) != MPHF_OK) return st;
+        b->nsec = pin[6];
+        b->nleft = pin[7];
+        uint32_t* dsec;
+        uint64_t* dleft;
+        auto lay4 = [&](Carver& c) {
+            dsec = c.take<uint32_t>((b->nsec + 1) * SEC_WORDS);
+            dleft = c.take<uint64_t>(b->nleft + 1);
+        };
+        if ((st = mem.own(b, lay4, "batch structure")) != MPHF_OK) return st;
+        HIP_TRY(launch_batch_pack(b->sec, b->sets, nsets, spre, lpre, b->scratch, dsec, dleft, s), "pack");
+        HIP_TRY(launch_batch_heads(b->sets, b->levels, b->D, nsets, b->heads, b->lev, b->aux, s), "heads");
+        HIP_TRY(hipStreamSynchronize(s), "batch final sync");
+        tr.mark("batch structure");
+        b->sec = dsec;
+        b->left = dleft;
+        // the borrowed temporaries go back with the workspace lock
+        b->scratch = b->region = nullptr;
+        b->order = nullptr;
+        b->region_w = b->sreg_base = nullptr;
+        b->queue = nullptr;
+        b->fail32 = b->left32 = b->sec32 = nullptr;
+        b->offsets = nullptr;
+    } else {
+        HIP_TRY(hipStreamSynchronize(s), "plan sync");
     }
-    HIP_TRY(launch_batch_heads(b->sets, b->levels, o.max_levels, b->words, b->rank, 9, nsets, b->heads, b->lev,
-                               b->aux, s),
-            "heads");
-    HIP_TRY(hipStreamSynchronize(s), "batch final sync");
-    tr.mark("batch structure");
     for (void* p : b->mem) ar.keep(p);
     guard.b = nullptr;
     *out = b;
+    return MPHF_OK;
+}
+
+mphf_status batch_totals_of(mphf_batch* b, hipStream_t s) {
+    // sum of the sets' bits, their fallback keys and sectors (a planned batch: after a rebuild)
+    std::vector<BatchSet> hs(b->nsets);
+    HIP_TRY(hipMemcpyAsync(hs.data(), b->sets, b->nsets * sizeof(BatchSet), hipMemcpyDeviceToHost, s), "copy sets");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    uint64_t tb = 0, tl = 0, ts = 0;
+    for (const BatchSet& x : hs) {
+        tb += x.bits;
+        tl += x.nleft;
+        ts += (x.bits + SEC_BITS - 1) / SEC_BITS;
+    }
+    b->total_bits = tb;
+    b->used_left = tl;
+    b->used_sec = ts;
     return MPHF_OK;
 }
 
@@ -1207,7 +1268,44 @@ mphf_status mphf_build_batch(const uint64_t* keys, const uint64_t* offsets, uint
     mphf_opts o;
     if (opts) o = *opts;
     else mphf_default_opts(&o);
-    return build_batch_impl(keys, offsets, nsets, gamma, seed, o, (hipStream_t)stream, out);
+    mphf_status st = build_batch_impl(keys, offsets, nsets, gamma, seed, o, false, (hipStream_t)stream, out);
+    if (st == MPHF_OK && (st = batch_totals_of(*out, (hipStream_t)stream)) != MPHF_OK) {
+        free_batch(*out);
+        *out = nullptr;
+    }
+    return st;
+}
+
+mphf_status mphf_batch_plan(const uint64_t* offsets, uint64_t nsets, double gamma, uint64_t seed,
+                            const mphf_opts* opts, void* stream, mphf_batch_t** out) {
+    if (!out) return fail(MPHF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    mphf_opts o;
+    if (opts) o = *opts;
+    else mphf_default_opts(&o);
+    return build_batch_impl(nullptr, offsets, nsets, gamma, seed, o, true, (hipStream_t)stream, out);
+}
+
+mphf_status mphf_batch_rebuild(mphf_batch_t* b, const uint64_t* keys, void* stream) {
+    if (!b) return fail(MPHF_E_INVALID, "handle is NULL");
+    if (!b->planned) return fail(MPHF_E_INVALID, "the batch was not planned");
+    if (b->nkeys && !keys) return fail(MPHF_E_INVALID, "keys is NULL");
+    const hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(batch_levels(b, keys, s), "batch levels");
+    HIP_TRY(launch_batch_heads(b->sets, b->levels, b->D, b->nsets, b->heads, b->lev, b->aux, s), "heads");
+    return MPHF_OK;
+}
+
+mphf_status mphf_batch_status(mphf_batch_t* b, void* stream) {
+    if (!b) return fail(MPHF_E_INVALID, "handle is NULL");
+    if (!b->planned) return MPHF_OK;
+    uint64_t* pin = batch_pinned(b->device);
+    if (!pin) return fail(MPHF_E_NOMEM, "pinned read-back buffer");
+    HIP_TRY(hipMemcpyAsync(pin, b->fail32, 8, hipMemcpyDeviceToHost, (hipStream_t)stream), "read back");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "sync");
+    mphf_status st = batch_failure(pin[0]);
+    if (st != MPHF_OK) return st;
+    return batch_totals_of(b, (hipStream_t)stream);
 }
 
 mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, const uint64_t* keys,
@@ -1216,8 +1314,8 @@ mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, co
     if (!n) return MPHF_OK;
     if (!set_ids || !keys || !out || !is_device_ptr(set_ids) || !is_device_ptr(keys) || !is_device_ptr(out))
         return fail(MPHF_E_INVALID, "set_ids, keys and out must be device memory");
-    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->heads, b->lev, b->aux, b->D, b->nsets, b->sec, b->super,
-                                b->left, b->seeds, (hipStream_t)stream),
+    HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->heads, b->lev, b->aux, b->D, b->nsets, b->sec, b->left,
+                                b->seeds, (hipStream_t)stream),
             "batch lookup");
     return MPHF_OK;
 }
@@ -1251,10 +1349,29 @@ mphf_status mphf_batch_export_set(const mphf_batch_t* b, uint64_t set, uint64_t*
     HIP_TRY(hipMemcpy(&bs, b->sets + set, sizeof(bs), hipMemcpyDeviceToHost), "copy set");
     if ((words && nwords != bs.bits / 64) || (fallback_keys && nfb != bs.nleft))
         return fail(MPHF_E_INVALID, "export sizes differ from the set's");
-    if (words && nwords)
-        HIP_TRY(hipMemcpy(words, b->words + bs.start_bit / 64, nwords * 8, hipMemcpyDeviceToHost), "copy bits");
+    if (words && nwords) {
+        // the set's bits are words 1..15 of each of its sectors
+        const uint64_t ns = (bs.bits + SEC_BITS - 1) / SEC_BITS;
+        std::vector<uint32_t> secs(ns * SEC_WORDS);
+        HIP_TRY(hipMemcpy(secs.data(), b->sec + bs.sec_base * SEC_WORDS, secs.size() * 4, hipMemcpyDeviceToHost),
+                "copy sectors");
+        uint32_t* w32 = (uint32_t*)words;
+        for (uint64_t i = 0; i < 2 * nwords; ++i) w32[i] = secs[(i / 15) * SEC_WORDS + 1 + i % 15];
+    }
     if (fallback_keys && nfb)
         HIP_TRY(hipMemcpy(fallback_keys, b->left + bs.left_off, nfb * 8, hipMemcpyDeviceToHost), "copy fallback");
+    return MPHF_OK;
+}
+
+mphf_status mphf_batch_export_sectors(const mphf_batch_t* b, uint64_t set, uint32_t* sectors, uint64_t nsectors) {
+    if (!b || !sectors) return fail(MPHF_E_INVALID, "NULL argument");
+    if (set >= b->nsets) return fail(MPHF_E_INVALID, "no such set");
+    BatchSet bs;
+    HIP_TRY(hipMemcpy(&bs, b->sets + set, sizeof(bs), hipMemcpyDeviceToHost), "copy set");
+    if (nsectors != (bs.bits + SEC_BITS - 1) / SEC_BITS) return fail(MPHF_E_INVALID, "export size differs");
+    if (nsectors)
+        HIP_TRY(hipMemcpy(sectors, b->sec + bs.sec_base * SEC_WORDS, nsectors * SEC_WORDS * 4, hipMemcpyDeviceToHost),
+                "copy sectors");
     return MPHF_OK;
 }
 
@@ -1264,8 +1381,11 @@ mphf_status mphf_batch_totals(const mphf_batch_t* b, uint64_t* nsets, uint64_t* 
     if (nsets) *nsets = b->nsets;
     if (nkeys) *nkeys = b->nkeys;
     if (total_bits) *total_bits = b->total_bits;
-    if (bits_per_key)
-        *bits_per_key = b->nkeys ? (double)(b->total_bits + 64 * b->nrank + 64 * b->nleft) / (double)b->nkeys : 0.0;
+    if (bits_per_key) {
+        // the packed structure: lookup sectors, 16-byte heads and fallback keys
+        const double bits = 512.0 * (double)b->used_sec + 128.0 * (double)b->nsets + 64.0 * (double)b->used_left;
+        *bits_per_key = b->nkeys ? bits / (double)b->nkeys : 0.0;
+    }
     return MPHF_OK;
 }
 

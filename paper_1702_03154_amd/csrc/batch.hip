@@ -1,16 +1,20 @@
 // Batched construction: many independent key sets built in one persistent launch.
 //
-// A preparation pass checks the set offsets, sizes each set's worst-case region of bits (every key
+// A preparation pass checks the set offsets, sizes each set's worst-case regions (every key
 // surviving every level) and orders the sets by size class, largest first.  Each workgroup of the
 // build kernel then takes sets from an atomic work queue in that order and builds every level of
 // its set by itself (Algorithms 1 and 2): the level's A and C bits live in LDS, the keys of the level
 // are streamed from global memory (the set's own keys at level 0, its survivors in a scratch region
-// after that, compacted in place), and the finalized A words go to the set's region of an unpacked
-// bit buffer.  A second kernel packs the sets' bits into one concatenated array in set order; the rank
-// table and the lookup sectors are then built over it like for a single function.  Set s gets labels
-// 1..n_s: the ones of A before the key's bit minus the ones before the set's first bit, plus one.
-// Every set's levels, bits and labels equal those of a standalone build of that set, since the levels
-// depend only on the set's keys, gamma and the level seeds.
+// after that, compacted in place), and the finalized A words go to the set's staging region.  When
+// the set is done the workgroup writes the set's lookup sectors: 480 bits each with a counter of the
+// ones of the set before the sector, so a label is the rank within the set plus one (Section 2.2,
+// "Minimality", applied to the set alone).  Every set's levels, bits and labels equal those of a
+// standalone build of that set, since the levels depend only on the set's keys, gamma and the
+// level seeds.
+//
+// Nothing in a build after the preparation depends on a value read back by the host, so a planned
+// batch rebuilds with a fixed sequence of launches (capturable in a HIP graph).  The one-shot build
+// additionally packs the sectors and fallback keys densely once their sizes are known.
 #include <cmath>
 
 #include "internal.h"
@@ -32,12 +36,13 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Per set: worst-case region words, size class histogram, offset checks and the largest set.
-// info[0]: largest n (atomicMax); info[1]: flags (1 offsets decrease, 2 offsets[0] != 0, 4 a set too
-// large for the LDS levels).
+// Per set: worst-case staging words and lookup sectors, size class histogram, offset checks and the
+// largest set.  info[0]: largest n (atomicMax); info[1]: flags (1 offsets decrease, 2 offsets[0] != 0,
+// 4 a set too large for the LDS levels).
 __global__ void __launch_bounds__(PT)
 k_batch_prepare(const uint64_t* __restrict__ offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
-                uint32_t* __restrict__ bound, uint32_t* __restrict__ hist, unsigned long long* __restrict__ info) {
+                uint32_t* __restrict__ bound, uint32_t* __restrict__ sbound, uint32_t* __restrict__ hist,
+                unsigned long long* __restrict__ info) {
     __shared__ uint32_t lh[NCLASS];
     __shared__ unsigned long long smax;
     __shared__ uint32_t sflags;
@@ -53,6 +58,7 @@ k_batch_prepare(const uint64_t* __restrict__ offsets, uint64_t nsets, double gam
     for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s <= nsets; s += stride) {
         if (s == nsets) {
             bound[s] = 0;
+            sbound[s] = 0;
             continue;
         }
         const uint64_t a = offsets[s], b = offsets[s + 1];
@@ -60,10 +66,15 @@ k_batch_prepare(const uint64_t* __restrict__ offsets, uint64_t nsets, double gam
         if (b < a) flags |= 1;
         const uint64_t n = b >= a ? b - a : 0;
         const double dm = ceil(gamma * (double)n);
-        uint32_t w = 0;
-        if (dm > (double)max_m) flags |= 4;
-        else if (n) w = D * (uint32_t)(((uint64_t)dm + 63) >> 6);
+        uint32_t w = 0, ns = 0;
+        if (dm > (double)max_m) {
+            flags |= 4;
+        } else if (n) {
+            w = D * (uint32_t)(((uint64_t)dm + 63) >> 6);
+            ns = (uint32_t)(((uint64_t)w * 64 + SEC_BITS - 1) / SEC_BITS);
+        }
         bound[s] = w;
+        sbound[s] = ns;
         my_max = n > my_max ? n : my_max;
         atomicAdd(&lh[size_class(n)], 1u);
     }
@@ -110,15 +121,25 @@ k_batch_order(const uint64_t* __restrict__ offsets, uint64_t nsets, const uint32
     }
 }
 
+// Start of every build: empty work queue, no failure (fail[1] is the first failing set).
+__global__ void k_batch_reset(unsigned long long* queue, uint32_t* fail) {
+    if (threadIdx.x == 0) {
+        *queue = 0;
+        fail[0] = 0;
+        fail[1] = 0xFFFFFFFFu;
+    }
+}
+
 // One workgroup builds one set at a time.
 __global__ void __launch_bounds__(BW)
 k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ offsets,
               const uint32_t* __restrict__ order, uint64_t nsets, unsigned long long* next,
               uint64_t* __restrict__ scratch, const uint64_t* __restrict__ region_w, double gamma,
               SeedTable seeds, uint32_t D, uint32_t left_cap, uint64_t* __restrict__ region,
-              BatchSet* __restrict__ sets, BatchLevel* __restrict__ levels, uint32_t* __restrict__ bits32) {
+              uint32_t* __restrict__ sreg, const uint64_t* __restrict__ sreg_base,
+              BatchSet* __restrict__ sets, BatchLevel* __restrict__ levels) {
     extern __shared__ uint32_t lds[];
-    __shared__ uint32_t wsum[NWAVE];
+    __shared__ uint32_t wsum[NWAVE + 1];
     __shared__ unsigned long long s_item;
     __shared__ uint32_t s_status;
     __shared__ LevelHash s_L;
@@ -253,37 +274,64 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
             }
         }
         __syncthreads();
+        // the set's lookup sectors from its staged bits (written above by this workgroup)
+        {
+            const uint32_t* A32 = (const uint32_t*)A;
+            const uint64_t w32 = off >> 5;
+            const uint64_t nsec = (off + SEC_BITS - 1) / SEC_BITS;
+            uint4* S = (uint4*)(sreg + sreg_base[s] * SEC_WORDS);
+            uint32_t run = 0;
+            for (uint64_t c0 = 0; c0 < nsec; c0 += BW) {
+                const uint64_t k = c0 + threadIdx.x;
+                uint32_t e[15];
+                uint32_t c = 0;
+#pragma unroll
+                for (int j = 0; j < 15; ++j) {
+                    const uint64_t idx = 15 * k + j;
+                    e[j] = (k < nsec && idx < w32) ? A32[idx] : 0u;
+                    c += __popc(e[j]);
+                }
+                uint32_t tot;
+                const uint32_t ex = block_exclusive_sum<BW>(c, wsum, &tot);
+                if (k < nsec) {
+                    S[4 * k + 0] = make_uint4(run + ex, e[0], e[1], e[2]);
+                    S[4 * k + 1] = make_uint4(e[3], e[4], e[5], e[6]);
+                    S[4 * k + 2] = make_uint4(e[7], e[8], e[9], e[10]);
+                    S[4 * k + 3] = make_uint4(e[11], e[12], e[13], e[14]);
+                }
+                run += tot;
+            }
+        }
         if (threadIdx.x == 0) {
             BatchSet& st = sets[s];
             st.n = offsets[s + 1] - k0;
-            st.start_bit = 0;
+            st.sec_base = sreg_base[s];
             st.bits = off;
-            st.ones_before = 0;
-            st.left_off = 0;
+            st.left_off = k0;
             st.nlev = d;
             st.nleft = (uint32_t)n;
             st.status = s_status | (n > left_cap ? 2u : 0u);
             st.pad = 0;
-            bits32[s] = (uint32_t)off;
         }
         __syncthreads();
     }
 }
 
-// Per set: the leftover count (input of a prefix scan; the bit counts are already in bits32), and
-// the OR of the statuses with the first failing set.  fail[0]: OR of statuses; fail[1]: first bad set.
+// Per set: fallback-key and sector counts (inputs of the dense packing's prefix scans), and the OR
+// of the statuses with the first failing set.  fail[0]: OR of statuses; fail[1]: first bad set.
 __global__ void __launch_bounds__(PT)
 k_batch_tally(const BatchSet* __restrict__ sets, uint64_t nsets, uint32_t* __restrict__ left32,
-              uint32_t* __restrict__ bits32, uint32_t* __restrict__ fail) {
+              uint32_t* __restrict__ sec32, uint32_t* __restrict__ fail) {
     const uint64_t stride = (uint64_t)gridDim.x * PT;
     for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s <= nsets; s += stride) {
         if (s == nsets) {
             left32[s] = 0;
-            bits32[s] = 0;
+            sec32[s] = 0;
             continue;
         }
         const BatchSet st = sets[s];
         left32[s] = st.nleft;
+        sec32[s] = (uint32_t)((st.bits + SEC_BITS - 1) / SEC_BITS);
         if (st.status) {
             atomicOr(&fail[0], st.status);
             atomicMin(&fail[1], (uint32_t)s);
@@ -291,48 +339,38 @@ k_batch_tally(const BatchSet* __restrict__ sets, uint64_t nsets, uint32_t* __res
     }
 }
 
-// Packs every set's bits and fallback keys at their packed offsets; one workgroup per set.
-__global__ void k_batch_pack(const uint64_t* __restrict__ region, const uint64_t* __restrict__ region_w,
-                             BatchSet* __restrict__ sets, const uint64_t* __restrict__ bit_pre,
-                             const uint64_t* __restrict__ left_pre, const uint64_t* __restrict__ left_sorted,
-                             const uint64_t* __restrict__ offsets, uint64_t* __restrict__ words,
+// Dense copy of every set's sectors and fallback keys; one workgroup per set.
+__global__ void k_batch_pack(const uint32_t* __restrict__ sreg, BatchSet* __restrict__ sets,
+                             const uint64_t* __restrict__ sec_pre, const uint64_t* __restrict__ left_pre,
+                             const uint64_t* __restrict__ scratch, uint32_t* __restrict__ sec,
                              uint64_t* __restrict__ left) {
     const uint64_t s = blockIdx.x;
-    const uint64_t start = bit_pre[s];
-    const uint64_t nw = sets[s].bits / 64;
-    const uint64_t* src = region + region_w[s];
-    uint64_t* dst = words + start / 64;
-    for (uint64_t j = threadIdx.x; j < nw; j += blockDim.x) dst[j] = src[j];
-    const uint32_t nl = sets[s].nleft;
-    for (uint32_t j = threadIdx.x; j < nl; j += blockDim.x) left[left_pre[s] + j] = left_sorted[offsets[s] + j];
+    const BatchSet st = sets[s];
+    const uint64_t n4 = 4 * ((st.bits + SEC_BITS - 1) / SEC_BITS);
+    const uint4* src = (const uint4*)(sreg + st.sec_base * SEC_WORDS);
+    uint4* dst = (uint4*)(sec + sec_pre[s] * SEC_WORDS);
+    for (uint64_t j = threadIdx.x; j < n4; j += blockDim.x) dst[j] = src[j];
+    for (uint32_t j = threadIdx.x; j < st.nleft; j += blockDim.x) left[left_pre[s] + j] = scratch[st.left_off + j];
+    __syncthreads();
     if (threadIdx.x == 0) {
-        sets[s].start_bit = start;
+        sets[s].sec_base = sec_pre[s];
         sets[s].left_off = left_pre[s];
     }
 }
 
-// Per set: the ones of A before the set (from the rank table, sampled every 2^rank_shift bits) and
-// the lookup records: the 16-byte head, levels 2.. in the set's D - 2 slots, the fallback record.
+// Per set: the lookup records: the 16-byte head, levels 2.. in the set's D - 2 slots, the fallback
+// record.
 __global__ void __launch_bounds__(PT)
-k_batch_heads(BatchSet* __restrict__ sets, const BatchLevel* __restrict__ levels, uint32_t D,
-              const uint64_t* __restrict__ words, const uint64_t* __restrict__ rank, uint32_t rank_shift,
+k_batch_heads(const BatchSet* __restrict__ sets, const BatchLevel* __restrict__ levels, uint32_t D,
               uint64_t nsets, BatchHead* __restrict__ heads, BatchLev* __restrict__ lev, BatchAux* __restrict__ aux) {
     const uint64_t stride = (uint64_t)gridDim.x * PT;
     for (uint64_t s = (uint64_t)blockIdx.x * PT + threadIdx.x; s < nsets; s += stride) {
         const BatchSet st = sets[s];
-        uint64_t r = 0;
-        if (st.bits) {
-            const uint64_t g = st.start_bit;   // a multiple of 64
-            const uint64_t b = g >> rank_shift;
-            r = rank[b];
-            for (uint64_t k = (b << rank_shift) >> 6; k < (g >> 6); ++k) r += __popcll(words[k]);
-        }
-        sets[s].ones_before = r;
         const BatchLevel* L = levels + s * D;
         const uint64_t m0 = st.nlev > 0 ? L[0].m : 0, m1 = st.nlev > 1 ? L[1].m : 0;
         BatchHead h;
-        h.a = st.start_bit | (m0 << HEAD_START_BITS);
-        h.b = r | (m1 << HEAD_ONES_BITS) | ((uint64_t)st.nlev << (HEAD_ONES_BITS + HEAD_M_BITS));
+        h.a = st.sec_base | (m0 << HEAD_BASE_BITS);
+        h.b = m1 | ((uint64_t)st.nlev << HEAD_M_BITS);
         heads[s] = h;
         BatchAux x;
         x.left_off = st.left_off;
@@ -365,12 +403,12 @@ __device__ __forceinline__ uint32_t mod_small(uint64_t h, uint32_t m, double rm)
     return (uint32_t)r;
 }
 
-// Lookup of (set, key) pairs: Algorithm 3 within the set, ranks through the sector layout.
+// Lookup of (set, key) pairs: Algorithm 3 within the set, ranks through the set's sectors.
 __global__ void __launch_bounds__(256)
 k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict__ q, uint64_t n,
                uint64_t* __restrict__ out, const BatchHead* __restrict__ heads, const BatchLev* __restrict__ lev,
                const BatchAux* __restrict__ aux, uint32_t D, uint64_t nsets, const uint32_t* __restrict__ sec,
-               const uint64_t* __restrict__ super, const uint64_t* __restrict__ left, SeedTable seeds) {
+               const uint64_t* __restrict__ left, SeedTable seeds) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint64_t s = set_ids[i];
@@ -378,11 +416,10 @@ k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict_
         uint64_t label = 0;
         if (s < nsets) {
             const BatchHead h = heads[s];
-            const uint64_t start = h.a & ((1ull << HEAD_START_BITS) - 1);
-            const uint32_t m0 = (uint32_t)(h.a >> HEAD_START_BITS);
-            const uint64_t ones = h.b & ((1ull << HEAD_ONES_BITS) - 1);
-            const uint32_t m1 = (uint32_t)(h.b >> HEAD_ONES_BITS) & ((1u << HEAD_M_BITS) - 1);
-            const uint32_t nlev = (uint32_t)(h.b >> (HEAD_ONES_BITS + HEAD_M_BITS));
+            const uint64_t base = h.a & ((1ull << HEAD_BASE_BITS) - 1);
+            const uint32_t m0 = (uint32_t)(h.a >> HEAD_BASE_BITS);
+            const uint32_t m1 = (uint32_t)h.b & ((1u << HEAD_M_BITS) - 1);
+            const uint32_t nlev = (uint32_t)(h.b >> HEAD_M_BITS);
             bool found = false;
             for (uint32_t d = 0; d < nlev; ++d) {
                 uint32_t m, off;
@@ -397,11 +434,11 @@ k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict_
                     m = e.m;
                     off = e.off;
                 }
-                const uint32_t pos = mod_small(fmix64(x ^ seeds.s[d]), m, 1.0 / (double)m);
-                uint64_t rank;
-                const uint64_t g = start + off + pos;
-                if (sector_rank(sec, super, g, &rank)) {
-                    label = rank - ones + 1;
+                const uint32_t g = off + mod_small(fmix64(x ^ seeds.s[d]), m, 1.0 / (double)m);
+                const uint32_t j = g / (uint32_t)SEC_BITS;
+                uint32_t c;
+                if (sector_probe(sec, base + j, g - j * (uint32_t)SEC_BITS, &c)) {
+                    label = (uint64_t)c + 1;
                     found = true;
                     break;
                 }
@@ -433,9 +470,10 @@ uint32_t prep_grid(uint64_t items) {
 uint32_t batch_classes() { return NCLASS; }
 
 hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
-                                uint32_t* bound, uint32_t* hist, unsigned long long* info, hipStream_t s) {
+                                uint32_t* bound, uint32_t* sbound, uint32_t* hist, unsigned long long* info,
+                                hipStream_t s) {
     hipLaunchKernelGGL(k_batch_prepare, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, offsets, nsets, gamma, D,
-                       max_m, bound, hist, info);
+                       max_m, bound, sbound, hist, info);
     return hipGetLastError();
 }
 
@@ -445,21 +483,27 @@ hipError_t launch_batch_order(const uint64_t* offsets, uint64_t nsets, const uin
     return hipGetLastError();
 }
 
+hipError_t launch_batch_reset(unsigned long long* queue, uint32_t* fail, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, queue, fail);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
                               uint64_t nsets, unsigned long long* next, uint64_t* scratch,
                               const uint64_t* region_w, double gamma, const SeedTable& seeds,
-                              uint32_t D, uint32_t left_cap, uint64_t* region, BatchSet* sets,
-                              BatchLevel* levels, uint32_t* bits32, uint64_t max_m, uint32_t grid,
-                              hipStream_t s) {
+                              uint32_t D, uint32_t left_cap, uint64_t* region, uint32_t* sreg,
+                              const uint64_t* sreg_base, BatchSet* sets, BatchLevel* levels, uint64_t max_m,
+                              uint32_t grid, hipStream_t s) {
     const uint64_t lds = batch_lds_bytes(max_m, left_cap);
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_batch_build,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
     hipLaunchKernelGGL(k_batch_build, dim3(grid), dim3(BW), (unsigned)lds, s, keys, offsets, order, nsets,
-                       next, scratch, region_w, gamma, seeds, D, left_cap, region, sets, levels, bits32);
+                       next, scratch, region_w, gamma, seeds, D, left_cap, region, sreg, sreg_base, sets, levels);
     return hipGetLastError();
+}
+
+hipError_t batch_kernel_setup(uint64_t max_m, uint32_t left_cap) {
+    const uint64_t lds = batch_lds_bytes(max_m, left_cap);
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)k_batch_build, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap) {
@@ -469,41 +513,39 @@ uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap) {
     return lds;
 }
 
-hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* bits32,
+hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* sec32,
                               uint32_t* fail, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_tally, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, sets, nsets, left32, bits32,
+    hipLaunchKernelGGL(k_batch_tally, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, sets, nsets, left32, sec32,
                        fail);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_w, BatchSet* sets,
-                             uint64_t nsets, const uint64_t* bit_pre, const uint64_t* left_pre,
-                             const uint64_t* left_sorted, const uint64_t* offsets, uint64_t* words,
-                             uint64_t* left, hipStream_t s) {
+hipError_t launch_batch_pack(const uint32_t* sreg, BatchSet* sets, uint64_t nsets, const uint64_t* sec_pre,
+                             const uint64_t* left_pre, const uint64_t* scratch, uint32_t* sec, uint64_t* left,
+                             hipStream_t s) {
     if (!nsets) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_pack, dim3((unsigned)nsets), dim3(256), 0, s, region, region_w, sets, bit_pre,
-                       left_pre, left_sorted, offsets, words, left);
+    hipLaunchKernelGGL(k_batch_pack, dim3((unsigned)nsets), dim3(256), 0, s, sreg, sets, sec_pre, left_pre, scratch,
+                       sec, left);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_heads(BatchSet* sets, const BatchLevel* levels, uint32_t D, const uint64_t* words,
-                              const uint64_t* rank, uint32_t rank_shift, uint64_t nsets, BatchHead* heads,
-                              BatchLev* lev, BatchAux* aux, hipStream_t s) {
+hipError_t launch_batch_heads(const BatchSet* sets, const BatchLevel* levels, uint32_t D, uint64_t nsets,
+                              BatchHead* heads, BatchLev* lev, BatchAux* aux, hipStream_t s) {
     if (!nsets) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_heads, dim3(prep_grid(nsets)), dim3(PT), 0, s, sets, levels, D, words, rank,
-                       rank_shift, nsets, heads, lev, aux);
+    hipLaunchKernelGGL(k_batch_heads, dim3(prep_grid(nsets)), dim3(PT), 0, s, sets, levels, D, nsets, heads, lev,
+                       aux);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
                                const BatchHead* heads, const BatchLev* lev, const BatchAux* aux, uint32_t D,
-                               uint64_t nsets, const uint32_t* sec, const uint64_t* super, const uint64_t* left,
-                               const SeedTable& seeds, hipStream_t s) {
+                               uint64_t nsets, const uint32_t* sec, const uint64_t* left, const SeedTable& seeds,
+                               hipStream_t s) {
     if (!n) return hipSuccess;
     uint64_t blocks = (n + 1023) / 1024;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_batch_lookup, dim3((unsigned)blocks), dim3(256), 0, s, set_ids, q, n, out, heads, lev, aux,
-                       D, nsets, sec, super, left, seeds);
+                       D, nsets, sec, left, seeds);
     return hipGetLastError();
 }
 

@@ -96,12 +96,10 @@ constexpr uint64_t SEC_BITS = 480;
 constexpr uint32_t SEC_WORDS = 16;
 constexpr uint32_t SUPER_SHIFT = 21;
 
-// If bit g of A is set: *rank = the ones of A before g, and true.
-__device__ __forceinline__ bool sector_rank(const uint32_t* __restrict__ sec,
-                                            const uint64_t* __restrict__ super, uint64_t g,
-                                            uint64_t* rank) {
-    const uint64_t j = g / SEC_BITS;
-    const uint32_t r = (uint32_t)(g - j * SEC_BITS);
+// If bit r (< 480) of sector j is set: *count = the sector's counter plus the ones of the sector
+// before bit r, and true.
+__device__ __forceinline__ bool sector_probe(const uint32_t* __restrict__ sec, uint64_t j, uint32_t r,
+                                             uint32_t* count) {
     const uint32_t t = 1 + (r >> 5), b = r & 31u;   // the bit's u32 word in the sector
     const uint4* s4 = (const uint4*)(sec + j * SEC_WORDS);
     uint4 v[4];
@@ -114,15 +112,26 @@ __device__ __forceinline__ bool sector_rank(const uint32_t* __restrict__ sec,
     for (uint32_t k = 1; k < SEC_WORDS; ++k)
         if (k == t) w = e[k];
     if (!((w >> b) & 1u)) return false;
-    // superblock + sector counter + whole words before t + bits of t below g
-    uint64_t acc = super[j >> SUPER_SHIFT] + e[0];
+    // sector counter + whole words before t + bits of t below r
+    uint32_t acc = e[0];
     const uint32_t mask = (1u << b) - 1u;
 #pragma unroll
     for (uint32_t k = 1; k < SEC_WORDS; ++k) {
         if (k < t) acc += __popc(e[k]);
         else if (k == t) acc += __popc(e[k] & mask);
     }
-    *rank = acc;
+    *count = acc;
+    return true;
+}
+
+// If bit g of A is set: *rank = the ones of A before g, and true.
+__device__ __forceinline__ bool sector_rank(const uint32_t* __restrict__ sec,
+                                            const uint64_t* __restrict__ super, uint64_t g,
+                                            uint64_t* rank) {
+    const uint64_t j = g / SEC_BITS;
+    uint32_t c;
+    if (!sector_probe(sec, j, (uint32_t)(g - j * SEC_BITS), &c)) return false;
+    *rank = super[j >> SUPER_SHIFT] + c;
     return true;
 }
 

@@ -37,10 +37,9 @@ struct TailSummary {
 // Batched builds: per set and per (set, level) records.
 struct BatchSet {
     uint64_t n;            // keys of the set
-    uint64_t start_bit;    // first bit of the set in the packed A
+    uint64_t sec_base;     // first of the set's lookup sectors
     uint64_t bits;         // bits of the set's levels (64-bit padded)
-    uint64_t ones_before;  // ones of the packed A before start_bit
-    uint64_t left_off;     // first of the set's fallback keys in the packed fallback array
+    uint64_t left_off;     // first of the set's fallback keys in the fallback array
     uint32_t nlev;
     uint32_t nleft;
     uint32_t status;       // bit 0: duplicate keys; bit 1: too many leftovers for the batch kernel
@@ -54,20 +53,21 @@ struct BatchLevel {
     uint32_t sh;           // sh1 | sh2 << 8
 };
 
-// What a batched lookup reads first for set s: 16 bytes with the set's first bit in the packed A
-// (44 bits) and m0 (20 bits) in word a, and the ones before the set (37 bits), m1 (20 bits) and the
-// level count (7 bits) in word b.  Level 1 starts at bit (m0 + 63) & ~63 of the set; levels 2.. are
+// What a batched lookup reads first for set s: 16 bytes with the set's first lookup sector
+// (44 bits) and m0 (20 bits) in word a, and m1 (20 bits) and the level count (7 bits) in word b.
+// A set's sectors hold its own bits with counters of the ones of the set before each sector, so a
+// label is that rank plus one.  Level 1 starts at bit (m0 + 63) & ~63 of the set; levels 2.. are
 // BatchLev records in D - 2 slots per set, and the fallback table is described by BatchAux.
 struct __attribute__((aligned(16))) BatchHead {
     uint64_t a, b;
 };
-constexpr uint32_t HEAD_START_BITS = 44, HEAD_ONES_BITS = 37, HEAD_M_BITS = 20;
+constexpr uint32_t HEAD_BASE_BITS = 44, HEAD_M_BITS = 20;
 struct BatchLev {
     uint32_t m;
     uint32_t off;          // bit offset of the level inside the set
 };
 struct BatchAux {
-    uint64_t left_off;     // first of the set's fallback keys in the packed fallback array
+    uint64_t left_off;     // first of the set's fallback keys in the fallback array
     uint32_t n;
     uint32_t nleft;
 };
@@ -132,28 +132,29 @@ hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L
 
 uint32_t batch_classes();
 hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
-                                uint32_t* bound, uint32_t* hist, unsigned long long* info, hipStream_t s);
+                                uint32_t* bound, uint32_t* sbound, uint32_t* hist, unsigned long long* info,
+                                hipStream_t s);
 hipError_t launch_batch_order(const uint64_t* offsets, uint64_t nsets, const uint32_t* hist, uint32_t* cursor,
                               uint32_t* order, hipStream_t s);
+hipError_t launch_batch_reset(unsigned long long* queue, uint32_t* fail, hipStream_t s);
 hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
                               uint64_t nsets, unsigned long long* next, uint64_t* scratch,
                               const uint64_t* region_w, double gamma, const SeedTable& seeds,
-                              uint32_t D, uint32_t left_cap, uint64_t* region, BatchSet* sets,
-                              BatchLevel* levels, uint32_t* bits32, uint64_t max_m, uint32_t grid,
-                              hipStream_t s);
+                              uint32_t D, uint32_t left_cap, uint64_t* region, uint32_t* sreg,
+                              const uint64_t* sreg_base, BatchSet* sets, BatchLevel* levels, uint64_t max_m,
+                              uint32_t grid, hipStream_t s);
 uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap);
-hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* bits32,
+hipError_t batch_kernel_setup(uint64_t max_m, uint32_t left_cap);   // once per size, before any launch
+hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* sec32,
                               uint32_t* fail, hipStream_t s);
-hipError_t launch_batch_pack(const uint64_t* region, const uint64_t* region_w, BatchSet* sets,
-                             uint64_t nsets, const uint64_t* bit_pre, const uint64_t* left_pre,
-                             const uint64_t* left_sorted, const uint64_t* offsets, uint64_t* words,
-                             uint64_t* left, hipStream_t s);
-hipError_t launch_batch_heads(BatchSet* sets, const BatchLevel* levels, uint32_t D, const uint64_t* words,
-                              const uint64_t* rank, uint32_t rank_shift, uint64_t nsets, BatchHead* heads,
-                              BatchLev* lev, BatchAux* aux, hipStream_t s);
+hipError_t launch_batch_pack(const uint32_t* sreg, BatchSet* sets, uint64_t nsets, const uint64_t* sec_pre,
+                             const uint64_t* left_pre, const uint64_t* scratch, uint32_t* sec, uint64_t* left,
+                             hipStream_t s);
+hipError_t launch_batch_heads(const BatchSet* sets, const BatchLevel* levels, uint32_t D, uint64_t nsets,
+                              BatchHead* heads, BatchLev* lev, BatchAux* aux, hipStream_t s);
 hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint64_t n, uint64_t* out,
                                const BatchHead* heads, const BatchLev* lev, const BatchAux* aux, uint32_t D,
-                               uint64_t nsets, const uint32_t* sec, const uint64_t* super, const uint64_t* left,
-                               const SeedTable& seeds, hipStream_t s);
+                               uint64_t nsets, const uint32_t* sec, const uint64_t* left, const SeedTable& seeds,
+                               hipStream_t s);
 
 }  // namespace mphfk

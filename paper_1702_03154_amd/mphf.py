@@ -91,6 +91,10 @@ def lib() -> C.CDLL:
             "mphf_batch_totals": (st, [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                        C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
             "mphf_batch_destroy": (None, [vp]),
+            "mphf_batch_plan": (st, [vp, u64, C.c_double, u64, C.POINTER(Opts), vp, C.POINTER(vp)]),
+            "mphf_batch_rebuild": (st, [vp, vp, vp]),
+            "mphf_batch_status": (st, [vp, vp]),
+            "mphf_batch_export_sectors": (st, [vp, u64, vp, u64]),
             "mphf_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -232,6 +236,36 @@ class Batch:
             _check(L.mphf_build_batch(kp, _dev(offsets, "offsets"), offsets.numel() - 1, float(gamma),
                                       seed & (2**64 - 1), C.byref(o), _stream(stream), C.byref(h)))
         return cls(h.value, keys.device)
+
+    @classmethod
+    def plan(cls, offsets: torch.Tensor, gamma: float = 2.0, seed: int = 0, max_levels: int = 25,
+             stream=None) -> "Batch":
+        """A planned batch for these set sizes; fill it with :meth:`rebuild`."""
+        L = lib()
+        o = Opts(max_levels, 512, 0, 0, 0)
+        h = C.c_void_p()
+        with torch.cuda.device(offsets.device):
+            _check(L.mphf_batch_plan(_dev(offsets, "offsets"), offsets.numel() - 1, float(gamma),
+                                     seed & (2**64 - 1), C.byref(o), _stream(stream), C.byref(h)))
+        return cls(h.value, offsets.device)
+
+    def rebuild(self, keys: torch.Tensor, stream=None) -> "Batch":
+        """Enqueue the build of a planned batch (launches only; capturable in a graph)."""
+        kp = _dev(keys, "keys") if keys.numel() else 0
+        _check(lib().mphf_batch_rebuild(self._h, kp, _stream(stream)))
+        return self
+
+    def status(self, stream=None) -> "Batch":
+        """Wait for the stream and raise if the last build of a planned batch failed."""
+        _check(lib().mphf_batch_status(self._h, _stream(stream)))
+        return self
+
+    def export_sectors(self, s: int) -> np.ndarray:
+        info = self.set_info(s)
+        ns = (info["total_bits"] + 479) // 480
+        out = np.zeros(ns * 16, dtype=np.uint32)
+        _check(lib().mphf_batch_export_sectors(self._h, s, out.ctypes.data, ns))
+        return out.reshape(ns, 16)
 
     def lookup(self, set_ids: torch.Tensor, queries: torch.Tensor, out: torch.Tensor | None = None,
                stream=None) -> torch.Tensor:

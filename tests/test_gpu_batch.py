@@ -32,7 +32,22 @@ def make_sets(sizes, seed=4):
     return sizes, I.set_keys(sizes, seed), I.set_offsets(sizes)
 
 
-def check_set(b, s, ks, gamma, seed, max_levels, labels):
+def sectors_from_words(words, total_bits):
+    """The lookup sectors of a set laid out from its A words: 480 bits per sector, word 0 the ones
+    of the set before the sector."""
+    w32 = words.view(np.uint32) if len(words) else np.zeros(0, dtype=np.uint32)
+    ns = (total_bits + 479) // 480
+    out = np.zeros((ns, 16), dtype=np.uint32)
+    run = 0
+    for k in range(ns):
+        chunk = w32[15 * k:15 * k + 15]
+        out[k, 1:1 + len(chunk)] = chunk
+        out[k, 0] = run
+        run += int(sum(bin(int(v)).count("1") for v in chunk))
+    return out
+
+
+def check_set(b, s, ks, gamma, seed, max_levels, labels, sectors=True):
     st = O.build(ks, gamma, seed, max_levels=max_levels)
     info = b.set_info(s)
     assert info["n"] == len(ks)
@@ -45,14 +60,19 @@ def check_set(b, s, ks, gamma, seed, max_levels, labels):
     ex = b.export_set(s)
     assert np.array_equal(ex["words"], st.words), s
     assert np.array_equal(ex["fallback_keys"], st.fallback_keys), s
+    if sectors:
+        assert np.array_equal(b.export_sectors(s), sectors_from_words(st.words, st.total_bits)), s
     assert np.array_equal(labels, O.lookup(st, ks)), s
     return st
 
 
-def check_batch(M, sizes, gamma, seed=0, max_levels=25, check=None, absent=True):
+def check_batch(M, sizes, gamma, seed=0, max_levels=25, check=None, absent=True, planned=False):
     sizes, keys, off = make_sets(sizes)
     nsets = sizes.numel()
-    b = M.build_batch(keys.cuda(), off.cuda(), gamma, seed, max_levels=max_levels)
+    if planned:
+        b = M.Batch.plan(off.cuda(), gamma, seed, max_levels=max_levels).rebuild(keys.cuda()).status()
+    else:
+        b = M.build_batch(keys.cuda(), off.cuda(), gamma, seed, max_levels=max_levels)
     set_ids = torch.repeat_interleave(torch.arange(nsets), sizes)
     lab = host(b.lookup(set_ids.cuda(), keys.cuda()))
     knp = keys.numpy().view(np.uint64)
@@ -60,7 +80,8 @@ def check_batch(M, sizes, gamma, seed=0, max_levels=25, check=None, absent=True)
     sets = range(nsets) if check is None else check
     for s in sets:
         ks = knp[offn[s]:offn[s + 1]]
-        st = check_set(b, s, ks, gamma, seed, max_levels, lab[offn[s]:offn[s + 1]])
+        st = check_set(b, s, ks, gamma, seed, max_levels, lab[offn[s]:offn[s + 1]],
+                       sectors=(s % 7 == 0) or len(ks) < 3000)
         if absent and len(ks):
             q = I.splitmix64(1000 + s, 300).numpy().view(np.uint64)
             got = host(b.lookup(torch.full((300,), s, dtype=torch.int64).cuda(),
@@ -178,3 +199,83 @@ def test_batch_repeat_is_deterministic(M):
         assert np.array_equal(b1.export_set(s)["words"], b2.export_set(s)["words"])
     ids = torch.repeat_interleave(torch.arange(300), sizes).cuda()
     assert torch.equal(b1.lookup(ids, kc), b2.lookup(ids, kc))
+
+
+# ------------------------------------------------------------ planned batches and graph capture
+
+@pytest.mark.parametrize("max_levels", [3, 25])
+def test_planned_batch_equals_oracle(M, max_levels):
+    sizes = [0, 1, 2, 17, 300, 4097, 20000, 5, 1200]
+    check_batch(M, sizes, 2.0, seed=21, max_levels=max_levels, planned=True)
+
+
+def test_planned_batch_rebuilds_with_new_keys(M):
+    sizes = I.log_uniform_sizes(200, 16, 8192, seed=22)
+    off = I.set_offsets(sizes)
+    b = M.Batch.plan(off.cuda(), 2.0, 5)
+    ids = torch.repeat_interleave(torch.arange(200), sizes).cuda()
+    for seed in (31, 32, 33):
+        keys = I.set_keys(sizes, seed)
+        kc = keys.cuda()
+        b.rebuild(kc).status()
+        ref = M.build_batch(kc, off.cuda(), 2.0, 5)
+        assert torch.equal(b.lookup(ids, kc), ref.lookup(ids, kc))
+        for s in range(0, 200, 23):
+            assert np.array_equal(b.export_set(s)["words"], ref.export_set(s)["words"])
+            assert np.array_equal(b.export_sectors(s), ref.export_sectors(s))
+        assert b.totals()["bits_per_key"] == ref.totals()["bits_per_key"]
+
+
+def test_planned_batch_reports_duplicates_and_recovers(M):
+    sizes = torch.tensor([100, 500], dtype=torch.int64)
+    off = I.set_offsets(sizes)
+    b = M.Batch.plan(off.cuda(), 2.0, 0)
+    good = I.set_keys(sizes, 4)
+    bad = good.clone()
+    bad[150] = bad[120]
+    with pytest.raises(M.DuplicateKeysError):
+        b.rebuild(bad.cuda()).status()
+    b.rebuild(good.cuda()).status()
+    ids = torch.repeat_interleave(torch.arange(2), sizes).cuda()
+    lab = host(b.lookup(ids, good.cuda()))
+    st = O.build(good[100:].numpy().view(np.uint64), 2.0, 0)
+    assert np.array_equal(lab[100:], O.lookup(st, good[100:].numpy().view(np.uint64)))
+
+
+def test_rebuild_needs_a_plan(M):
+    sizes, keys, off = make_sets([10, 20])
+    b = M.build_batch(keys.cuda(), off.cuda(), 2.0, 0)
+    with pytest.raises(M.MphfError):
+        b.rebuild(keys.cuda())
+
+
+def test_planned_batch_in_hip_graph(M):
+    """Rebuild + lookup captured once in a graph and replayed on new keys: every replay must equal
+    an eager one-shot build of the same keys."""
+    sizes = I.log_uniform_sizes(300, 16, 16384, seed=40)
+    off = I.set_offsets(sizes).cuda()
+    ids = torch.repeat_interleave(torch.arange(300), sizes).cuda()
+    keys_buf = I.set_keys(sizes, 41).cuda()
+    out = torch.empty_like(keys_buf)
+    b = M.Batch.plan(off, 2.0, 9)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):   # warm-up outside the capture
+        b.rebuild(keys_buf).lookup(ids, keys_buf, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.rebuild(keys_buf)
+        b.lookup(ids, keys_buf, out=out)
+    for seed in (42, 43, 44, 42):
+        keys_buf.copy_(I.set_keys(sizes, seed).cuda())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        b.status()
+        ref = M.build_batch(keys_buf, off, 2.0, 9)
+        assert torch.equal(out, ref.lookup(ids, keys_buf)), seed
+        for s in range(0, 300, 37):
+            assert np.array_equal(b.export_sectors(s), ref.export_sectors(s)), (seed, s)
+        ref.close()
