@@ -107,6 +107,14 @@ def bench_batch(args):
     torch.cuda.synchronize()
     print(f"# inputs ready: {nsets} sets, {total} keys", file=sys.stderr, flush=True)
 
+    launch, tune_rec = None, None
+    if args.tune:
+        from paper_1702_03154_amd import autotune
+        launch = autotune.batch_launch(off, args.gamma, verbose=True)
+        cache = autotune._load()
+        tune_rec = cache.get(autotune.device_key(), {}).get(autotune.workload_key(off, args.gamma, 25))
+        print(f"# tuned launch {launch}", file=sys.stderr, flush=True)
+
     s = torch.cuda.current_stream()
     build_ms, lookup_ms, step_ms = [], [], []
     tot = None
@@ -114,7 +122,7 @@ def bench_batch(args):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         torch.cuda.synchronize()
         e0.record(s)
-        b = mphf.build_batch(keys, off, args.gamma, 0)
+        b = mphf.build_batch(keys, off, args.gamma, 0, launch=launch)
         e1.record(s)
         b.lookup(q_ids, q_keys, out=out)
         e2.record(s)
@@ -128,6 +136,30 @@ def bench_batch(args):
         b.close()
         print(f"# step {it}: batch build {e0.elapsed_time(e1):.3f} ms lookup {e1.elapsed_time(e2):.3f} ms",
               file=sys.stderr, flush=True)
+    # the planned batch: rebuild + lookup captured once in a HIP graph and replayed
+    plan = mphf.Batch.plan(off, args.gamma, 0, launch=launch)
+    plan.rebuild(keys).lookup(q_ids, q_keys, out=out)
+    plan.status()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.rebuild(keys)
+        plan.lookup(q_ids, q_keys, out=out)
+    graph_ms = []
+    for it in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        g.replay()
+        e1.record(s)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            graph_ms.append(e0.elapsed_time(e1))
+    plan.status()
+    del g
+    plan.close()
+    print(f"# graph replay {statistics.median(graph_ms):.3f} ms", file=sys.stderr, flush=True)
+
     # labels of every set are a bijection onto [1, n_s]: offset + label - 1 covers [0, total)
     g = off[q_ids] + out - 1
     seen = torch.zeros(total, dtype=torch.int8, device=dev)
@@ -168,6 +200,11 @@ def bench_batch(args):
         "build_ms": tb, "lookup_ms": tl,
         "labels_bijective_per_set": ok,
         "bits_per_key": tot["bits_per_key"],
+        "graph_replay": {"value": total / (statistics.median(graph_ms) / 1e3), "unit": "keys/s",
+                         "ms": statistics.median(graph_ms),
+                         "what": "planned batch: rebuild + lookup captured in one HIP graph, replayed"},
+        "launch": list(launch) if launch else "default (256 threads, 8 keys in flight)",
+        "tuning": tune_rec and {"ms": tune_rec["ms"], "default_ms": tune_rec["default_ms"]},
         "plain_loop": {"value": plain_keys / plain_s, "unit": "keys/s", "sets": len(sample),
                        "keys": plain_keys,
                        "sample": "seeded Feistel sample of the sets; per set one plain build and "
@@ -182,6 +219,7 @@ def main():
     ap.add_argument("--workload", choices=["plain", "batch"], default="plain")
     ap.add_argument("--sets", type=float, default=65536)
     ap.add_argument("--plain-sample", type=float, default=2048)
+    ap.add_argument("--tune", action="store_true", help="batch: autotune the build launch first")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)

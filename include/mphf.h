@@ -58,6 +58,13 @@ typedef struct mphf_opts {
                                  (workspace plus the structure); 0 = no bound */
     uint32_t keep_collisions; /* nonzero: keep every C_d so that mphf_export_collisions works */
     uint32_t flags;           /* 0, or MPHF_FLAG_ATOMIC_LEVELS */
+    /* Launch configuration of the batched build (0 = default; ignored by single builds):
+     * threads per workgroup 128/256/512 (default 256), keys in flight per thread 4/8/16
+     * (default 8), workgroups per CU 1..8 (default: as many as the LDS allows, at most 8). */
+    uint32_t batch_threads;
+    uint32_t batch_items;
+    uint32_t batch_wgs_per_cu;
+    uint32_t reserved;        /* 0 */
 } mphf_opts;
 
 /* Build every level by global atomic test-and-set on the interleaved A/C words instead of the

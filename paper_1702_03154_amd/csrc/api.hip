@@ -938,6 +938,7 @@ struct mphf_batch {
     uint64_t* region = nullptr;
     uint64_t max_m = 0;
     uint32_t grid = 0;
+    BatchLaunch cfg;
 };
 
 namespace {
@@ -1061,6 +1062,9 @@ mphf_status check_batch_args(const uint64_t* offsets, uint64_t nsets, double gam
     if (st != MPHF_OK) return st;
     if (o.flags) return fail(MPHF_E_INVALID, "flags are not supported for batched builds");
     if (o.rank_sample != 512) return fail(MPHF_E_INVALID, "batched builds use rank_sample 512");
+    const uint32_t t = o.batch_threads, it = o.batch_items;
+    if ((t && t != 128 && t != 256 && t != 512) || (it && it != 4 && it != 8 && it != 16) || o.batch_wgs_per_cu > 8)
+        return fail(MPHF_E_INVALID, "batch launch: threads 128/256/512, items 4/8/16, at most 8 workgroups per CU");
     return MPHF_OK;
 }
 
@@ -1140,9 +1144,13 @@ mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* off
     if ((st = mem.own(b, lay3, "set records")) != MPHF_OK) return st;
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
-    HIP_TRY(batch_kernel_setup(b->max_m, BATCH_LEFT_CAP), "batch kernel LDS size");
+    b->cfg.threads = o.batch_threads ? o.batch_threads : 256;
+    b->cfg.items = o.batch_items ? o.batch_items : 8;
+    b->cfg.wgs_per_cu = o.batch_wgs_per_cu;
+    HIP_TRY(batch_kernel_setup(b->cfg, b->max_m, BATCH_LEFT_CAP), "batch kernel setup");
     const uint64_t lds = batch_lds_bytes(b->max_m, BATCH_LEFT_CAP);
-    const uint32_t per_cu = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, 155000 / (lds + 1024)));
+    uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, 155000 / (lds + 1024)));
+    if (b->cfg.wgs_per_cu) per_cu = std::min<uint64_t>(per_cu, b->cfg.wgs_per_cu);
     b->grid = (uint32_t)std::min<uint64_t>(nsets, (uint64_t)cus * per_cu);
     if (keep) {
         b->left = b->scratch;
@@ -1158,7 +1166,7 @@ hipError_t batch_levels(const mphf_batch* b, const uint64_t* keys, hipStream_t s
     if ((e = launch_batch_reset(b->queue, b->fail32, s)) != hipSuccess) return e;
     if ((e = launch_batch_build(keys, b->offsets, b->order, b->nsets, b->queue, b->scratch, b->region_w, b->gamma,
                                 b->seeds, b->D, BATCH_LEFT_CAP, b->region, b->sec, b->sreg_base, b->sets, b->levels,
-                                b->max_m, b->grid, s)) != hipSuccess)
+                                b->max_m, b->cfg, b->grid, s)) != hipSuccess)
         return e;
     return launch_batch_tally(b->sets, b->nsets, b->left32, b->sec32, b->fail32, s);
 }

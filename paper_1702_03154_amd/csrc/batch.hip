@@ -23,9 +23,6 @@ namespace mphfk {
 
 namespace {
 
-constexpr int BW = 256;             // threads per set-building workgroup
-constexpr int NWAVE = BW / 64;
-constexpr int FI = 8;               // keys per thread in flight in the level passes
 constexpr int NCLASS = 65;          // size classes: 0 for an empty set, else floor(log2 n) + 1
 constexpr int PT = 256;             // threads of the preparation kernels
 
@@ -130,7 +127,9 @@ __global__ void k_batch_reset(unsigned long long* queue, uint32_t* fail) {
     }
 }
 
-// One workgroup builds one set at a time.
+// One workgroup of BW threads builds one set at a time, with FI keys per thread in flight in the
+// level passes.
+template <int BW, int FI>
 __global__ void __launch_bounds__(BW)
 k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ offsets,
               const uint32_t* __restrict__ order, uint64_t nsets, unsigned long long* next,
@@ -138,6 +137,7 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
               SeedTable seeds, uint32_t D, uint32_t left_cap, uint64_t* __restrict__ region,
               uint32_t* __restrict__ sreg, const uint64_t* __restrict__ sreg_base,
               BatchSet* __restrict__ sets, BatchLevel* __restrict__ levels) {
+    constexpr int NWAVE = BW / 64;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t wsum[NWAVE + 1];
     __shared__ unsigned long long s_item;
@@ -460,6 +460,23 @@ k_batch_lookup(const uint64_t* __restrict__ set_ids, const uint64_t* __restrict_
     }
 }
 
+// The build kernel for a launch configuration, or null if it is not one of the compiled ones.
+const void* batch_kernel(const BatchLaunch& cfg) {
+#define MPHF_BATCH_CASE(T, I) \
+    if (cfg.threads == T && cfg.items == I) return (const void*)k_batch_build<T, I>;
+    MPHF_BATCH_CASE(128, 4)
+    MPHF_BATCH_CASE(128, 8)
+    MPHF_BATCH_CASE(128, 16)
+    MPHF_BATCH_CASE(256, 4)
+    MPHF_BATCH_CASE(256, 8)
+    MPHF_BATCH_CASE(256, 16)
+    MPHF_BATCH_CASE(512, 4)
+    MPHF_BATCH_CASE(512, 8)
+    MPHF_BATCH_CASE(512, 16)
+#undef MPHF_BATCH_CASE
+    return nullptr;
+}
+
 uint32_t prep_grid(uint64_t items) {
     const uint64_t g = (items + PT - 1) / PT;
     return (uint32_t)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
@@ -493,17 +510,22 @@ hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, con
                               const uint64_t* region_w, double gamma, const SeedTable& seeds,
                               uint32_t D, uint32_t left_cap, uint64_t* region, uint32_t* sreg,
                               const uint64_t* sreg_base, BatchSet* sets, BatchLevel* levels, uint64_t max_m,
-                              uint32_t grid, hipStream_t s) {
+                              const BatchLaunch& cfg, uint32_t grid, hipStream_t s) {
     const uint64_t lds = batch_lds_bytes(max_m, left_cap);
-    hipLaunchKernelGGL(k_batch_build, dim3(grid), dim3(BW), (unsigned)lds, s, keys, offsets, order, nsets,
-                       next, scratch, region_w, gamma, seeds, D, left_cap, region, sreg, sreg_base, sets, levels);
-    return hipGetLastError();
+    const void* k = batch_kernel(cfg);
+    if (!k) return hipErrorInvalidValue;
+    void* args[] = {(void*)&keys, (void*)&offsets, (void*)&order, (void*)&nsets, (void*)&next, (void*)&scratch,
+                    (void*)&region_w, (void*)&gamma, (void*)&seeds, (void*)&D, (void*)&left_cap, (void*)&region,
+                    (void*)&sreg, (void*)&sreg_base, (void*)&sets, (void*)&levels};
+    return hipLaunchKernel(k, dim3(grid), dim3(cfg.threads), args, (size_t)lds, s);
 }
 
-hipError_t batch_kernel_setup(uint64_t max_m, uint32_t left_cap) {
+hipError_t batch_kernel_setup(const BatchLaunch& cfg, uint64_t max_m, uint32_t left_cap) {
+    const void* k = batch_kernel(cfg);
+    if (!k) return hipErrorInvalidValue;
     const uint64_t lds = batch_lds_bytes(max_m, left_cap);
     if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute((const void*)k_batch_build, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap) {

@@ -130,6 +130,14 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
 hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
                             hipStream_t s);
 
+// Launch configuration of the batched build kernel: threads per workgroup (128, 256 or 512), keys
+// per thread in flight (4, 8 or 16) and workgroups per CU (1..8, further bounded by LDS).
+struct BatchLaunch {
+    uint32_t threads = 256;
+    uint32_t items = 8;
+    uint32_t wgs_per_cu = 0;   // 0: as many as the LDS allows, at most 8
+};
+
 uint32_t batch_classes();
 hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
                                 uint32_t* bound, uint32_t* sbound, uint32_t* hist, unsigned long long* info,
@@ -142,9 +150,10 @@ hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, con
                               const uint64_t* region_w, double gamma, const SeedTable& seeds,
                               uint32_t D, uint32_t left_cap, uint64_t* region, uint32_t* sreg,
                               const uint64_t* sreg_base, BatchSet* sets, BatchLevel* levels, uint64_t max_m,
-                              uint32_t grid, hipStream_t s);
+                              const BatchLaunch& cfg, uint32_t grid, hipStream_t s);
 uint64_t batch_lds_bytes(uint64_t max_m, uint32_t left_cap);
-hipError_t batch_kernel_setup(uint64_t max_m, uint32_t left_cap);   // once per size, before any launch
+// Once per configuration and size, before any launch (and so outside a graph capture).
+hipError_t batch_kernel_setup(const BatchLaunch& cfg, uint64_t max_m, uint32_t left_cap);
 hipError_t launch_batch_tally(const BatchSet* sets, uint64_t nsets, uint32_t* left32, uint32_t* sec32,
                               uint32_t* fail, hipStream_t s);
 hipError_t launch_batch_pack(const uint32_t* sreg, BatchSet* sets, uint64_t nsets, const uint64_t* sec_pre,

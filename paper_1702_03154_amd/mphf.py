@@ -32,7 +32,8 @@ class DuplicateKeysError(MphfError):
 class Opts(C.Structure):
     _fields_ = [("max_levels", C.c_uint32), ("rank_sample", C.c_uint32),
                 ("mem_budget", C.c_uint64), ("keep_collisions", C.c_uint32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("batch_threads", C.c_uint32), ("batch_items", C.c_uint32),
+                ("batch_wgs_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 _U64L = C.c_uint64 * MAX_LEVELS
@@ -225,11 +226,20 @@ class Batch:
         self._h = handle
         self.device = device
 
+    @staticmethod
+    def _opts(max_levels: int, launch) -> Opts:
+        o = Opts(max_levels, 512, 0, 0, 0)
+        if launch is not None:
+            o.batch_threads, o.batch_items, o.batch_wgs_per_cu = (int(v) for v in launch)
+        return o
+
     @classmethod
     def build(cls, keys: torch.Tensor, offsets: torch.Tensor, gamma: float = 2.0, seed: int = 0,
-              max_levels: int = 25, stream=None) -> "Batch":
+              max_levels: int = 25, stream=None, launch=None) -> "Batch":
+        """One-shot batched build.  ``launch``: (threads, items, workgroups per CU), e.g. from
+        :func:`paper_1702_03154_amd.autotune.batch_launch`; None = the library's default."""
         L = lib()
-        o = Opts(max_levels, 512, 0, 0, 0)
+        o = cls._opts(max_levels, launch)
         h = C.c_void_p()
         kp = _dev(keys, "keys") if keys.numel() else keys.data_ptr()
         with torch.cuda.device(keys.device):
@@ -239,10 +249,10 @@ class Batch:
 
     @classmethod
     def plan(cls, offsets: torch.Tensor, gamma: float = 2.0, seed: int = 0, max_levels: int = 25,
-             stream=None) -> "Batch":
+             stream=None, launch=None) -> "Batch":
         """A planned batch for these set sizes; fill it with :meth:`rebuild`."""
         L = lib()
-        o = Opts(max_levels, 512, 0, 0, 0)
+        o = cls._opts(max_levels, launch)
         h = C.c_void_p()
         with torch.cuda.device(offsets.device):
             _check(L.mphf_batch_plan(_dev(offsets, "offsets"), offsets.numel() - 1, float(gamma),

@@ -279,3 +279,40 @@ def test_planned_batch_in_hip_graph(M):
         for s in range(0, 300, 37):
             assert np.array_equal(b.export_sectors(s), ref.export_sectors(s)), (seed, s)
         ref.close()
+
+
+# ------------------------------------------------------------ launch configurations and the tuner
+
+def test_every_launch_configuration_gives_the_same_batch(M):
+    from paper_1702_03154_amd import autotune
+    sizes, keys, off = make_sets(I.log_uniform_sizes(150, 1, 20000, seed=50))
+    kc, oc = keys.cuda(), off.cuda()
+    ids = torch.repeat_interleave(torch.arange(150), sizes).cuda()
+    ref = M.build_batch(kc, oc, 2.0, 3)
+    want = ref.lookup(ids, kc)
+    secs = {s: ref.export_sectors(s) for s in range(0, 150, 11)}
+    for launch in autotune.candidates():
+        b = M.build_batch(kc, oc, 2.0, 3, launch=launch)
+        assert torch.equal(b.lookup(ids, kc), want), launch
+        for s, v in secs.items():
+            assert np.array_equal(b.export_sectors(s), v), (launch, s)
+        b.close()
+    with pytest.raises(M.MphfError):
+        M.build_batch(kc, oc, 2.0, 3, launch=(300, 8, 0))
+
+
+def test_tuner_picks_a_candidate_and_caches_it(M, tmp_path, monkeypatch):
+    from paper_1702_03154_amd import autotune
+    monkeypatch.setenv("MPHF_TUNE_CACHE", str(tmp_path / "tune.json"))
+    sizes = I.log_uniform_sizes(500, 16, 4096, seed=51)
+    off = I.set_offsets(sizes).cuda()
+    launch = autotune.batch_launch(off, 2.0)
+    assert launch in set(autotune.candidates())
+    rec = autotune._load()[autotune.device_key()][autotune.workload_key(off, 2.0, 25)]
+    assert tuple(rec["launch"]) == launch and rec["ms"] <= rec["default_ms"]
+    assert autotune.batch_launch(off, 2.0) == launch   # from the cache
+    keys = I.set_keys(sizes, 4).cuda()
+    ids = torch.repeat_interleave(torch.arange(500), sizes).cuda()
+    b = M.build_batch(keys, off, 2.0, 0, launch=launch)
+    ref = M.build_batch(keys, off, 2.0, 0)
+    assert torch.equal(b.lookup(ids, keys), ref.lookup(ids, keys))
