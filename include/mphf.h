@@ -225,6 +225,68 @@ mphf_status mphf_batch_totals(const mphf_batch_t* b, uint64_t* nsets, uint64_t* 
 /* Free every device buffer of b.  NULL is allowed; must not overlap a lookup or build on b. */
 void mphf_batch_destroy(mphf_batch_t* b);
 
+/* ---- Serving: many resident functions, lookup requests batched as they arrive ---------------
+ * A server keeps registered functions resident and answers lookup requests from host memory.
+ * Requests wait in arrival order and are admitted while their device memory (16 bytes per key:
+ * the key in, the label out) fits the server's HBM budget; every admitted group of requests is one
+ * batch: its keys are copied in, one segmented lookup kernel labels all of them (each request
+ * against its own function, Algorithm 3), and the labels are copied out.  Up to max_inflight
+ * batches are on the device at once on their own streams, so requests arriving while a batch runs
+ * form the next one and its copies overlap the running kernels (continuous batching).  A request's
+ * labels are exactly those of mphf_lookup on its function, alone or in any mix.
+ * The server's threads issue all device work; the API calls are thread-safe. */
+typedef struct mphf_server mphf_server_t;
+
+typedef struct mphf_server_opts {
+    uint64_t hbm_budget;           /* device bytes for requests in flight (default 1 GiB); split
+                                      evenly over the in-flight batches */
+    uint32_t max_inflight;         /* batches on the device at once, 1..8 (default 2) */
+    uint32_t max_batch_requests;   /* requests per batch (default 1024) */
+} mphf_server_opts;
+
+typedef struct mphf_request_info {
+    uint32_t done;                 /* 1 once the labels are in the caller's array */
+    uint32_t batch_requests;       /* requests in the batch that served this one */
+    uint64_t batch;                /* sequence number of that batch */
+    double submit_us, start_us, done_us;   /* server clock: submitted, batch launched, labels out */
+} mphf_request_info;
+
+typedef struct mphf_server_stats {
+    uint64_t requests, keys, batches;      /* completed */
+    uint64_t max_batch_requests_seen;
+    uint64_t peak_bytes_in_flight;
+} mphf_server_stats;
+
+/* Fill *opts with the defaults. */
+mphf_status mphf_server_default_opts(mphf_server_opts* opts);
+
+/* A server on the current device (NULL opts = defaults). */
+mphf_status mphf_server_create(const mphf_server_opts* opts, mphf_server_t** out);
+
+/* Make a built function resident: its id is written to *id.  h must be on the server's device and
+ * outlive the server (the server does not own it). */
+mphf_status mphf_server_register(mphf_server_t* s, const mphf_t* h, uint32_t* id);
+
+/* Queue a request: label keys[0..n) (host memory) against function `id` into out[0..n) (host
+ * memory).  Both arrays must stay valid until the request is done; pinned memory from
+ * mphf_host_alloc copies fastest.  *ticket identifies the request.  MPHF_E_INVALID for an unknown
+ * id or a request larger than one batch's share of the budget. */
+mphf_status mphf_server_submit(mphf_server_t* s, uint32_t id, const uint64_t* keys, uint64_t n,
+                               uint64_t* out, uint64_t* ticket);
+
+/* State of a request; with wait != 0, block until it is done.  A done request is forgotten after
+ * it has been reported (poll each ticket until done once). */
+mphf_status mphf_server_poll(mphf_server_t* s, uint64_t ticket, int wait, mphf_request_info* info);
+
+mphf_status mphf_server_get_stats(const mphf_server_t* s, mphf_server_stats* st);
+
+/* Finish every queued request, stop the server's threads and free its memory.  NULL is allowed. */
+void mphf_server_destroy(mphf_server_t* s);
+
+/* Pinned host memory for request arrays (and its release). */
+mphf_status mphf_host_alloc(uint64_t bytes, void** out);
+void mphf_host_free(void* p);
+
 /* Free the build temporaries the library keeps per device between builds (a few times the
  * largest key set built so far).  Must not overlap a build. */
 mphf_status mphf_trim(void);

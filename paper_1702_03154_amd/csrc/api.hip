@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "api_internal.h"
 #include "internal.h"
 #include "mphf.h"
 
@@ -906,6 +907,30 @@ mphf_status mphf_trim(void) {
 const char* mphf_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- shared with the serving loop
+
+namespace mphf_api {
+
+mphf_status set_error(mphf_status st, const std::string& msg) { return fail(st, msg); }
+
+mphf_status hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+bool device_ptr(const void* p) { return is_device_ptr(p); }
+
+void lookup_desc(const mphf_t* h, SegDesc* d, int* device) {
+    d->lev = h->dlev;
+    d->sec = h->sec;
+    d->super = h->super;
+    d->fbk = h->fb_keys;
+    d->nfb = h->nfb;
+    d->N = h->n;
+    d->nlev = h->num_levels;
+    d->pad = 0;
+    *device = h->device;
+}
+
+}  // namespace mphf_api
 
 // ---------------------------------------------------------------- batched builds
 

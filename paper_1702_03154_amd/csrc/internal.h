@@ -20,6 +20,41 @@ struct DevLevel {
 
 LevelHash make_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off);
 
+// One request of a served batch: the function it queries (device pointers owned by the handle,
+// as the single lookup kernel takes them).  Its queries are q[seg_off[r] .. seg_off[r + 1]).
+struct SegDesc {
+    const DevLevel* lev;
+    const uint32_t* sec;
+    const uint64_t* super;
+    const uint64_t* fbk;
+    uint64_t nfb;
+    uint64_t N;
+    uint32_t nlev;
+    uint32_t pad;
+};
+
+// The label of query x (Algorithm 3): the first level whose bit is set gives the ones of A before
+// it plus one; else the fallback table (ascending keys, labels N - nfb + 1 ..); else 0.
+__device__ __forceinline__ uint64_t label_of(uint64_t x, const DevLevel* __restrict__ lev, uint32_t nlev,
+                                             const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
+                                             const uint64_t* __restrict__ fbk, uint64_t nfb, uint64_t N) {
+    for (uint32_t d = 0; d < nlev; ++d) {
+        const DevLevel L = lev[d];
+        const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
+        uint64_t rank;
+        if (sector_rank(sec, super, g, &rank)) return rank + 1;
+    }
+    if (nfb) {
+        uint64_t lo = 0, hi = nfb;   // first index with fbk[idx] >= x
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (fbk[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        if (lo < nfb && fbk[lo] == x) return N - nfb + 1 + lo;
+    }
+    return 0;
+}
+
 struct SeedTable {
     uint64_t s[64];
 };
@@ -124,6 +159,8 @@ uint64_t sector_count(uint64_t total_bits);
 uint64_t super_count(uint64_t nsec);
 hipError_t launch_sectors(const uint64_t* words, uint64_t total_bits, uint32_t* sec, uint64_t* super,
                           uint32_t* tmp_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s);
+hipError_t launch_lookup_segments(const uint64_t* q, uint64_t n, uint64_t* out, const SegDesc* segs,
+                                  const uint64_t* seg_off, uint32_t nseg, hipStream_t s);
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
                          uint32_t nlev, const uint32_t* sec, const uint64_t* super,
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);

@@ -312,30 +312,8 @@ __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* _
                          const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
                          const uint64_t* __restrict__ fbk, uint64_t nfb, uint64_t N) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint64_t x = q[i];
-        uint64_t label = 0;
-        bool found = false;
-        for (uint32_t d = 0; d < nlev; ++d) {
-            const DevLevel L = lev[d];
-            const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
-            uint64_t rank;
-            if (sector_rank(sec, super, g, &rank)) {
-                label = rank + 1;
-                found = true;
-                break;
-            }
-        }
-        if (!found && nfb) {
-            uint64_t lo = 0, hi = nfb;   // first index with fbk[idx] >= x
-            while (lo < hi) {
-                const uint64_t mid = (lo + hi) >> 1;
-                if (fbk[mid] < x) lo = mid + 1; else hi = mid;
-            }
-            if (lo < nfb && fbk[lo] == x) label = N - nfb + 1 + lo;
-        }
-        out[i] = label;
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = label_of(q[i], lev, nlev, sec, super, fbk, nfb, N);
 }
 
 __global__ void k_positions(const uint64_t* __restrict__ keys, uint64_t n, LevelHash L,

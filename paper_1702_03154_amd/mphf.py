@@ -55,6 +55,21 @@ class SetInfo(C.Structure):
                 ("total_bits", C.c_uint64)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_inflight", C.c_uint32),
+                ("max_batch_requests", C.c_uint32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("done", C.c_uint32), ("batch_requests", C.c_uint32), ("batch", C.c_uint64),
+                ("submit_us", C.c_double), ("start_us", C.c_double), ("done_us", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("requests", C.c_uint64), ("keys", C.c_uint64), ("batches", C.c_uint64),
+                ("max_batch_requests_seen", C.c_uint64), ("peak_bytes_in_flight", C.c_uint64)]
+
+
 class View(C.Structure):
     _fields_ = [("words", C.c_void_p), ("rank", C.c_void_p), ("fallback_keys", C.c_void_p),
                 ("collisions", C.c_void_p), ("total_words", C.c_uint64), ("rank_entries", C.c_uint64),
@@ -97,6 +112,15 @@ def lib() -> C.CDLL:
             "mphf_batch_status": (st, [vp, vp]),
             "mphf_batch_export_sectors": (st, [vp, u64, vp, u64]),
             "mphf_last_error": (C.c_char_p, []),
+            "mphf_server_default_opts": (st, [C.POINTER(ServerOpts)]),
+            "mphf_server_create": (st, [C.POINTER(ServerOpts), C.POINTER(vp)]),
+            "mphf_server_register": (st, [vp, vp, C.POINTER(C.c_uint32)]),
+            "mphf_server_submit": (st, [vp, u32, vp, u64, vp, C.POINTER(C.c_uint64)]),
+            "mphf_server_poll": (st, [vp, u64, C.c_int, C.POINTER(RequestInfo)]),
+            "mphf_server_get_stats": (st, [vp, C.POINTER(ServerStats)]),
+            "mphf_server_destroy": (None, [vp]),
+            "mphf_host_alloc": (st, [u64, C.POINTER(vp)]),
+            "mphf_host_free": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -334,3 +358,84 @@ def positions(keys: torch.Tensor, level_seed: int, m: int, stream=None) -> torch
         _check(lib().mphf_positions(_dev(keys, "keys"), keys.numel(), level_seed & (2**64 - 1), m,
                                     _dev(out, "out"), _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- serving
+
+class HostArray:
+    """Pinned host memory from mphf_host_alloc, seen as a numpy uint64 array (``.a``)."""
+
+    def __init__(self, n: int):
+        self._p = C.c_void_p()
+        _check(lib().mphf_host_alloc(max(1, n) * 8, C.byref(self._p)))
+        buf = (C.c_uint64 * max(1, n)).from_address(self._p.value)
+        self.a = np.ctypeslib.as_array(buf)[:n]
+
+    def close(self):
+        if self._p:
+            lib().mphf_host_free(self._p)
+            self._p = None
+            self.a = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Resident functions answering lookup requests from host memory, batched as they arrive
+    (mphf_server_*).  Registered functions must stay alive while the server runs."""
+
+    def __init__(self, hbm_budget: int = 1 << 30, max_inflight: int = 2, max_batch_requests: int = 1024):
+        o = ServerOpts(int(hbm_budget), int(max_inflight), int(max_batch_requests))
+        h = C.c_void_p()
+        _check(lib().mphf_server_create(C.byref(o), C.byref(h)))
+        self._h = h.value
+        self._keep = {}      # ticket -> (keys, out): the arrays must outlive the request
+        self._fns = []
+
+    def register(self, f: "MPHF") -> int:
+        i = C.c_uint32()
+        _check(lib().mphf_server_register(self._h, f._h, C.byref(i)))
+        self._fns.append(f)
+        return i.value
+
+    def submit(self, fn: int, keys: np.ndarray, out: np.ndarray) -> int:
+        """Queue the labelling of ``keys`` (uint64/int64 host array) into ``out`` (same length)."""
+        if keys.dtype.itemsize != 8 or out.dtype.itemsize != 8 or not keys.flags.c_contiguous \
+                or not out.flags.c_contiguous or not out.flags.writeable or len(out) < len(keys):
+            raise ValueError("keys and out must be contiguous 64-bit host arrays, out writable and as long")
+        t = C.c_uint64()
+        _check(lib().mphf_server_submit(self._h, fn, keys.ctypes.data, len(keys), out.ctypes.data,
+                                        C.byref(t)))
+        self._keep[t.value] = (keys, out)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True) -> dict:
+        info = RequestInfo()
+        try:
+            _check(lib().mphf_server_poll(self._h, ticket, 1 if wait else 0, C.byref(info)))
+        finally:
+            if info.done:
+                self._keep.pop(ticket, None)
+        return {"done": bool(info.done), "batch": info.batch, "batch_requests": info.batch_requests,
+                "submit_us": info.submit_us, "start_us": info.start_us, "done_us": info.done_us}
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().mphf_server_get_stats(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().mphf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
