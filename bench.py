@@ -9,6 +9,11 @@ log-uniform sizes in [16, 65536] (seeded) plus the lookup of every key of every
 set, shuffled, beside the same work done by a loop of plain per-set builds and
 lookups over a seeded sample of the sets.
 
+--workload serve: 64 resident functions (log-uniform sizes in [1e6, 1e9]) answer
+Poisson-arriving lookup requests from host memory through the serving loop;
+throughput at saturation and p50/p99 latency at 0.5/0.8/0.95 of the plain
+per-request capacity, beside plain per-request lookups.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -214,9 +219,150 @@ def bench_batch(args):
     print(json.dumps(res))
 
 
+def bench_serve(args):
+    """Serving: many resident functions, Poisson-arriving lookup requests from host memory, batched
+    as they arrive; p50/p99 latency and throughput beside plain per-request lookups."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_1702_03154_amd import inputs, mphf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nfn = int(args.functions)
+    u = inputs._srl(inputs.splitmix64(6, nfn), 11).double() / float(1 << 53)
+    sizes = torch.floor(1e6 * torch.pow(torch.tensor(1000.0, dtype=torch.float64), u) * args.serve_scale)
+    sizes = sizes.long().clamp(min=1).tolist()
+    fn_seeds = [int(v) & ((1 << 64) - 1) for v in inputs.splitmix64(7, nfn).tolist()]
+    fns, struct_bytes = [], 0
+    t0 = time.perf_counter()
+    for j in range(nfn):
+        k = inputs.splitmix64(fn_seeds[j], sizes[j], device=dev)
+        h = mphf.build(k, 2.0, 0)
+        del k
+        fns.append(h)
+        struct_bytes += h.stats()["structure_bytes"]
+    torch.cuda.synchronize()
+    print(f"# {nfn} functions built ({sum(sizes)} keys, {struct_bytes / 2**30:.2f} GiB) in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    # requests: sizes floor(1e6^u), function uniform, 90% present keys (a uniform index into the
+    # function's key stream), 10% absent keys (a separate stream); all in pinned host memory
+    R = int(args.requests)
+    ru = inputs._srl(inputs.splitmix64(8, 3 * R), 11).double() / float(1 << 53)
+    rsize = torch.floor(torch.pow(torch.tensor(1e6, dtype=torch.float64), ru[:R])).long().tolist()
+    rfn = (ru[R:2 * R] * nfn).long().clamp(max=nfn - 1).tolist()
+    gaps = (-torch.log1p(-ru[2 * R:])).tolist()   # unit-rate exponential inter-arrival gaps
+    qs, outs = [], []
+    absent_at = 0
+    for i in range(R):
+        n, f = rsize[i], rfn[i]
+        idx = (inputs.splitmix64(10_000 + i, n, device=dev) & ((1 << 62) - 1)) % sizes[f]
+        q = torch.empty(0, dtype=torch.int64, device=dev)
+        if n:
+            # key idx of the function's stream: mix(seed + (idx + 1) * golden)
+            z = (idx + 1) * inputs._s64(inputs._GOLDEN) + inputs._s64(fn_seeds[f])
+            q = inputs._mix(z)
+            absent = (inputs.splitmix64(20_000 + i, n, device=dev) & 1023) < 102
+            na = int(absent.sum())
+            if na:
+                q[absent] = inputs.splitmix64(9, na, start=absent_at, device=dev)
+                absent_at += na
+        hq, ho = mphf.HostArray(n), mphf.HostArray(n)
+        if n:
+            hq.a[:] = q.cpu().numpy().view(np.uint64)
+        qs.append(hq)
+        outs.append(ho)
+    total_keys = sum(rsize)
+    print(f"# {R} requests, {total_keys} keys", file=sys.stderr, flush=True)
+
+    # plain: one lookup per request, each copied in, labelled, copied out and waited for
+    s = torch.cuda.current_stream()
+    dq = torch.empty(max(rsize) + 1, dtype=torch.int64, device=dev)
+    do = torch.empty_like(dq)
+    plain_lab = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(R):
+        n = rsize[i]
+        if n:
+            dq[:n].copy_(torch.from_numpy(qs[i].a.view(np.int64)), non_blocking=True)
+            fns[rfn[i]].lookup(dq[:n], out=do[:n])
+            outs[i].a.view(np.int64)[:] = do[:n].cpu().numpy()
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    plain_rps = R / plain_s
+    for i in range(R):
+        plain_lab.append(outs[i].a.copy())
+    print(f"# plain: {plain_rps:.0f} requests/s, {total_keys / plain_s:.3e} keys/s", file=sys.stderr, flush=True)
+
+    server = mphf.Server(hbm_budget=int(args.hbm_budget), max_inflight=int(args.inflight))
+    ids = [server.register(h) for h in fns]
+
+    def run(rate):
+        for o in outs:
+            o.a[:] = 0
+        tickets = [None] * R
+        start = time.perf_counter()
+        t_next = start
+        for i in range(R):
+            if rate:
+                t_next += gaps[i] / rate
+                while time.perf_counter() < t_next:
+                    pass
+            tickets[i] = server.submit(ids[rfn[i]], qs[i].a, outs[i].a)
+        infos = [server.poll(t, wait=True) for t in tickets]
+        wall = time.perf_counter() - start
+        lat = np.array([x["done_us"] - x["submit_us"] for x in infos])
+        ok = all(np.array_equal(outs[i].a, plain_lab[i]) for i in range(R))
+        return {"offered_requests_per_s": rate or None, "requests_per_s": R / wall, "keys_per_s": total_keys / wall,
+                "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+                "mean_batch_requests": float(np.mean([x["batch_requests"] for x in infos])),
+                "equal_to_plain": ok}
+
+    sat = run(0)
+    print(f"# served at saturation: {sat['requests_per_s']:.0f} requests/s, p50 {sat['p50_us']:.0f} us",
+          file=sys.stderr, flush=True)
+    loads = {}
+    for f in (0.5, 0.8, 0.95):
+        loads[str(f)] = run(f * plain_rps)
+        print(f"# load {f}: p50 {loads[str(f)]['p50_us']:.0f} us p99 {loads[str(f)]['p99_us']:.0f} us",
+              file=sys.stderr, flush=True)
+    st = server.stats()
+    server.close()
+    res = {
+        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "value": sat["keys_per_s"], "unit": "keys/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * total_keys / sat["keys_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"serving: {nfn} resident functions, sizes floor(1e6*1000^u*{args.serve_scale}) "
+                               f"(seed 6), gamma=2; {R} requests of floor(1e6^u) keys (seed 8), 90% present, "
+                               f"10% absent, from pinned host memory",
+                   "functions": nfn, "function_keys": sum(sizes), "structure_bytes": struct_bytes,
+                   "requests": R, "request_keys": total_keys, "hbm_budget": int(args.hbm_budget),
+                   "max_inflight": int(args.inflight)},
+        "plain": {"requests_per_s": plain_rps, "keys_per_s": total_keys / plain_s,
+                  "what": "per request: copy in, lookup, copy out, wait"},
+        "served_saturation": sat, "served_over_plain": sat["keys_per_s"] / (total_keys / plain_s),
+        "poisson_loads_of_plain_capacity": loads,
+        "server_stats": st,
+    }
+    for o in qs + outs:
+        o.close()
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["plain", "batch"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batch", "serve"], default="plain")
+    ap.add_argument("--functions", type=float, default=64, help="serve: resident functions")
+    ap.add_argument("--serve-scale", type=float, default=1.0, help="serve: function size scale")
+    ap.add_argument("--requests", type=float, default=2000, help="serve: requests per run")
+    ap.add_argument("--hbm-budget", type=float, default=2 << 30, help="serve: admission budget (bytes)")
+    ap.add_argument("--inflight", type=float, default=2, help="serve: batches in flight")
     ap.add_argument("--sets", type=float, default=65536)
     ap.add_argument("--plain-sample", type=float, default=2048)
     ap.add_argument("--tune", action="store_true", help="batch: autotune the build launch first")
@@ -238,6 +384,9 @@ def main():
         calibrate_copy()
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     import torch
