@@ -9,6 +9,11 @@ log-uniform sizes in [16, 65536] (seeded) plus the lookup of every key of every
 set, shuffled, beside the same work done by a loop of plain per-set builds and
 lookups over a seeded sample of the sets.
 
+--workload kmer: the first 4e9 distinct canonical 31-mers of a 4.2e9-base random
+DNA sequence (32 GB of keys in HBM); plain build + lookup and the batched path
+over 2^15 hash sets, with per-level sizes checked against the occupancy
+statistics.
+
 --workload serve: 64 resident functions (log-uniform sizes in [1e6, 1e9]) answer
 Poisson-arriving lookup requests from host memory through the serving loop;
 throughput at saturation and p50/p99 latency at 0.5/0.8/0.95 of the plain
@@ -355,9 +360,117 @@ def bench_serve(args):
     print(json.dumps(res))
 
 
+def bench_kmer(args):
+    """k-mer keys: canonical 31-mers of a seeded random DNA sequence, first occurrences up to the
+    target; plain build + lookup, and the batched path over hash sets, on the same keys."""
+    import math
+
+    import torch
+
+    from paper_1702_03154_amd import inputs, mphf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nb, target, k = int(args.kmer_bases), int(args.kmer_keys), 31
+    t0 = time.perf_counter()
+    seq = inputs.dna_sequence(nb, seed=5, device=dev)
+    km = mphf.kmers(seq, nb, k)
+    del seq
+    keys = mphf.first_occurrences(km, target)
+    del km
+    torch.cuda.synchronize()
+    n = keys.numel()
+    print(f"# {n} distinct canonical {k}-mers from {nb} bases in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    s = torch.cuda.current_stream()
+    out = torch.empty_like(keys)
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        r = fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return r, e0.elapsed_time(e1)
+
+    def bijective(lab, base=None):
+        seen = torch.zeros(n, dtype=torch.int8, device=dev)
+        idx = lab - 1 if base is None else base + lab - 1
+        ok = bool(((idx >= 0) & (idx < n)).all())
+        seen[idx.clamp(0, n - 1)] = 1
+        return ok and bool(seen.all())
+
+    # plain path
+    build_ms, lookup_ms = [], []
+    stats = None
+    for it in range(args.warmup + args.steps):
+        h, tb = timed(lambda: mphf.build(keys, args.gamma, 0))
+        _, tl = timed(lambda: h.lookup(keys, out=out))
+        if it >= args.warmup:
+            build_ms.append(tb)
+            lookup_ms.append(tl)
+        if stats is None:
+            stats = h.stats()
+        h.close()
+        print(f"# plain step {it}: build {tb:.1f} ms lookup {tl:.1f} ms", file=sys.stderr, flush=True)
+    plain_ok = bijective(out)
+    # per-level placed keys against the exact occupancy mean (structured keys, hashed)
+    worst = 0.0
+    for d in range(stats["num_levels"]):
+        nd, md, wd = stats["level_n"][d], stats["level_m"][d], stats["level_weight"][d]
+        if nd < 100:
+            break
+        mu = nd * (1 - 1 / md) ** (nd - 1)
+        var = nd * (nd - 1) * (1 - 2 / md) ** (nd - 2) + mu - mu * mu
+        worst = max(worst, abs(wd - mu) / math.sqrt(max(var, 1e-9)))
+
+    # batched path: hash sets of about n / 2^bits keys
+    bits = int(args.kmer_set_bits)
+    (grouped, off), tpart = timed(lambda: mphf.partition_sets(keys, bits, seed=0x5E7))
+    ids, tids = timed(lambda: mphf.set_ids(keys, bits, seed=0x5E7))
+    bb_ms, bl_ms = [], []
+    for it in range(args.warmup + args.steps):
+        b, tb = timed(lambda: mphf.build_batch(grouped, off, args.gamma, 0))
+        _, tl = timed(lambda: b.lookup(ids, keys, out=out))
+        if it >= args.warmup:
+            bb_ms.append(tb)
+            bl_ms.append(tl)
+        tot = b.totals()
+        b.close()
+        print(f"# batched step {it}: build {tb:.1f} ms lookup {tl:.1f} ms", file=sys.stderr, flush=True)
+    batch_ok = bijective(out, off[ids])
+    import statistics
+    tb, tl = statistics.median(build_ms), statistics.median(lookup_ms)
+    bb, bl = statistics.median(bb_ms), statistics.median(bl_ms)
+    res = {
+        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "value": n / ((tb + tl) / 1e3), "unit": "keys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb + tl,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"canonical {k}-mers of a {nb}-base SplitMix64 (seed 5) DNA sequence, first "
+                               f"{target} distinct in sequence order, gamma={args.gamma}",
+                   "keys": n, "bases": nb, "k": k, "gamma": args.gamma, "key_bytes": 8 * n},
+        "plain": {"build_keys_per_s": n / (tb / 1e3), "lookup_queries_per_s": n / (tl / 1e3),
+                  "build_ms": tb, "lookup_ms": tl, "labels_bijective": plain_ok,
+                  "levels": stats["num_levels"], "bits_per_key": stats["bits_per_key"],
+                  "level_n": stats["level_n"][:stats["num_levels"]],
+                  "worst_level_sigma": worst, "peak_bytes": stats["peak_bytes"]},
+        "batched": {"sets": 1 << bits, "partition_ms": tpart, "set_ids_ms": tids,
+                    "build_keys_per_s": n / (bb / 1e3), "lookup_queries_per_s": n / (bl / 1e3),
+                    "build_ms": bb, "lookup_ms": bl, "labels_bijective": batch_ok,
+                    "bits_per_key": tot["bits_per_key"]},
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["plain", "batch", "serve"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer"], default="plain")
+    ap.add_argument("--kmer-bases", type=float, default=4.2e9, help="kmer: sequence length")
+    ap.add_argument("--kmer-keys", type=float, default=4e9, help="kmer: distinct k-mers kept")
+    ap.add_argument("--kmer-set-bits", type=float, default=15, help="kmer: log2 of the batched sets")
     ap.add_argument("--functions", type=float, default=64, help="serve: resident functions")
     ap.add_argument("--serve-scale", type=float, default=1.0, help="serve: function size scale")
     ap.add_argument("--requests", type=float, default=2000, help="serve: requests per run")
@@ -387,6 +500,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "kmer":
+        bench_kmer(args)
         return
 
     import torch

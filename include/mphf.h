@@ -287,6 +287,31 @@ void mphf_server_destroy(mphf_server_t* s);
 mphf_status mphf_host_alloc(uint64_t bytes, void** out);
 void mphf_host_free(void* p);
 
+/* ---- k-mer keys (the de Bruijn graph use of Section 1) -----------------------------------------
+ * A DNA sequence of nbases bases packed 2 bits per base (A=0, C=1, G=2, T=3): base i is bits
+ * 63-2(i%32) .. 62-2(i%32) of seq[i/32] (first base of a word in its most significant pair). */
+
+/* out[p] = canonical k-mer at p for p in [0, nbases-k]: the smaller of the forward k-mer (bases
+ * p..p+k-1, first base most significant, 2k bits) and its reverse complement (bases reversed, each
+ * x -> 3-x).  1 <= k <= 32; device arrays; asynchronous on `stream`. */
+mphf_status mphf_kmers(const uint64_t* seq, uint64_t nbases, uint32_t k, uint64_t* out, void* stream);
+
+/* The first min(target, distinct) distinct keys of keys[0..n) in order of first occurrence, into the
+ * device array out (room for target keys); *nout gets their number.  Synchronous.  Uses about
+ * 17.5 n bytes of temporary device memory (a sorted copy finds the keys that repeat). */
+mphf_status mphf_first_occurrences(const uint64_t* keys, uint64_t n, uint64_t target, uint64_t* out,
+                                   uint64_t* nout, void* stream);
+
+/* Hash partition of n keys into 2^bits sets (set of x = top `bits` bits of fmix64(x XOR seed)):
+ * out gets the keys grouped by set (any order within a set), offsets (2^bits + 1 device u64) the
+ * start of each set: the input of mphf_build_batch.  Synchronous.  1 <= bits <= 24. */
+mphf_status mphf_partition_sets(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed,
+                                uint64_t* out, uint64_t* offsets, void* stream);
+
+/* out[i] = the set of keys[i] under the same partition (the set ids of batched lookups). */
+mphf_status mphf_set_ids(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed, uint64_t* out,
+                         void* stream);
+
 /* Free the build temporaries the library keeps per device between builds (a few times the
  * largest key set built so far).  Must not overlap a build. */
 mphf_status mphf_trim(void);

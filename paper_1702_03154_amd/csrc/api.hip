@@ -908,6 +908,128 @@ const char* mphf_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- k-mer workload
+
+extern "C" {
+
+mphf_status mphf_kmers(const uint64_t* seq, uint64_t nbases, uint32_t k, uint64_t* out, void* stream) {
+    if (k < 1 || k > 32) return fail(MPHF_E_INVALID, "k must be 1..32");
+    if (nbases < k) return MPHF_OK;
+    if (!seq || !out || !is_device_ptr(seq) || !is_device_ptr(out))
+        return fail(MPHF_E_INVALID, "seq and out must be device memory");
+    HIP_TRY(launch_kmers(seq, nbases - k + 1, k, out, (hipStream_t)stream), "kmers");
+    return MPHF_OK;
+}
+
+mphf_status mphf_first_occurrences(const uint64_t* keys, uint64_t n, uint64_t target, uint64_t* out,
+                                   uint64_t* nout, void* stream) {
+    if (!nout) return fail(MPHF_E_INVALID, "nout is NULL");
+    *nout = 0;
+    if (!n || !target) return MPHF_OK;
+    if (!keys || !out || !is_device_ptr(keys) || !is_device_ptr(out))
+        return fail(MPHF_E_INVALID, "keys and out must be device memory");
+    const hipStream_t s = (hipStream_t)stream;
+    mphf_status st;
+    Arena ar(0, s);
+    // keys that repeat: adjacent equal keys after a sort of a copy
+    uint64_t *a, *b, *offs, *tiles, *cnt64;
+    uint32_t* counts;
+    const uint64_t nc = radix_tmp_counts(n);
+    if ((st = ar.alloc(&a, n, "sort copy")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&b, n, "sort scratch")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&counts, nc, "sort counts")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&offs, nc, "sort offsets")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&tiles, scan_tmp_tiles(nc), "sort tiles")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&cnt64, 2, "counters")) != MPHF_OK) return st;
+    HIP_TRY(hipMemcpyAsync(a, keys, 8 * n, hipMemcpyDeviceToDevice, s), "copy keys");
+    HIP_TRY(radix_sort_u64(a, b, n, counts, offs, tiles, s), "sort");
+    ar.release(b);
+    ar.release(counts);
+    ar.release(offs);
+    const uint64_t cap = std::min<uint64_t>(n, 1ull << 24);
+    uint64_t* rep;
+    if ((st = ar.alloc(&rep, cap, "repeated keys")) != MPHF_OK) return st;
+    HIP_TRY(launch_zero(cnt64, 2, s), "zero counters");
+    HIP_TRY(launch_repeated(a, n, rep, cap, (unsigned long long*)cnt64, s), "repeated");
+    uint64_t nrep = 0;
+    HIP_TRY(hipMemcpyAsync(&nrep, cnt64, 8, hipMemcpyDeviceToHost, s), "read back");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    ar.release(a);
+    if (nrep > cap) return fail(MPHF_E_INVALID, "more than 2^24 distinct keys repeat");
+    std::vector<uint64_t> removed;
+    if (nrep) {
+        std::vector<uint64_t> h(nrep);
+        HIP_TRY(hipMemcpy(h.data(), rep, 8 * nrep, hipMemcpyDeviceToHost), "copy repeated");
+        std::sort(h.begin(), h.end());
+        HIP_TRY(hipMemcpy(rep, h.data(), 8 * nrep, hipMemcpyHostToDevice), "copy repeated");
+        unsigned long long* first;
+        uint64_t* later;
+        const uint64_t cap2 = std::min<uint64_t>(n, 1ull << 25);
+        if ((st = ar.alloc(&first, nrep, "first positions")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&later, cap2, "later positions")) != MPHF_OK) return st;
+        HIP_TRY(launch_first_pos(keys, n, rep, nrep, first, s), "first positions");
+        HIP_TRY(launch_later_pos(keys, n, rep, nrep, first, later, cap2, (unsigned long long*)cnt64 + 1, s),
+                "later positions");
+        uint64_t nrem = 0;
+        HIP_TRY(hipMemcpyAsync(&nrem, cnt64 + 1, 8, hipMemcpyDeviceToHost, s), "read back");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (nrem > cap2) return fail(MPHF_E_INVALID, "more than 2^25 repeated positions");
+        removed.resize(nrem);
+        HIP_TRY(hipMemcpy(removed.data(), later, 8 * nrem, hipMemcpyDeviceToHost), "copy positions");
+        std::sort(removed.begin(), removed.end());
+    }
+    // the first `target` kept positions end at P: every removed position below P moves P by one
+    uint64_t j = 0;
+    uint64_t P = n, kept = n - removed.size();
+    if (kept > target) {
+        while (j < removed.size() && removed[j] < target + j) ++j;
+        P = target + j;
+        kept = target;
+    } else {
+        j = removed.size();
+    }
+    uint64_t* drem = nullptr;
+    if (j) {
+        if ((st = ar.alloc(&drem, j, "removed positions")) != MPHF_OK) return st;
+        HIP_TRY(hipMemcpyAsync(drem, removed.data(), 8 * j, hipMemcpyHostToDevice, s), "copy positions");
+    }
+    HIP_TRY(launch_drop_positions(keys, P, drem, j, out, s), "compact");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    *nout = kept;
+    return MPHF_OK;
+}
+
+mphf_status mphf_partition_sets(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed, uint64_t* out,
+                                uint64_t* offsets, void* stream) {
+    if (bits < 1 || bits > 24) return fail(MPHF_E_INVALID, "bits must be 1..24");
+    if (!offsets || !is_device_ptr(offsets) || (n && (!keys || !out || !is_device_ptr(keys) || !is_device_ptr(out))))
+        return fail(MPHF_E_INVALID, "keys, out and offsets must be device memory");
+    const hipStream_t s = (hipStream_t)stream;
+    mphf_status st;
+    Arena ar(0, s);
+    const uint64_t nb = 1ull << bits;
+    uint32_t* counts;
+    unsigned long long* cursor;
+    uint64_t* tiles;
+    if ((st = ar.alloc(&counts, nb + 1, "set counts")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&cursor, nb, "set cursors")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&tiles, scan_tmp_tiles(nb + 1), "scan tiles")) != MPHF_OK) return st;
+    HIP_TRY(launch_set_partition(keys, n, seed, bits, counts, offsets, cursor, tiles, out, s), "partition");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    return MPHF_OK;
+}
+
+mphf_status mphf_set_ids(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed, uint64_t* out,
+                         void* stream) {
+    if (bits < 1 || bits > 24) return fail(MPHF_E_INVALID, "bits must be 1..24");
+    if (n && (!keys || !out || !is_device_ptr(keys) || !is_device_ptr(out)))
+        return fail(MPHF_E_INVALID, "keys and out must be device memory");
+    HIP_TRY(launch_set_ids(keys, n, seed, bits, out, (hipStream_t)stream), "set ids");
+    return MPHF_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- shared with the serving loop
 
 namespace mphf_api {

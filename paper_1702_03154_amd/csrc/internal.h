@@ -149,6 +149,23 @@ hipError_t launch_rank(const uint64_t* words, uint64_t total_words, uint32_t ran
 uint64_t scan_tmp_tiles(uint64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
                                  hipStream_t s);
+// k-mer workload (kmer.hip)
+hipError_t launch_kmers(const uint64_t* seq, uint64_t npos, uint32_t k, uint64_t* out, hipStream_t s);
+hipError_t launch_repeated(const uint64_t* sorted, uint64_t n, uint64_t* out, uint64_t cap,
+                           unsigned long long* count, hipStream_t s);
+hipError_t launch_first_pos(const uint64_t* keys, uint64_t n, const uint64_t* rep, uint64_t nrep,
+                            unsigned long long* first, hipStream_t s);
+hipError_t launch_later_pos(const uint64_t* keys, uint64_t n, const uint64_t* rep, uint64_t nrep,
+                            const unsigned long long* first, uint64_t* out, uint64_t cap, unsigned long long* count,
+                            hipStream_t s);
+hipError_t launch_drop_positions(const uint64_t* keys, uint64_t n, const uint64_t* removed, uint64_t nrem,
+                                 uint64_t* out, hipStream_t s);
+hipError_t launch_set_partition(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t bits, uint32_t* counts,
+                                uint64_t* offsets, unsigned long long* cursor, uint64_t* tiles, uint64_t* out,
+                                hipStream_t s);
+hipError_t launch_set_ids(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t bits, uint64_t* out,
+                          hipStream_t s);
+
 // LSD radix sort of n keys; `a` holds the input and receives the sorted keys, `b` is scratch.
 uint64_t radix_tmp_counts(uint64_t n);
 hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t n, uint32_t* counts,

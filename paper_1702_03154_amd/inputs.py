@@ -12,6 +12,8 @@ arrays, no rank.  It only produces the workloads the paper measures on:
   size of set j is floor(lo * (hi/lo)^u_j) with u_j the top 53 bits of output
   j of a SplitMix64 stream over 2^53, and set j holds the first size_j outputs
   of the SplitMix64 stream seeded with output j of a second stream;
+* a DNA sequence for the k-mer workload: 2 bits per base (A=0, C=1, G=2, T=3),
+  32 bases per SplitMix64 output, the first base in the two most significant bits;
 * a seeded permutation of [0, N) for the shuffled query order: a 4-round
   balanced Feistel network on 2h bits (2^(2h) >= N) with cycle walking
   (Black and Rogaway, CT-RSA 2002), so it is a bijection of [0, N).
@@ -144,3 +146,9 @@ def set_keys(sizes: torch.Tensor, seed: int = 4, device="cpu", chunk: int = 1 <<
         z = (i + 1) * _s64(_GOLDEN) + set_seeds[j]
         out[lo:hi] = _mix(z)
     return out
+
+
+def dna_sequence(nbases: int, seed: int = 5, device="cpu") -> torch.Tensor:
+    """A uniform random ACGT sequence of nbases bases, 2-bit packed (32 per word, first base in the
+    top two bits): the first ceil(nbases/32) SplitMix64 outputs of ``seed``."""
+    return splitmix64(seed, (nbases + 31) // 32, 0, device)

@@ -112,6 +112,10 @@ def lib() -> C.CDLL:
             "mphf_batch_status": (st, [vp, vp]),
             "mphf_batch_export_sectors": (st, [vp, u64, vp, u64]),
             "mphf_last_error": (C.c_char_p, []),
+            "mphf_kmers": (st, [vp, u64, u32, vp, vp]),
+            "mphf_first_occurrences": (st, [vp, u64, u64, vp, C.POINTER(C.c_uint64), vp]),
+            "mphf_partition_sets": (st, [vp, u64, u32, u64, vp, vp, vp]),
+            "mphf_set_ids": (st, [vp, u64, u32, u64, vp, vp]),
             "mphf_server_default_opts": (st, [C.POINTER(ServerOpts)]),
             "mphf_server_create": (st, [C.POINTER(ServerOpts), C.POINTER(vp)]),
             "mphf_server_register": (st, [vp, vp, C.POINTER(C.c_uint32)]),
@@ -357,6 +361,45 @@ def positions(keys: torch.Tensor, level_seed: int, m: int, stream=None) -> torch
     if keys.numel():
         _check(lib().mphf_positions(_dev(keys, "keys"), keys.numel(), level_seed & (2**64 - 1), m,
                                     _dev(out, "out"), _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- k-mer keys
+
+def kmers(seq: torch.Tensor, nbases: int, k: int = 31, stream=None) -> torch.Tensor:
+    """Canonical k-mers at every position of a 2-bit packed sequence (mphf_kmers)."""
+    n = max(0, nbases - k + 1)
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=seq.device)
+    _check(lib().mphf_kmers(_dev(seq, "seq"), nbases, k, _dev(out, "out"), _stream(stream)))
+    return out[:n]
+
+
+def first_occurrences(keys: torch.Tensor, target: int, stream=None) -> torch.Tensor:
+    """The first `target` distinct keys in order of first occurrence (mphf_first_occurrences)."""
+    out = torch.empty(max(1, min(target, keys.numel())), dtype=torch.int64, device=keys.device)
+    n = C.c_uint64()
+    if keys.numel() and target:
+        _check(lib().mphf_first_occurrences(_dev(keys, "keys"), keys.numel(), target, _dev(out, "out"),
+                                            C.byref(n), _stream(stream)))
+    return out[:n.value]
+
+
+def partition_sets(keys: torch.Tensor, bits: int, seed: int = 0, stream=None):
+    """Keys grouped into 2^bits hash sets and the set offsets (mphf_partition_sets)."""
+    out = torch.empty_like(keys)
+    off = torch.empty((1 << bits) + 1, dtype=torch.int64, device=keys.device)
+    kp = _dev(keys, "keys") if keys.numel() else 0
+    op = _dev(out, "out") if keys.numel() else 0
+    _check(lib().mphf_partition_sets(kp, keys.numel(), bits, seed & (2**64 - 1), op, _dev(off, "offsets"),
+                                     _stream(stream)))
+    return out, off
+
+
+def set_ids(keys: torch.Tensor, bits: int, seed: int = 0, stream=None) -> torch.Tensor:
+    out = torch.empty_like(keys)
+    if keys.numel():
+        _check(lib().mphf_set_ids(_dev(keys, "keys"), keys.numel(), bits, seed & (2**64 - 1), _dev(out, "out"),
+                                  _stream(stream)))
     return out
 
 

@@ -1,0 +1,122 @@
+"""GPU parity of the k-mer workload: canonical k-mers, first occurrences and the hash partition
+against the string-based oracle, and the method on structured (k-mer) keys: the per-level sizes
+must still follow the occupancy statistics of Section 2.3 and the batched path over hash sets must
+give a bijection whose sets equal standalone builds."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import kmers as K
+from oracle import mphf_oracle as O
+from paper_1702_03154_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_03154_amd import mphf
+    mphf.lib()
+    return mphf
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 21, 31, 32])
+@pytest.mark.parametrize("nbases", [40, 97, 1000, 4099])
+def test_kmers_equal_the_oracle(M, k, nbases):
+    seq = I.dna_sequence(nbases, seed=5 + k)
+    got = host(M.kmers(seq.cuda(), nbases, k))
+    assert np.array_equal(got, K.canonical_kmers(seq.numpy().view(np.uint64), nbases, k))
+
+
+def test_kmers_short_sequence_and_bad_k(M):
+    seq = I.dna_sequence(20).cuda()
+    assert M.kmers(seq, 20, 31).numel() == 0
+    with pytest.raises(M.MphfError):
+        M.kmers(seq, 20, 33)
+
+
+def low_complexity(nbases, seed):
+    """A sequence with many repeated k-mers: a short motif repeated, with rare substitutions."""
+    rng = np.random.default_rng(seed)
+    motif = rng.integers(0, 4, size=37)
+    bases = np.resize(motif, nbases)
+    flips = rng.random(nbases) < 0.01
+    bases[flips] = rng.integers(0, 4, size=int(flips.sum()))
+    words = np.zeros((nbases + 31) // 32, dtype=np.uint64)
+    for i, b in enumerate(bases):
+        words[i // 32] |= np.uint64(int(b)) << np.uint64(62 - 2 * (i % 32))
+    return words
+
+
+@pytest.mark.parametrize("target", [1, 50, 600, 10 ** 6])
+def test_first_occurrences_equal_the_oracle(M, target):
+    words = low_complexity(6000, 3)
+    kmers = M.kmers(torch.from_numpy(words.view(np.int64)).cuda(), 6000, 21)
+    got = host(M.first_occurrences(kmers, target))
+    assert np.array_equal(got, K.first_occurrences(host(kmers), target))
+
+
+def test_first_occurrences_of_random_keys_keep_everything(M):
+    k = I.keys(200_000, 9).cuda()
+    assert torch.equal(M.first_occurrences(k, 10 ** 9), k)
+    assert torch.equal(M.first_occurrences(k, 1234), k[:1234])
+
+
+def test_partition_sets(M):
+    keys = I.keys(300_000, 10).cuda()
+    out, off = M.partition_sets(keys, 8, seed=77)
+    offn = off.cpu().numpy()
+    assert offn[0] == 0 and offn[-1] == keys.numel() and np.all(np.diff(offn) >= 0)
+    ids = M.set_ids(out, 8, seed=77).cpu().numpy()
+    want = np.repeat(np.arange(256), np.diff(offn))
+    assert np.array_equal(ids, want)
+    assert np.array_equal(np.sort(host(out)), np.sort(host(keys)))
+
+
+def occupancy(n, m):
+    """Exact mean and standard deviation of the number of cells hit exactly once when n keys fall
+    uniformly into m cells (the textbook occupancy problem)."""
+    p1 = n * (1 - 1 / m) ** (n - 1)
+    e2 = n * (n - 1) * (1 - 2 / m) ** (n - 2)
+    var = e2 + p1 - p1 * p1
+    return p1, math.sqrt(max(var, 0.0))
+
+
+def test_levels_of_kmer_keys_follow_the_occupancy_statistics(M):
+    """Structured keys (overlapping k-mers of one sequence) hashed by fmix64: every level's placed
+    count within 6 sigma of the exact occupancy mean (Section 2.3)."""
+    nb = 3_000_000
+    km = M.kmers(I.dna_sequence(nb, seed=11).cuda(), nb, 31)
+    keys = M.first_occurrences(km, 2_000_000)
+    assert keys.numel() == 2_000_000
+    h = M.build(keys, 2.0, 0)
+    st = h.stats()
+    for d in range(min(st["num_levels"], 8)):
+        n, m, w = st["level_n"][d], st["level_m"][d], st["level_weight"][d]
+        mu, sd = occupancy(n, m)
+        assert abs(w - mu) <= 6 * sd + 1, (d, n, m, w, mu, sd)
+    lab = h.lookup(keys)
+    assert torch.equal(torch.sort(lab).values, torch.arange(1, keys.numel() + 1, device=lab.device))
+
+
+def test_batched_path_over_hash_sets(M):
+    nb = 1_200_000
+    keys = M.first_occurrences(M.kmers(I.dna_sequence(nb, seed=12).cuda(), nb, 31), 1_000_000)
+    grouped, off = M.partition_sets(keys, 6, seed=5)
+    b = M.build_batch(grouped, off, 2.0, 0)
+    ids = M.set_ids(keys, 6, seed=5)
+    lab = b.lookup(ids, keys)
+    glob = off[ids] + lab - 1
+    assert torch.equal(torch.sort(glob).values, torch.arange(keys.numel(), device=glob.device))
+    for s in (0, 17, 63):
+        ks = host(grouped[int(off[s]):int(off[s + 1])])
+        st = O.build(ks, 2.0, 0)
+        assert np.array_equal(b.export_set(s)["words"], st.words)
