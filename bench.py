@@ -379,6 +379,7 @@ def bench_kmer(args):
     keys = mphf.first_occurrences(km, target)
     del km
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     n = keys.numel()
     print(f"# {n} distinct canonical {k}-mers from {nb} bases in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
@@ -421,11 +422,15 @@ def bench_kmer(args):
         nd, md, wd = stats["level_n"][d], stats["level_m"][d], stats["level_weight"][d]
         if nd < 100:
             break
-        mu = nd * (1 - 1 / md) ** (nd - 1)
-        var = nd * (nd - 1) * (1 - 2 / md) ** (nd - 2) + mu - mu * mu
+        # exact occupancy moments: E[X] = n (1-1/m)^(n-1), E[X(X-1)] = n (n-1) (1-1/m) (1-2/m)^(n-2)
+        mu = nd * math.exp((nd - 1) * math.log1p(-1.0 / md))
+        e2 = (md - 1) / md * nd * (nd - 1) * math.exp((nd - 2) * math.log1p(-2.0 / md))
+        var = e2 + mu - mu * mu
         worst = max(worst, abs(wd - mu) / math.sqrt(max(var, 1e-9)))
 
-    # batched path: hash sets of about n / 2^bits keys
+    # batched path: hash sets of about n / 2^bits keys (the plain build's cached workspace is
+    # released first: both paths together would not fit)
+    mphf.trim()
     bits = int(args.kmer_set_bits)
     (grouped, off), tpart = timed(lambda: mphf.partition_sets(keys, bits, seed=0x5E7))
     ids, tids = timed(lambda: mphf.set_ids(keys, bits, seed=0x5E7))

@@ -1086,6 +1086,7 @@ struct mphf_batch {
     uint64_t max_m = 0;
     uint32_t grid = 0;
     BatchLaunch cfg;
+    bool retried = false;   // the one-shot build was redone with worst-case regions
 };
 
 namespace {
@@ -1218,7 +1219,8 @@ mphf_status check_batch_args(const uint64_t* offsets, uint64_t nsets, double gam
 // Offsets checked, worst-case regions sized, size-ordered work queue, and every buffer a build needs.
 // `keep` = a planned batch: everything lives in the handle; else the temporaries are borrowed.
 mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* offsets, uint64_t nsets, double gamma,
-                        uint64_t seed, const mphf_opts& o, bool keep, hipStream_t s, BatchMem& mem, uint64_t* pin) {
+                        uint64_t seed, const mphf_opts& o, bool keep, double slack, hipStream_t s, BatchMem& mem,
+                        uint64_t* pin) {
     mphf_status st;
     b->nsets = nsets;
     b->gamma = gamma;
@@ -1254,7 +1256,8 @@ mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* off
     }
     HIP_TRY(launch_zero32(hist, 2 * ncls + 2, s), "zero classes");
     HIP_TRY(launch_zero((uint64_t*)info, 4, s), "zero counters");
-    HIP_TRY(launch_batch_prepare(b->offsets, nsets, gamma, o.max_levels, BATCH_MAX_M, bound, sbound, hist, info, s),
+    HIP_TRY(launch_batch_prepare(b->offsets, nsets, gamma, o.max_levels, BATCH_MAX_M, slack, bound, sbound, hist,
+                                 info, s),
             "prepare");
     HIP_TRY(launch_exclusive_scan(bound, b->region_w, S1, tiles, s), "region prefix");
     HIP_TRY(launch_exclusive_scan(sbound, b->sreg_base, S1, tiles, s), "sector prefix");
@@ -1320,6 +1323,7 @@ hipError_t batch_levels(const mphf_batch* b, const uint64_t* keys, hipStream_t s
 
 mphf_status batch_failure(uint64_t word) {
     const uint32_t bad = (uint32_t)word, first_bad = (uint32_t)(word >> 32);
+    if (bad & 4u) return fail(MPHF_E_DEVICE, "set " + std::to_string(first_bad) + " outgrew its region");
     if (bad & 1u) return fail(MPHF_E_DUPLICATE_KEYS, "duplicate keys in set " + std::to_string(first_bad));
     if (bad & 2u)
         return fail(MPHF_E_INVALID, "set " + std::to_string(first_bad) +
@@ -1343,11 +1347,25 @@ mphf_status build_batch_impl(const uint64_t* keys, const uint64_t* offsets, uint
     if (!pin) return fail(MPHF_E_NOMEM, "pinned read-back buffer");
     Arena ar(o.mem_budget, s);
     BatchMem mem(ar, b->device, !planned && o.mem_budget == 0);
-    if ((st = batch_setup(b, keys, offsets, nsets, gamma, seed, o, planned, s, mem, pin)) != MPHF_OK) return st;
+    // a one-shot build first sizes each set's regions for the expected level sizes (with slack);
+    // a set that outgrows them (vanishingly rare but possible) makes the batch run again with the
+    // worst case.  A planned batch always takes the worst case.
+    const double slack = planned ? 0.0 : 1.5 * std::exp(1.0 / gamma) * 1.0;
+    if ((st = batch_setup(b, keys, offsets, nsets, gamma, seed, o, planned, slack, s, mem, pin)) != MPHF_OK) return st;
     tr.mark("batch setup", (long)b->nkeys);
     if (!planned) {
         if (b->nkeys && !keys) return fail(MPHF_E_INVALID, "keys is NULL");
         HIP_TRY(batch_levels(b, keys, s), "batch levels");
+        HIP_TRY(hipMemcpyAsync(pin + 5, b->fail32, 8, hipMemcpyDeviceToHost, s), "read back");
+        HIP_TRY(hipStreamSynchronize(s), "batch sync");
+        if (((uint32_t)pin[5] & 4u) && !((uint32_t)pin[5] & 3u)) {
+            for (void* p : b->mem) ar.release(p);
+            b->mem.clear();
+            if ((st = batch_setup(b, keys, offsets, nsets, gamma, seed, o, false, 0.0, s, mem, pin)) != MPHF_OK)
+                return st;
+            HIP_TRY(batch_levels(b, keys, s), "batch levels");
+            b->retried = true;
+        }
         const uint64_t S1 = nsets + 1;
         uint64_t *spre, *lpre, *tiles;
         auto lay = [&](Carver& c) {

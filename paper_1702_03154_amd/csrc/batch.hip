@@ -33,12 +33,12 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Per set: worst-case staging words and lookup sectors, size class histogram, offset checks and the
-// largest set.  info[0]: largest n (atomicMax); info[1]: flags (1 offsets decrease, 2 offsets[0] != 0,
+// Per set: staging words and lookup sectors (worst case, or the expected size with slack), size class
+// histogram, offset checks and the largest set.  info[0]: largest n (atomicMax); info[1]: flags (1 offsets decrease, 2 offsets[0] != 0,
 // 4 a set too large for the LDS levels).
 __global__ void __launch_bounds__(PT)
 k_batch_prepare(const uint64_t* __restrict__ offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
-                uint32_t* __restrict__ bound, uint32_t* __restrict__ sbound, uint32_t* __restrict__ hist,
+                double slack, uint32_t* __restrict__ bound, uint32_t* __restrict__ sbound, uint32_t* __restrict__ hist,
                 unsigned long long* __restrict__ info) {
     __shared__ uint32_t lh[NCLASS];
     __shared__ unsigned long long smax;
@@ -67,7 +67,11 @@ k_batch_prepare(const uint64_t* __restrict__ offsets, uint64_t nsets, double gam
         if (dm > (double)max_m) {
             flags |= 4;
         } else if (n) {
-            w = D * (uint32_t)(((uint64_t)dm + 63) >> 6);
+            // every level is at most m0 bits plus padding; with slack > 0, the expected total
+            // (slack * m0 bits) plus one word of padding per level instead
+            const uint64_t w0 = ((uint64_t)dm + 63) >> 6;
+            const uint64_t tight = (uint64_t)ceil(slack * dm / 64.0) + D;
+            w = (uint32_t)(slack > 0 && tight < D * w0 ? tight : D * w0);
             ns = (uint32_t)(((uint64_t)w * 64 + SEC_BITS - 1) / SEC_BITS);
         }
         bound[s] = w;
@@ -159,10 +163,16 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
         const uint64_t* F = keys + k0;
         uint64_t* scr = scratch + k0;
         uint64_t* A = region + region_w[s];
+        const uint64_t cap_bits = 64 * (region_w[s + 1] - region_w[s]);
         uint64_t off = 0;
         uint32_t d = 0;
+        bool overflow = false;
         while (n > 0 && d < D) {
             const uint64_t m = (uint64_t)ceil(gamma * (double)n);
+            if (off + 64 * ((m + 63) >> 6) > cap_bits) {   // uniform: stop, the batch is redone larger
+                overflow = true;
+                break;
+            }
             const uint32_t aw = (uint32_t)((m + 31) >> 5);
             uint32_t* Ab = lds;
             uint32_t* Cb = lds + aw + (aw & 1);
@@ -256,7 +266,7 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
         // leftovers: sorted ascending by counting, back into the front of the set's scratch region
         // (there are almost never more than a few; above left_cap the set is reported and the batch
         // fails)
-        if (n > 0 && n <= left_cap) {
+        if (n > 0 && n <= left_cap && !overflow) {
             uint64_t* lk = (uint64_t*)lds;   // at most left_cap keys
             for (uint64_t i = threadIdx.x; i < n; i += BW) lk[i] = scr[i];
             __syncthreads();
@@ -310,7 +320,7 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
             st.left_off = k0;
             st.nlev = d;
             st.nleft = (uint32_t)n;
-            st.status = s_status | (n > left_cap ? 2u : 0u);
+            st.status = overflow ? 4u : (s_status | (n > left_cap ? 2u : 0u));
             st.pad = 0;
         }
         __syncthreads();
@@ -487,10 +497,10 @@ uint32_t prep_grid(uint64_t items) {
 uint32_t batch_classes() { return NCLASS; }
 
 hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
-                                uint32_t* bound, uint32_t* sbound, uint32_t* hist, unsigned long long* info,
-                                hipStream_t s) {
+                                double slack, uint32_t* bound, uint32_t* sbound, uint32_t* hist,
+                                unsigned long long* info, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_prepare, dim3(prep_grid(nsets + 1)), dim3(PT), 0, s, offsets, nsets, gamma, D,
-                       max_m, bound, sbound, hist, info);
+                       max_m, slack, bound, sbound, hist, info);
     return hipGetLastError();
 }
 

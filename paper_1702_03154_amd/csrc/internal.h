@@ -77,7 +77,7 @@ struct BatchSet {
     uint64_t left_off;     // first of the set's fallback keys in the fallback array
     uint32_t nlev;
     uint32_t nleft;
-    uint32_t status;       // bit 0: duplicate keys; bit 1: too many leftovers for the batch kernel
+    uint32_t status;       // bit 0: duplicate keys; bit 1: too many leftovers; bit 2: region too small
     uint32_t pad;
 };
 struct BatchLevel {
@@ -194,8 +194,8 @@ struct BatchLaunch {
 
 uint32_t batch_classes();
 hipError_t launch_batch_prepare(const uint64_t* offsets, uint64_t nsets, double gamma, uint32_t D, uint64_t max_m,
-                                uint32_t* bound, uint32_t* sbound, uint32_t* hist, unsigned long long* info,
-                                hipStream_t s);
+                                double slack, uint32_t* bound, uint32_t* sbound, uint32_t* hist,
+                                unsigned long long* info, hipStream_t s);
 hipError_t launch_batch_order(const uint64_t* offsets, uint64_t nsets, const uint32_t* hist, uint32_t* cursor,
                               uint32_t* order, hipStream_t s);
 hipError_t launch_batch_reset(unsigned long long* queue, uint32_t* fail, hipStream_t s);

@@ -364,6 +364,11 @@ def positions(keys: torch.Tensor, level_seed: int, m: int, stream=None) -> torch
     return out
 
 
+def trim() -> None:
+    """Release the build workspaces the library caches per device (mphf_trim)."""
+    _check(lib().mphf_trim())
+
+
 # ---------------------------------------------------------------- k-mer keys
 
 def kmers(seq: torch.Tensor, nbases: int, k: int = 31, stream=None) -> torch.Tensor:

@@ -4,6 +4,8 @@ and against a standalone build of the same set through the plain entry point.
 
 Sets are independent functions (Section 2: the levels of a key set depend only on its keys,
 gamma and the level seeds), so a batch must reproduce each standalone result exactly."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -316,3 +318,43 @@ def test_tuner_picks_a_candidate_and_caches_it(M, tmp_path, monkeypatch):
     b = M.build_batch(keys, off, 2.0, 0, launch=launch)
     ref = M.build_batch(keys, off, 2.0, 0)
     assert torch.equal(b.lookup(ids, keys), ref.lookup(ids, keys))
+
+
+def test_batch_set_outgrowing_its_expected_region(M):
+    """Keys crafted so that every key collides at level 0 (pairs with equal level-0 positions): the
+    set's levels then total about 2.65 m0 bits, more than the 1.5 e^(1/gamma) m0 the one-shot build
+    reserves first, so the batch is redone with worst-case regions; the result must not change."""
+    U64 = (1 << 64) - 1
+    inv1 = pow(0xFF51AFD7ED558CCD, -1, 1 << 64)
+    inv2 = pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)
+
+    def unfmix64(y):
+        z = y ^ (y >> 33)
+        z = (z * inv2) & U64
+        z ^= z >> 33
+        z = (z * inv1) & U64
+        return z ^ (z >> 33)
+
+    n = 50_000
+    m0 = 2 * n
+    s0 = O.level_seeds(0, 1)[0]
+    rng = np.random.default_rng(60)
+    crafted = []
+    for h in rng.integers(0, 1 << 62, size=n // 2, dtype=np.uint64).tolist():
+        crafted += [unfmix64(h) ^ s0, unfmix64(h + m0) ^ s0]
+    crafted = np.array(crafted, dtype=np.uint64)
+    assert len(np.unique(crafted)) == n
+    assert len(np.unique(O.level_positions(crafted, s0, m0))) <= n // 2
+    other = I.keys(3000, 61).numpy().view(np.uint64)
+    keys = np.concatenate([other[:1000], crafted, other[1000:]])
+    off = torch.tensor([0, 1000, 1000 + n, 3000 + n], dtype=torch.int64)
+    b = M.build_batch(torch.from_numpy(keys.view(np.int64)).cuda(), off.cuda(), 2.0, 0)
+    ids = torch.repeat_interleave(torch.arange(3), off[1:] - off[:-1]).cuda()
+    lab = host(b.lookup(ids, torch.from_numpy(keys.view(np.int64)).cuda()))
+    offn = off.numpy()
+    for s in range(3):
+        ks = keys[offn[s]:offn[s + 1]]
+        st = check_set(b, s, ks, 2.0, 0, 25, lab[offn[s]:offn[s + 1]])
+        if s == 1:
+            assert st.levels[1].n == n   # nothing placed at level 0
+            assert st.total_bits > 1.5 * math.exp(0.5) * m0 + 64 * 25

@@ -83,11 +83,12 @@ def test_partition_sets(M):
 
 def occupancy(n, m):
     """Exact mean and standard deviation of the number of cells hit exactly once when n keys fall
-    uniformly into m cells (the textbook occupancy problem)."""
-    p1 = n * (1 - 1 / m) ** (n - 1)
-    e2 = n * (n - 1) * (1 - 2 / m) ** (n - 2)
-    var = e2 + p1 - p1 * p1
-    return p1, math.sqrt(max(var, 0.0))
+    uniformly into m cells (the textbook occupancy problem): E[X] = n (1-1/m)^(n-1) and
+    E[X(X-1)] = n (n-1) (1-1/m) (1-2/m)^(n-2) (two keys alone: different cells, no other key in
+    either), powers taken through log1p so that large n keeps its precision."""
+    p1 = n * math.exp((n - 1) * math.log1p(-1.0 / m))
+    e2 = (m - 1) / m * n * (n - 1) * math.exp((n - 2) * math.log1p(-2.0 / m)) if n > 1 else 0.0
+    return p1, math.sqrt(max(e2 + p1 - p1 * p1, 0.0))
 
 
 def test_levels_of_kmer_keys_follow_the_occupancy_statistics(M):
