@@ -154,6 +154,29 @@ mphf_status mphf_export_collisions(const mphf_t* h, uint32_t level, uint64_t* ou
 mphf_status mphf_positions(const uint64_t* keys, uint64_t n, uint64_t level_seed, uint64_t m,
                            uint64_t* out, void* stream);
 
+/* ---- Streaming build: key sets generated on the fly, beyond device memory -------------------
+ * The keys are never stored: key i (0 <= i < n) is output start + i of the SplitMix64 stream
+ * seeded with `seed` (Steele, Lea and Flood, OOPSLA 2014): the mix of seed + (start+i+1) *
+ * 0x9E3779B97F4A7C15, so the n keys are distinct (as the generated stream of Section 4.5). */
+typedef struct mphf_key_stream {
+    uint64_t seed;
+    uint64_t start;
+} mphf_key_stream;
+
+/* Build over the n keys of `src`.  While more than resident_keys keys are left, a level re-generates
+ * every key, skips those placed at an earlier level (a lookup walk over the finished levels) and
+ * marks the others with global test-and-set: the re-scan strategy of Section 3.4, which stores no
+ * F_d.  Then the survivors are collected (8 bytes each) and the build continues in memory.  The
+ * function, its levels and labels equal those of mphf_build_ex on the materialized keys.  Device
+ * memory: the structure, 2 gamma n bits for the first level's A and C, and the survivors.
+ * flags must be 0.  Synchronous, like mphf_build_ex. */
+mphf_status mphf_build_stream(const mphf_key_stream* src, uint64_t n, double gamma, uint64_t seed,
+                              const mphf_opts* opts, uint64_t resident_keys, void* stream, mphf_t** out);
+
+/* Keys first .. first+count-1 of the stream into the device array out (queries of a streamed build). */
+mphf_status mphf_stream_keys(const mphf_key_stream* src, uint64_t first, uint64_t count, uint64_t* out,
+                             void* stream);
+
 /* ---- Batched builds: many independent key sets built in one launch ---------------------------
  * Set s holds the device keys keys[offsets[s] .. offsets[s+1]) (offsets: nsets+1 device u64,
  * non-decreasing, offsets[0] = 0).  Every set is an independent function with labels 1..n_s whose

@@ -271,6 +271,65 @@ class Builder {
 
     mphf_status run(const uint64_t* keys, uint64_t n, double gamma) {
         mphf_status st;
+        if ((st = setup(n, gamma)) != MPHF_OK) return st;
+        return levels_and_finish(keys, n, 0, 0);
+    }
+
+    // Streamed levels over a generated key stream while the survivors exceed `budget` keys (no key
+    // is stored), then the survivors are collected and the in-memory levels continue.
+    mphf_status run_stream(uint64_t kseed, uint64_t kstart, uint64_t n, double gamma, uint64_t budget) {
+        mphf_status st;
+        if ((st = setup(n, gamma)) != MPHF_OK) return st;
+        const uint32_t D = o_.max_levels;
+        DevLevel* lev = nullptr;
+        if ((st = ar_.alloc(&lev, MPHF_MAX_LEVELS, "stream levels")) != MPHF_OK) return st;
+        unsigned long long* counters = (unsigned long long*)dev_;
+        HIP_TRY(launch_zero(dev_, 256, s_), "zero counters");
+        uint64_t* W = nullptr;
+        uint32_t d = 0;
+        uint64_t off = 0, nd = n;
+        while (nd > 0 && d < D && nd > budget) {
+            const uint64_t m = level_size(gamma_, nd);
+            const uint64_t wd = (m + 63) / 64;
+            if (!W && (st = ar_.alloc(&W, 2 * wd + 2, "stream W")) != MPHF_OK) return st;
+            const LevelHash L = make_level_hash(seeds_.s[d], m, off);
+            if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
+            HIP_TRY(launch_zero(W, 2 * wd, s_), "zero W");
+            HIP_TRY(launch_stream_fill(kseed, kstart, n, lev, d, words_, W, L, s_), "stream fill");
+            HIP_TRY(launch_finalize(W, wd, words_ + off / 64, coll_ ? coll_ + off / 64 : nullptr, counters + d, s_),
+                    "finalize");
+            if ((st = read_back(counters + d, 8)) != MPHF_OK) return st;
+            const uint64_t weight = host_[0];
+            if (weight > nd) return fail(MPHF_E_DEVICE, "level weight exceeds the level's keys");
+            record(d, nd, m, weight, off);
+            // the level joins the walk of the next scans
+            DevLevel* hl = (DevLevel*)(host_ + 64);
+            *hl = DevLevel{L.seed, L.m, L.magic, L.bit_off, L.sh1, L.sh2};
+            HIP_TRY(hipMemcpyAsync(lev + d, hl, sizeof(DevLevel), hipMemcpyHostToDevice, s_), "copy level");
+            HIP_TRY(hipStreamSynchronize(s_), "level sync");
+            off += 64 * wd;
+            nd -= weight;
+            ++d;
+            tr_.mark("streamed level", (long)(d - 1));
+        }
+        if (W) ar_.release(W);
+        if (!nd) {
+            h_->total_words = h_->total_bits / 64;
+            return finish();
+        }
+        // the survivors of the streamed levels, in any order (the levels do not depend on it)
+        uint64_t* dense = nullptr;
+        if ((st = ar_.alloc(&dense, nd, "streamed survivors")) != MPHF_OK) return st;
+        HIP_TRY(launch_stream_collect(kseed, kstart, n, lev, d, words_, dense, nd, counters + 200, s_), "collect");
+        if ((st = read_back(counters + 200, 8)) != MPHF_OK) return st;
+        if (host_[0] != nd) return fail(MPHF_E_DEVICE, "collected survivors differ from the level counts");
+        tr_.mark("collect", (long)nd);
+        return levels_and_finish(dense, nd, d, off);
+    }
+
+    // Sizes, seeds, counters and the concatenated A reserved for n keys.
+    mphf_status setup(uint64_t n, double gamma) {
+        mphf_status st;
         gamma_ = gamma;
         acquire_workspace();
         level_seeds(h_->seed, o_.max_levels, seeds_.s);
@@ -293,6 +352,13 @@ class Builder {
             if ((st = ensure_words(cap)) != MPHF_OK) return st;
         }
         tr_.mark("setup");
+        return MPHF_OK;
+    }
+
+    // Levels d.. of the n keys at `keys` (the whole set when d = 0), starting at bit `off` of A,
+    // then the fallback table, rank table, lookup layout and level table.
+    mphf_status levels_and_finish(const uint64_t* keys, uint64_t n, uint32_t d, uint64_t off) {
+        mphf_status st;
         const bool atomic_only = o_.flags & MPHF_FLAG_ATOMIC_LEVELS;
         KeySet cur;
         uint64_t* pre0 = nullptr;
@@ -304,10 +370,8 @@ class Builder {
         cur.pre = pre0;
         cur.nseg = 1;
         cur.n = n;
-
-        uint32_t d = 0;
-        uint64_t off = 0;
         const uint32_t D = o_.max_levels;
+        const double gamma = gamma_;
         const uint32_t tk = tail_capacity(gamma);
         const BucketGeometry geo = bucket_geometry(gamma);
         bool fallback = atomic_only || geo.pbits == 0;
@@ -353,6 +417,11 @@ class Builder {
         }
         h_->total_words = h_->total_bits / 64;
         tr_.mark("levels done");
+        return finish();
+    }
+
+    mphf_status finish() {
+        mphf_status st;
         if ((st = fallback_table()) != MPHF_OK) return st;
         tr_.mark("fallback table", (long)nleft_);
         if ((st = rank_table()) != MPHF_OK) return st;
@@ -762,9 +831,56 @@ mphf_status build_impl(const uint64_t* keys, uint64_t n, double gamma, uint64_t 
     return MPHF_OK;
 }
 
+mphf_status build_stream_impl(uint64_t kseed, uint64_t kstart, uint64_t n, double gamma, uint64_t seed,
+                              const mphf_opts& opts, uint64_t budget, hipStream_t s, mphf** out) {
+    if (!(gamma >= 1.0) || !std::isfinite(gamma))
+        return fail(MPHF_E_INVALID, "gamma must be a finite number >= 1");
+    if (gamma * (double)n >= 9.2e18) return fail(MPHF_E_INVALID, "gamma * n too large");
+    mphf_status st = check_opts(opts);
+    if (st != MPHF_OK) return st;
+    mphf* h = new mphf();
+    HIP_TRY(hipGetDevice(&h->device), "hipGetDevice");
+    configure_pool(h->device);
+    h->n = n;
+    h->gamma = gamma;
+    h->seed = seed;
+    h->opts = opts;
+    h->rank_shift = opts.rank_sample == 1024 ? 10 : 9;
+    {
+        Builder b(h, opts, s);
+        st = b.run_stream(kseed, kstart, n, gamma, budget);
+    }
+    if (st != MPHF_OK) {
+        free_handle(h);
+        return st;
+    }
+    *out = h;
+    return MPHF_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+mphf_status mphf_build_stream(const mphf_key_stream* src, uint64_t n, double gamma, uint64_t seed,
+                              const mphf_opts* opts, uint64_t resident_keys, void* stream, mphf_t** out) {
+    if (!out || !src) return fail(MPHF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    mphf_opts o;
+    if (opts) o = *opts;
+    else mphf_default_opts(&o);
+    if (o.flags) return fail(MPHF_E_INVALID, "flags are not supported for streamed builds");
+    return build_stream_impl(src->seed, src->start, n, gamma, seed, o, resident_keys, (hipStream_t)stream, out);
+}
+
+mphf_status mphf_stream_keys(const mphf_key_stream* src, uint64_t first, uint64_t count, uint64_t* out,
+                             void* stream) {
+    if (!src) return fail(MPHF_E_INVALID, "src is NULL");
+    if (!count) return MPHF_OK;
+    if (!out || !is_device_ptr(out)) return fail(MPHF_E_INVALID, "out must be device memory");
+    HIP_TRY(launch_stream_keys(src->seed, src->start + first, count, out, (hipStream_t)stream), "stream keys");
+    return MPHF_OK;
+}
 
 mphf_status mphf_default_opts(mphf_opts* o) {
     if (!o) return fail(MPHF_E_INVALID, "opts is NULL");

@@ -149,6 +149,14 @@ hipError_t launch_rank(const uint64_t* words, uint64_t total_words, uint32_t ran
 uint64_t scan_tmp_tiles(uint64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
                                  hipStream_t s);
+// streaming build (stream.hip)
+hipError_t launch_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
+                              const uint64_t* words, uint64_t* W, const LevelHash& L, hipStream_t s);
+hipError_t launch_stream_collect(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
+                                 const uint64_t* words, uint64_t* out, uint64_t cap, unsigned long long* count,
+                                 hipStream_t s);
+hipError_t launch_stream_keys(uint64_t kseed, uint64_t kstart, uint64_t n, uint64_t* out, hipStream_t s);
+
 // k-mer workload (kmer.hip)
 hipError_t launch_kmers(const uint64_t* seq, uint64_t npos, uint32_t k, uint64_t* out, hipStream_t s);
 hipError_t launch_repeated(const uint64_t* sorted, uint64_t n, uint64_t* out, uint64_t cap,

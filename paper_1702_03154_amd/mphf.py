@@ -55,6 +55,10 @@ class SetInfo(C.Structure):
                 ("total_bits", C.c_uint64)]
 
 
+class KeyStream(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("start", C.c_uint64)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_inflight", C.c_uint32),
                 ("max_batch_requests", C.c_uint32)]
@@ -112,6 +116,9 @@ def lib() -> C.CDLL:
             "mphf_batch_status": (st, [vp, vp]),
             "mphf_batch_export_sectors": (st, [vp, u64, vp, u64]),
             "mphf_last_error": (C.c_char_p, []),
+            "mphf_build_stream": (st, [C.POINTER(KeyStream), u64, C.c_double, u64, C.POINTER(Opts), u64, vp,
+                                       C.POINTER(vp)]),
+            "mphf_stream_keys": (st, [C.POINTER(KeyStream), u64, u64, vp, vp]),
             "mphf_kmers": (st, [vp, u64, u32, vp, vp]),
             "mphf_first_occurrences": (st, [vp, u64, u64, vp, C.POINTER(C.c_uint64), vp]),
             "mphf_partition_sets": (st, [vp, u64, u32, u64, vp, vp, vp]),
@@ -361,6 +368,30 @@ def positions(keys: torch.Tensor, level_seed: int, m: int, stream=None) -> torch
     if keys.numel():
         _check(lib().mphf_positions(_dev(keys, "keys"), keys.numel(), level_seed & (2**64 - 1), m,
                                     _dev(out, "out"), _stream(stream)))
+    return out
+
+
+def build_stream(n: int, key_seed: int, gamma: float = 2.0, seed: int = 0, resident_keys: int = 1 << 31,
+                 start: int = 0, max_levels: int = 25, rank_sample: int = 512, device=None, stream=None) -> "MPHF":
+    """Streaming build over keys generated on the fly (mphf_build_stream): key i is output start+i of
+    the SplitMix64 stream of key_seed; no more than resident_keys survivors are ever stored."""
+    L = lib()
+    o = Opts(max_levels, rank_sample, 0, 0, 0)
+    src = KeyStream(key_seed & (2**64 - 1), start)
+    h = C.c_void_p()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        _check(L.mphf_build_stream(C.byref(src), n, float(gamma), seed & (2**64 - 1), C.byref(o), resident_keys,
+                                   _stream(stream), C.byref(h)))
+    return MPHF(h.value, dev)
+
+
+def stream_keys(key_seed: int, first: int, count: int, start: int = 0, device="cuda", stream=None) -> torch.Tensor:
+    """Keys first .. first+count-1 of a streamed key set (mphf_stream_keys)."""
+    out = torch.empty(count, dtype=torch.int64, device=device)
+    src = KeyStream(key_seed & (2**64 - 1), start)
+    if count:
+        _check(lib().mphf_stream_keys(C.byref(src), first, count, _dev(out, "out"), _stream(stream)))
     return out
 
 

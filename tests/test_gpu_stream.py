@@ -1,0 +1,81 @@
+"""GPU parity of the streaming build (keys generated on the fly, re-scanned at every streamed
+level, Section 3.4's second strategy): the function must equal the oracle's on the materialized
+keys bit for bit, whatever the number of streamed levels."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mphf_oracle as O
+from paper_1702_03154_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_03154_amd import mphf
+    mphf.lib()
+    return mphf
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def check(M, n, gamma, resident, key_seed=1, start=0, max_levels=25, rank_sample=512):
+    h = M.build_stream(n, key_seed, gamma, 0, resident_keys=resident, start=start, max_levels=max_levels,
+                       rank_sample=rank_sample)
+    keys = I.splitmix64(key_seed, n, start=start).numpy().view(np.uint64)
+    st = O.build(keys, gamma, 0, max_levels=max_levels, rank_sample=rank_sample)
+    s = h.stats()
+    assert s["num_levels"] == st.num_levels
+    assert s["level_n"] == [l.n for l in st.levels]
+    assert s["level_m"] == [l.m for l in st.levels]
+    assert s["level_weight"] == [l.weight for l in st.levels]
+    assert s["level_offset"] == [l.offset for l in st.levels]
+    ex = h.export()
+    assert np.array_equal(ex["words"], st.words)
+    assert np.array_equal(ex["rank"], st.rank)
+    assert np.array_equal(ex["fallback_keys"], st.fallback_keys)
+    if n:
+        q = torch.from_numpy(keys.view(np.int64)).cuda()
+        assert np.array_equal(host(h.lookup(q)), O.lookup(st, keys))
+    h.close()
+
+
+@pytest.mark.parametrize("resident", [0, 1000, 50_000, 10 ** 9])
+@pytest.mark.parametrize("n", [0, 1, 7, 1000, 300_000])
+def test_streamed_build_equals_the_oracle(M, n, resident):
+    check(M, n, 2.0, resident)
+
+
+@pytest.mark.parametrize("gamma", [1.0, 3.0])
+def test_streamed_build_other_gammas(M, gamma):
+    check(M, 200_000, gamma, 5000)
+
+
+def test_streamed_levels_with_a_fallback_table(M):
+    # three levels, all streamed: the leftovers are collected from the stream for the fallback table
+    check(M, 100_000, 2.0, 0, max_levels=3)
+    check(M, 100_000, 1.0, 10, max_levels=2, rank_sample=1024)
+
+
+def test_stream_offset_and_keys(M):
+    check(M, 50_000, 2.0, 100, key_seed=9, start=123_456)
+    got = M.stream_keys(9, 10, 1000, start=5)
+    assert torch.equal(got.cpu(), I.splitmix64(9, 1000, start=15))
+
+
+def test_streamed_build_large(M):
+    """2e7 keys, two levels streamed (resident budget below |F_1|), then in memory: labels are a
+    bijection onto [1, n] and the level sizes equal those of a build from the stored keys."""
+    n = 20_000_000
+    h = M.build_stream(n, 3, 2.0, 0, resident_keys=5_000_000)
+    keys = M.stream_keys(3, 0, n)
+    ref = M.build(keys, 2.0, 0)
+    assert h.stats()["level_n"] == ref.stats()["level_n"]
+    lab = h.lookup(keys)
+    assert torch.equal(lab, ref.lookup(keys))
+    assert torch.equal(torch.sort(lab).values, torch.arange(1, n + 1, device=lab.device))
