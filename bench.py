@@ -14,6 +14,10 @@ DNA sequence (32 GB of keys in HBM); plain build + lookup and the batched path
 over 2^15 hash sets, with per-level sizes checked against the occupancy
 statistics.
 
+--workload stream: the streaming build over 1e10 keys generated on the fly (never
+stored), levels re-scanning the stream while more than 2^31 keys survive; then the
+lookup of every key, regenerated chunk by chunk.
+
 --workload serve: 64 resident functions (log-uniform sizes in [1e6, 1e9]) answer
 Poisson-arriving lookup requests from host memory through the serving loop;
 throughput at saturation and p50/p99 latency at 0.5/0.8/0.95 of the plain
@@ -470,9 +474,80 @@ def bench_kmer(args):
     print(json.dumps(res))
 
 
+def bench_stream(args):
+    """Streaming build over n generated keys (never stored), then the lookup of every key,
+    regenerated chunk by chunk; bijection checked with one byte per label."""
+    import statistics
+
+    import torch
+
+    from paper_1702_03154_amd import mphf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = int(args.n)
+    resident = int(args.resident_keys)
+    s = torch.cuda.current_stream()
+    build_ms = []
+    h = None
+    for it in range(args.warmup + args.steps):
+        if h is not None:
+            h.close()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        h = mphf.build_stream(n, 1, args.gamma, 0, resident_keys=resident)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            build_ms.append(e0.elapsed_time(e1))
+        print(f"# stream build {it}: {e0.elapsed_time(e1):.1f} ms", file=sys.stderr, flush=True)
+    st = h.stats()
+    chunk = 1 << 28
+    seen = torch.zeros(n, dtype=torch.int8, device=dev)
+    q = torch.empty(min(chunk, n), dtype=torch.int64, device=dev)
+    lab = torch.empty_like(q)
+    lookup_ms, in_range = 0.0, True
+    for c0 in range(0, n, chunk):
+        c = min(chunk, n - c0)
+        q[:c] = mphf.stream_keys(1, c0, c)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        h.lookup(q[:c], out=lab[:c])
+        e1.record(s)
+        torch.cuda.synchronize()
+        lookup_ms += e0.elapsed_time(e1)
+        v = lab[:c]
+        in_range = in_range and bool(((v >= 1) & (v <= n)).all())
+        seen[(v - 1).clamp(0, n - 1)] = 1
+    ok = in_range and bool(seen.all())
+    del seen
+    streamed = sum(1 for x in st["level_n"][:st["num_levels"]] if x > resident)
+    tb = statistics.median(build_ms)
+    res = {
+        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "value": n / ((tb + lookup_ms) / 1e3), "unit": "keys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb + lookup_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"streaming build over {n} SplitMix64 keys (seed 1) generated on the fly, "
+                               f"re-scanned while more than {resident} survive, gamma={args.gamma}; "
+                               f"lookup of every key regenerated in chunks",
+                   "n": n, "gamma": args.gamma, "resident_keys": resident},
+        "build_keys_per_s": n / (tb / 1e3), "lookup_queries_per_s": n / (lookup_ms / 1e3),
+        "build_ms": tb, "lookup_ms": lookup_ms, "labels_bijective": ok,
+        "levels": st["num_levels"], "streamed_levels": streamed, "bits_per_key": st["bits_per_key"],
+        "n_fallback": st["n_fallback"], "structure_bytes": st["structure_bytes"],
+        "level_n": st["level_n"][:st["num_levels"]],
+    }
+    h.close()
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer", "stream"], default="plain")
+    ap.add_argument("--resident-keys", type=float, default=2 ** 31, help="stream: survivors kept in memory")
     ap.add_argument("--kmer-bases", type=float, default=4.2e9, help="kmer: sequence length")
     ap.add_argument("--kmer-keys", type=float, default=4e9, help="kmer: distinct k-mers kept")
     ap.add_argument("--kmer-set-bits", type=float, default=15, help="kmer: log2 of the batched sets")
@@ -508,6 +583,11 @@ def main():
         return
     if args.workload == "kmer":
         bench_kmer(args)
+        return
+    if args.workload == "stream":
+        if args.n == 1e9:
+            args.n = 1e10
+        bench_stream(args)
         return
 
     import torch

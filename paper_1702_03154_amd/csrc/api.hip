@@ -320,6 +320,7 @@ class Builder {
         // the survivors of the streamed levels, in any order (the levels do not depend on it)
         uint64_t* dense = nullptr;
         if ((st = ar_.alloc(&dense, nd, "streamed survivors")) != MPHF_OK) return st;
+        tr_.mark("collect alloc", (long)nd);
         HIP_TRY(launch_stream_collect(kseed, kstart, n, lev, d, words_, dense, nd, counters + 200, s_), "collect");
         if ((st = read_back(counters + 200, 8)) != MPHF_OK) return st;
         if (host_[0] != nd) return fail(MPHF_E_DEVICE, "collected survivors differ from the level counts");

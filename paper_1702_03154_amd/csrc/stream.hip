@@ -43,27 +43,65 @@ __device__ __forceinline__ void mark_pos(unsigned long long* W, uint64_t p) {
     if (old & b) atomicOr(w, b << 32);
 }
 
+constexpr int ZI = 8;   // keys per thread per iteration: independent walks in flight
+
 __global__ void __launch_bounds__(ZT)
 k_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __restrict__ lev, uint32_t d,
               const uint64_t* __restrict__ words, unsigned long long* W, LevelHash L) {
-    const uint64_t stride = (uint64_t)gridDim.x * ZT;
-    for (uint64_t i = (uint64_t)blockIdx.x * ZT + threadIdx.x; i < n; i += stride) {
-        const uint64_t x = stream_key(kseed, kstart + i);
-        if (!placed_before(x, lev, d, words)) mark_pos(W, level_pos(x, L));
+    const uint64_t stride = (uint64_t)gridDim.x * ZT * ZI;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * ZT * ZI; i0 < n; i0 += stride) {
+        uint64_t x[ZI];
+        bool live[ZI];
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const uint64_t i = i0 + (uint64_t)it * ZT + threadIdx.x;
+            live[it] = i < n;
+            x[it] = live[it] ? stream_key(kseed, kstart + i) : 0;
+        }
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) live[it] = live[it] && !placed_before(x[it], lev, d, words);
+#pragma unroll
+        for (int it = 0; it < ZI; ++it)
+            if (live[it]) mark_pos(W, level_pos(x[it], L));
     }
 }
 
+// Survivors appended with one counter update per block and iteration (ZT * ZI keys): a single
+// counter updated by every wave would serialize on one address.  Order inside a block's chunk is
+// thread-major; the build does not depend on the order of F_d.
 __global__ void __launch_bounds__(ZT)
 k_stream_collect(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __restrict__ lev, uint32_t d,
                  const uint64_t* __restrict__ words, uint64_t* __restrict__ out, uint64_t cap,
                  unsigned long long* count) {
-    const uint64_t stride = (uint64_t)gridDim.x * ZT;
-    for (uint64_t i = (uint64_t)blockIdx.x * ZT + threadIdx.x; i < n; i += stride) {
-        const uint64_t x = stream_key(kseed, kstart + i);
-        if (!placed_before(x, lev, d, words)) {
-            const unsigned long long j = atomicAdd(count, 1ull);
-            if (j < cap) out[j] = x;
+    __shared__ uint32_t wsum[ZT / 64 + 1];
+    __shared__ unsigned long long s_base;
+    const uint64_t stride = (uint64_t)gridDim.x * ZT * ZI;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * ZT * ZI; i0 < n; i0 += stride) {
+        uint64_t x[ZI];
+        uint32_t keep = 0;
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const uint64_t i = i0 + (uint64_t)it * ZT + threadIdx.x;
+            x[it] = i < n ? stream_key(kseed, kstart + i) : 0;
         }
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            const uint64_t i = i0 + (uint64_t)it * ZT + threadIdx.x;
+            if (i < n && !placed_before(x[it], lev, d, words)) keep |= 1u << it;
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum<ZT>((uint32_t)__popc(keep), wsum, &tot);
+        if (threadIdx.x == 0) s_base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+        __syncthreads();
+        uint64_t j = s_base + ex;
+#pragma unroll
+        for (int it = 0; it < ZI; ++it) {
+            if ((keep >> it) & 1u) {
+                if (j < cap) out[j] = x[it];
+                ++j;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -74,7 +112,7 @@ k_stream_keys(uint64_t kseed, uint64_t kstart, uint64_t n, uint64_t* __restrict_
 }
 
 unsigned zgrid(uint64_t n) {
-    uint64_t g = (n + 4 * ZT - 1) / (4 * ZT);
+    uint64_t g = (n + (uint64_t)ZI * ZT - 1) / ((uint64_t)ZI * ZT);
     if (g < 1) g = 1;
     if (g > 32768) g = 32768;
     return (unsigned)g;
