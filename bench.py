@@ -18,6 +18,9 @@ statistics.
 stored), levels re-scanning the stream while more than 2^31 keys survive; then the
 lookup of every key, regenerated chunk by chunk.
 
+--workload gamma: the plain build + lookup for gamma in 1..10 and with 1024-bit rank
+sampling, beside the space analysis (bits/key, probes per query).
+
 --workload serve: 64 resident functions (log-uniform sizes in [1e6, 1e9]) answer
 Poisson-arriving lookup requests from host memory through the serving loop;
 throughput at saturation and p50/p99 latency at 0.5/0.8/0.95 of the plain
@@ -544,9 +547,69 @@ def bench_stream(args):
     print(json.dumps(res))
 
 
+def bench_gamma(args):
+    """The influence of gamma (build time, query time, bits/key, probes per query) and the 1024-bit
+    rank sampling ('minirank'), each beside the space analysis."""
+    import math
+    import statistics
+
+    import torch
+
+    from paper_1702_03154_amd import inputs, mphf
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = int(args.n)
+    keys = inputs.keys(n, seed=1, device=dev)
+    queries = inputs.shuffled_queries(keys, seed=2)
+    out = torch.empty_like(keys)
+    s = torch.cuda.current_stream()
+    rows = []
+    runs = [(g, 512) for g in (1.0, 1.5, 2.0, 3.0, 5.0, 7.0, 10.0)] + [(1.0, 1024), (2.0, 1024)]
+    for gamma, rs in runs:
+        bms, lms = [], []
+        st = None
+        for it in range(args.warmup + args.steps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            torch.cuda.synchronize()
+            e0.record(s)
+            h = mphf.build(keys, gamma, 0, rank_sample=rs)
+            e1.record(s)
+            h.lookup(queries, out=out)
+            e2.record(s)
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                bms.append(e0.elapsed_time(e1))
+                lms.append(e1.elapsed_time(e2))
+            st = h.stats()
+            h.close()
+        tb, tl = statistics.median(bms), statistics.median(lms)
+        row = {"gamma": gamma, "rank_sample": rs, "build_keys_per_s": n / (tb / 1e3),
+               "lookup_queries_per_s": n / (tl / 1e3), "build_ms": tb, "lookup_ms": tl,
+               "bits_per_key": st["bits_per_key"],
+               "bits_per_key_analysis": (1 + 64 / rs) * gamma * math.exp(1 / gamma),
+               "mean_probes": mean_probes(st), "mean_probes_analysis": math.exp(1 / gamma),
+               "levels": st["num_levels"], "n_fallback": st["n_fallback"]}
+        rows.append(row)
+        print(f"# gamma {gamma} rank {rs}: build {tb:.1f} ms lookup {tl:.1f} ms, {row['bits_per_key']:.3f} bits/key",
+              file=sys.stderr, flush=True)
+    base = next(r for r in rows if r["gamma"] == 2.0 and r["rank_sample"] == 512)
+    res = {
+        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "value": n / ((base["build_ms"] + base["lookup_ms"]) / 1e3), "unit": "keys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": base["build_ms"] + base["lookup_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"gamma sweep: plain build + shuffled lookup of N={n} SplitMix64 keys (seed 1) "
+                               f"for gamma in 1..10 and 1024-bit rank sampling", "n": n},
+        "rows": rows,
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer", "stream"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer", "stream", "gamma"], default="plain")
     ap.add_argument("--resident-keys", type=float, default=2 ** 31, help="stream: survivors kept in memory")
     ap.add_argument("--kmer-bases", type=float, default=4.2e9, help="kmer: sequence length")
     ap.add_argument("--kmer-keys", type=float, default=4e9, help="kmer: distinct k-mers kept")
@@ -583,6 +646,9 @@ def main():
         return
     if args.workload == "kmer":
         bench_kmer(args)
+        return
+    if args.workload == "gamma":
+        bench_gamma(args)
         return
     if args.workload == "stream":
         if args.n == 1e9:

@@ -96,15 +96,17 @@ constexpr uint64_t SEC_BITS = 480;
 constexpr uint32_t SEC_WORDS = 16;
 constexpr uint32_t SUPER_SHIFT = 21;
 
-// If bit r (< 480) of sector j is set: *count = the sector's counter plus the ones of the sector
-// before bit r, and true.
-__device__ __forceinline__ bool sector_probe(const uint32_t* __restrict__ sec, uint64_t j, uint32_t r,
-                                             uint32_t* count) {
-    const uint32_t t = 1 + (r >> 5), b = r & 31u;   // the bit's u32 word in the sector
+// The 64 bytes of sector j (four 16-byte loads).
+__device__ __forceinline__ void sector_load(const uint32_t* __restrict__ sec, uint64_t j, uint4 v[4]) {
     const uint4* s4 = (const uint4*)(sec + j * SEC_WORDS);
-    uint4 v[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = s4[c];
+}
+
+// If bit r (< 480) of the loaded sector is set: *count = the sector's counter plus the ones of the
+// sector before bit r, and true.
+__device__ __forceinline__ bool sector_count(const uint4 v[4], uint32_t r, uint32_t* count) {
+    const uint32_t t = 1 + (r >> 5), b = r & 31u;   // the bit's u32 word in the sector
     const uint32_t e[16] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
                             v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
     uint32_t w = 0;
@@ -124,14 +126,31 @@ __device__ __forceinline__ bool sector_probe(const uint32_t* __restrict__ sec, u
     return true;
 }
 
+// The empty asm statements below consume loaded values before the bit test, so that the compiler
+// issues every load of a probe together instead of sinking the counter word and the superblock
+// load behind the test (a second round trip on every hit).  They contain no instruction.
+
+// If bit r (< 480) of sector j is set: *count = the sector's counter plus the ones before bit r.
+__device__ __forceinline__ bool sector_probe(const uint32_t* __restrict__ sec, uint64_t j, uint32_t r,
+                                             uint32_t* count) {
+    uint4 v[4];
+    sector_load(sec, j, v);
+    asm volatile("" ::"v"(v[0].x));
+    return sector_count(v, r, count);
+}
+
 // If bit g of A is set: *rank = the ones of A before g, and true.
 __device__ __forceinline__ bool sector_rank(const uint32_t* __restrict__ sec,
                                             const uint64_t* __restrict__ super, uint64_t g,
                                             uint64_t* rank) {
     const uint64_t j = g / SEC_BITS;
+    const uint64_t base = super[j >> SUPER_SHIFT];
+    uint4 v[4];
+    sector_load(sec, j, v);
+    asm volatile("" ::"v"(v[0].x), "v"(base));
     uint32_t c;
-    if (!sector_probe(sec, j, (uint32_t)(g - j * SEC_BITS), &c)) return false;
-    *rank = super[j >> SUPER_SHIFT] + c;
+    if (!sector_count(v, (uint32_t)(g - j * SEC_BITS), &c)) return false;
+    *rank = base + c;
     return true;
 }
 
