@@ -358,3 +358,31 @@ def test_batch_set_outgrowing_its_expected_region(M):
         if s == 1:
             assert st.levels[1].n == n   # nothing placed at level 0
             assert st.total_bits > 1.5 * math.exp(0.5) * m0 + 64 * 25
+
+
+def test_batch_full_config_65536_sets(M):
+    """The benchmark's batch at full size (65,536 sets, log-uniform in [16, 65536], about 5.1e8
+    keys): every set's labels are a bijection onto [1, n_s], and sampled sets, the largest among
+    them, equal the oracle."""
+    sizes = I.log_uniform_sizes(65536, 16, 65536, seed=3)
+    off = I.set_offsets(sizes)
+    keys = I.set_keys(sizes, seed=4, device="cuda")
+    offc = off.cuda()
+    b = M.build_batch(keys, offc, 2.0, 0)
+    ids = torch.repeat_interleave(torch.arange(65536, device="cuda"), sizes.cuda())
+    lab = b.lookup(ids, keys)
+    g = offc[ids] + lab - 1
+    assert bool((lab >= 1).all()) and bool((g < offc[ids + 1]).all())
+    seen = torch.zeros(keys.numel(), dtype=torch.int8, device="cuda")
+    seen[g] = 1
+    assert bool(seen.all())
+    big = int(torch.argmax(sizes))
+    for s in sorted({0, 1, 777, 4095, 32768, 65535, big}):
+        a, c = int(off[s]), int(off[s + 1])
+        ks = keys[a:c].cpu().numpy().view(np.uint64)
+        st = O.build(ks, 2.0, 0)
+        assert np.array_equal(b.export_set(s)["words"], st.words), s
+        assert np.array_equal(host(lab[a:c]), O.lookup(st, ks)), s
+    t = b.totals()
+    assert t["nsets"] == 65536 and t["nkeys"] == keys.numel()
+    assert abs(t["bits_per_key"] - 3.6) < 0.1
