@@ -252,8 +252,10 @@ void mphf_batch_destroy(mphf_batch_t* b);
  * A server keeps registered functions resident and answers lookup requests from host memory.
  * Requests wait in arrival order and are admitted while their device memory (16 bytes per key:
  * the key in, the label out) fits the server's HBM budget; every admitted group of requests is one
- * batch: its keys are copied in, one segmented lookup kernel labels all of them (each request
- * against its own function, Algorithm 3), and the labels are copied out.  Up to max_inflight
+ * batch: one segmented lookup kernel labels all of them (each request against its own function,
+ * Algorithm 3).  Arrays in pinned host memory (mphf_host_alloc) are read and written by that kernel
+ * in place over PCIe; other arrays are copied into the batch's device buffers and back.  The budget
+ * counts 16 bytes per key for every request alike.  Up to max_inflight
  * batches are on the device at once on their own streams, so requests arriving while a batch runs
  * form the next one and its copies overlap the running kernels (continuous batching).  A request's
  * labels are exactly those of mphf_lookup on its function, alone or in any mix.
@@ -292,7 +294,7 @@ mphf_status mphf_server_register(mphf_server_t* s, const mphf_t* h, uint32_t* id
 
 /* Queue a request: label keys[0..n) (host memory) against function `id` into out[0..n) (host
  * memory).  Both arrays must stay valid until the request is done; pinned memory from
- * mphf_host_alloc copies fastest.  *ticket identifies the request.  MPHF_E_INVALID for an unknown
+ * mphf_host_alloc is used in place (no copies).  *ticket identifies the request.  MPHF_E_INVALID for an unknown
  * id or a request larger than one batch's share of the budget. */
 mphf_status mphf_server_submit(mphf_server_t* s, uint32_t id, const uint64_t* keys, uint64_t n,
                                uint64_t* out, uint64_t* ticket);

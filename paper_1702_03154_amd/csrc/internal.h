@@ -20,8 +20,8 @@ struct DevLevel {
 
 LevelHash make_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off);
 
-// One request of a served batch: the function it queries (device pointers owned by the handle,
-// as the single lookup kernel takes them).  Its queries are q[seg_off[r] .. seg_off[r + 1]).
+// The function a served request queries (device pointers owned by the handle, as the single
+// lookup kernel takes them).
 struct SegDesc {
     const DevLevel* lev;
     const uint32_t* sec;
@@ -184,8 +184,6 @@ uint64_t sector_count(uint64_t total_bits);
 uint64_t super_count(uint64_t nsec);
 hipError_t launch_sectors(const uint64_t* words, uint64_t total_bits, uint32_t* sec, uint64_t* super,
                           uint32_t* tmp_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s);
-hipError_t launch_lookup_segments(const uint64_t* q, uint64_t n, uint64_t* out, const SegDesc* segs,
-                                  const uint64_t* seg_off, uint32_t nseg, hipStream_t s);
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
                          uint32_t nlev, const uint32_t* sec, const uint64_t* super,
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);

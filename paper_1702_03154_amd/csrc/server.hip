@@ -3,9 +3,9 @@
 //
 // Requests wait in arrival order.  A dispatcher thread takes a free in-flight slot (its own stream,
 // device memory and pinned staging), admits requests from the head of the queue while their keys
-// and labels fit the slot, and enqueues the batch: each request's keys are copied in, one
-// segmented lookup kernel labels every query against its own function (Algorithm 3), and the
-// labels are copied out to each request's array.  A completer thread waits for the batches in
+// and labels fit the slot, and enqueues the batch: one segmented lookup kernel labels every query
+// against its own function (Algorithm 3).  Requests in pinned host memory are read and written by
+// that kernel in place over PCIe; the others are copied into the slot's buffers and back.  A completer thread waits for the batches in
 // launch order and releases their requests and slots.  With several slots, a batch formed while
 // another runs overlaps it on the device; requests arriving in the meantime form the next batch.
 #include <chrono>
@@ -25,10 +25,19 @@ namespace {
 
 constexpr int ST = 256;
 
-// Labels q[0..n) where query i belongs to request r with seg_off[r] <= i < seg_off[r + 1].
+// One request of a batch: its function and where its queries and labels are (the slot's device
+// buffers, or the caller's pinned host arrays read and written directly over PCIe).
+struct ReqDesc {
+    SegDesc f;
+    const uint64_t* q;
+    uint64_t* out;
+};
+
+// Query i of the batch belongs to request r with seg_off[r] <= i < seg_off[r + 1]; it is the
+// request's query i - seg_off[r].
 __global__ void __launch_bounds__(ST)
-k_lookup_segments(const uint64_t* __restrict__ q, uint64_t n, uint64_t* __restrict__ out,
-                  const SegDesc* __restrict__ segs, const uint64_t* __restrict__ seg_off, uint32_t nseg) {
+k_lookup_segments(uint64_t n, const ReqDesc* __restrict__ segs, const uint64_t* __restrict__ seg_off,
+                  uint32_t nseg) {
     const uint64_t stride = (uint64_t)gridDim.x * ST;
     uint32_t cur = 0;
     uint64_t end = 0;   // the request of the previous query covers [.., end)
@@ -42,9 +51,38 @@ k_lookup_segments(const uint64_t* __restrict__ q, uint64_t n, uint64_t* __restri
             cur = lo;
             end = seg_off[lo + 1];
         }
-        const SegDesc d = segs[cur];
-        out[i] = label_of(q[i], d.lev, d.nlev, d.sec, d.super, d.fbk, d.nfb, d.N);
+        const ReqDesc d = segs[cur];
+        const uint64_t j = i - seg_off[cur];
+        d.out[j] = label_of(d.q[j], d.f.lev, d.f.nlev, d.f.sec, d.f.super, d.f.fbk, d.f.nfb, d.f.N);
     }
+}
+
+hipError_t launch_lookup_segments(uint64_t n, const ReqDesc* segs, const uint64_t* seg_off, uint32_t nseg,
+                                  hipStream_t s) {
+    if (!n || !nseg) return hipSuccess;
+    uint64_t blocks = (n + 4 * ST - 1) / (4 * ST);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_lookup_segments, dim3((unsigned)blocks), dim3(ST), 0, s, n, segs, seg_off, nseg);
+    return hipGetLastError();
+}
+
+// The device-visible alias of a pinned host range [p, p + bytes), or null for other memory.
+const void* pinned_alias(const void* p, uint64_t bytes) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+    hipPointerAttribute_t b;
+    const void* last = (const char*)p + bytes - 1;
+    if (hipPointerGetAttributes(&b, last) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (b.type != hipMemoryTypeHost || (const char*)b.devicePointer - (const char*)a.devicePointer != (ptrdiff_t)(bytes - 1))
+        return nullptr;
+    return a.devicePointer;
 }
 
 struct Request {
@@ -53,6 +91,8 @@ struct Request {
     const uint64_t* keys = nullptr;
     uint64_t n = 0;
     uint64_t* out = nullptr;
+    const uint64_t* dkeys = nullptr;   // device aliases of pinned request arrays (else staged)
+    uint64_t* dout = nullptr;
     bool done = false;
     mphf_status status = MPHF_OK;
     uint64_t batch = 0;
@@ -104,20 +144,27 @@ struct mphf_server {
 namespace {
 
 // The batch's request offsets and descriptors in the slot's pinned staging (under the server lock:
-// the function table may grow meanwhile).
+// the function table may grow meanwhile).  A pinned request is read and written in place; any
+// other request goes through the slot's device buffers at its offset.
 void stage_batch(mphf_server* s, Slot& sl) {
     uint64_t* hoff = (uint64_t*)sl.host;
-    SegDesc* hdesc = (SegDesc*)(sl.host + align256(8 * (s->opts.max_batch_requests + 1)));
+    ReqDesc* hdesc = (ReqDesc*)(sl.host + align256(8 * (s->opts.max_batch_requests + 1)));
+    uint64_t* dkeys = (uint64_t*)sl.dev;
+    uint64_t* dlab = (uint64_t*)(sl.dev + align256(8 * s->slot_keys));
     uint64_t acc = 0;
     for (size_t r = 0; r < sl.reqs.size(); ++r) {
+        const Request* q = sl.reqs[r];
         hoff[r] = acc;
-        hdesc[r] = s->fns[sl.reqs[r]->fn];
-        acc += sl.reqs[r]->n;
+        hdesc[r].f = s->fns[q->fn];
+        hdesc[r].q = q->dkeys ? q->dkeys : dkeys + acc;
+        hdesc[r].out = q->dout ? q->dout : dlab + acc;
+        acc += q->n;
     }
     hoff[sl.reqs.size()] = acc;
 }
 
-// Copies in, one segmented lookup, copies out, completion event: all on the slot's stream.
+// Copies in (staged requests), one segmented lookup, copies out, completion event: all on the
+// slot's stream.
 hipError_t launch_batch(mphf_server* s, Slot& sl) {
     const uint32_t R = (uint32_t)sl.reqs.size();
     const uint64_t K = sl.keys;
@@ -127,15 +174,17 @@ hipError_t launch_batch(mphf_server* s, Slot& sl) {
     const uint64_t* hoff = (const uint64_t*)sl.host;
     hipError_t e;
     for (uint32_t r = 0; r < R; ++r)
-        if ((e = hipMemcpyAsync(dkeys + hoff[r], sl.reqs[r]->keys, 8 * sl.reqs[r]->n, hipMemcpyHostToDevice,
+        if (!sl.reqs[r]->dkeys &&
+            (e = hipMemcpyAsync(dkeys + hoff[r], sl.reqs[r]->keys, 8 * sl.reqs[r]->n, hipMemcpyHostToDevice,
                                 sl.stream)) != hipSuccess)
             return e;
     if ((e = hipMemcpyAsync(dmeta, sl.host, s->meta_bytes, hipMemcpyHostToDevice, sl.stream)) != hipSuccess) return e;
     const uint64_t* doff = (const uint64_t*)dmeta;
-    const SegDesc* ddesc = (const SegDesc*)(dmeta + align256(8 * (s->opts.max_batch_requests + 1)));
-    if ((e = launch_lookup_segments(dkeys, K, dlab, ddesc, doff, R, sl.stream)) != hipSuccess) return e;
+    const ReqDesc* ddesc = (const ReqDesc*)(dmeta + align256(8 * (s->opts.max_batch_requests + 1)));
+    if ((e = launch_lookup_segments(K, ddesc, doff, R, sl.stream)) != hipSuccess) return e;
     for (uint32_t r = 0; r < R; ++r)
-        if ((e = hipMemcpyAsync(sl.reqs[r]->out, dlab + hoff[r], 8 * sl.reqs[r]->n, hipMemcpyDeviceToHost,
+        if (!sl.reqs[r]->dout &&
+            (e = hipMemcpyAsync(sl.reqs[r]->out, dlab + hoff[r], 8 * sl.reqs[r]->n, hipMemcpyDeviceToHost,
                                 sl.stream)) != hipSuccess)
             return e;
     return hipEventRecord(sl.done, sl.stream);
@@ -227,18 +276,6 @@ void free_server(mphf_server* s) {
 
 }  // namespace
 
-namespace mphfk {
-
-hipError_t launch_lookup_segments(const uint64_t* q, uint64_t n, uint64_t* out, const SegDesc* segs,
-                                  const uint64_t* seg_off, uint32_t nseg, hipStream_t s) {
-    if (!n || !nseg) return hipSuccess;
-    uint64_t blocks = (n + 4 * ST - 1) / (4 * ST);
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_lookup_segments, dim3((unsigned)blocks), dim3(ST), 0, s, q, n, out, segs, seg_off, nseg);
-    return hipGetLastError();
-}
-
-}  // namespace mphfk
 
 extern "C" {
 
@@ -266,7 +303,7 @@ mphf_status mphf_server_create(const mphf_server_opts* opts, mphf_server_t** out
         delete s;
         return mphf_api::hip_error(e, "hipGetDevice");
     }
-    s->meta_bytes = align256(8 * (o.max_batch_requests + 1)) + align256(sizeof(SegDesc) * o.max_batch_requests);
+    s->meta_bytes = align256(8 * (o.max_batch_requests + 1)) + align256(sizeof(ReqDesc) * o.max_batch_requests);
     s->slot_bytes = o.hbm_budget / o.max_inflight;
     if (s->slot_bytes < s->meta_bytes + 4096) {
         delete s;
@@ -320,6 +357,10 @@ mphf_status mphf_server_submit(mphf_server_t* s, uint32_t id, const uint64_t* ke
     r->keys = keys;
     r->n = n;
     r->out = out;
+    if (n) {   // pinned arrays are read and written by the lookup kernel directly
+        r->dkeys = (const uint64_t*)pinned_alias(keys, 8 * n);
+        r->dout = (uint64_t*)pinned_alias(out, 8 * n);
+    }
     r->t_submit = s->now_us();
     s->reqs[r->ticket] = r;
     if (n == 0) {   // nothing to copy or label: done at once

@@ -177,3 +177,29 @@ def test_server_rejects_bad_requests(M, fns):
     with pytest.raises(M.MphfError):
         M.Server(hbm_budget=1000)
     s.close()
+
+
+def test_pinned_and_pageable_requests_in_one_batch(M, fns):
+    """Pinned arrays are labelled in place over PCIe, pageable ones through the batch's device
+    buffers; both kinds share batches and give the plain labels."""
+    s = M.Server(hbm_budget=128 << 20, max_inflight=2)
+    ids = [s.register(h) for h, _ in fns]
+    reqs = make_requests(fns, 80, seed=7)
+    pinned, outs, tickets = [], [], []
+    for i, (f, q) in enumerate(reqs):
+        if i % 2:
+            pq, po = M.HostArray(len(q)), M.HostArray(len(q))
+            pq.a[:] = q
+            pinned += [pq, po]
+            qa, oa = pq.a, po.a
+        else:
+            qa, oa = q, np.zeros(len(q), dtype=np.uint64)
+        outs.append(oa)
+        tickets.append(s.submit(ids[f], qa, oa))
+    infos = [s.poll(t, wait=True) for t in tickets]
+    assert max(x["batch_requests"] for x in infos) > 1
+    for (f, q), o in zip(reqs, outs):
+        assert np.array_equal(o, plain_labels(M, fns, f, q))
+    for p in pinned:
+        p.close()
+    s.close()
