@@ -252,8 +252,35 @@ struct KeySet {
     uint64_t n = 0;
 };
 
-// Capacity of a region expected to receive e keys: 8 standard deviations and a margin above e.
-uint64_t region_cap(double e) { return (uint64_t)std::ceil(e + 8.0 * std::sqrt(e) + 64.0); }
+// Capacity of a region expected to receive e keys: 8 standard deviations and a margin above e,
+// rounded up to whole 16-key (128-byte) lines, so that every region starts on a line.
+uint64_t region_cap(double e) { return ((uint64_t)std::ceil(e + 8.0 * std::sqrt(e) + 64.0) + 15) & ~15ull; }
+
+// The first 128-byte boundary at or after p (a buffer allocated 16 words longer).
+uint64_t* line_align(uint64_t* p) { return (uint64_t*)(((uintptr_t)p + 127) & ~(uintptr_t)127); }
+
+// Workgroups of a partition pass: two fit on a compute unit (LDS), 256 compute units.
+constexpr uint64_t PART_WGS = 512;
+
+// Workgroups per coarse bin in the second partition pass over n keys (the bucket pass then reads
+// that many regions per bucket).  The C * K workgroups run in ceil(C * K / PART_WGS) rounds, each
+// doing 1 / (C * K) of the keys, so K minimizes rounds / (C * K): C = 188 gives K = 8 (1504
+// workgroups in 3 rounds) rather than K = 2 (376 workgroups, a quarter of the slots idle).  A
+// workgroup keeps at least 16 tiles of work while there are more workgroups than slots.
+uint64_t slots_per_group(uint64_t C, uint64_t n) {
+    const uint64_t cap = std::max<uint64_t>(PART_WGS, n / 65536) / C;
+    const uint64_t kmax = std::max<uint64_t>(1, std::min<uint64_t>(16, cap));
+    uint64_t best = 1;
+    double best_t = 1e300;
+    for (uint64_t K = 1; K <= kmax; ++K) {
+        const double t = (double)((C * K + PART_WGS - 1) / PART_WGS) / (double)(C * K);
+        if (t < best_t * 0.999) {
+            best_t = t;
+            best = K;
+        }
+    }
+    return best;
+}
 
 uint32_t ceil_log2(uint64_t x) {
     uint32_t l = 0;
@@ -574,15 +601,17 @@ class Builder {
         HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
         uint64_t xcap;
         uint32_t S;
+        uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
         if (B <= 1024) {
             // one pass: every workgroup scatters its share straight into the buckets
             uint64_t W = (n + 8191) / 8192;
             W = std::max<uint64_t>(1, std::min<uint64_t>(W, 256));
             const uint64_t cap = region_cap((double)n / W * (double)P / (double)m);
-            if ((st = ensure(&ws_->X, &ws_->capX, B * W * cap, "partition X")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->X, &ws_->capX, B * W * cap + 16, "partition X")) != MPHF_OK) return st;
+            X = line_align(ws_->X);
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(B <= 256 ? 8 : 10, false, in.base, in.stride, in.pre, 1, in.nseg,
-                                     (uint32_t)W, L, pb, 0, false, 0, B, ws_->X, cap, (uint32_t)W,
+                                     (uint32_t)W, L, pb, 0, false, 0, B, X, cap, (uint32_t)W,
                                      ws_->cntX, ovf, s_),
                     "partition");
             xcap = cap;
@@ -592,26 +621,27 @@ class Builder {
             const uint32_t fb = lb - 8;
             const uint64_t C = (B + (1ull << fb) - 1) >> fb;
             uint64_t W = (n + 65535) / 65536;
-            W = std::max<uint64_t>(1, std::min<uint64_t>(W, 768));
+            W = std::max<uint64_t>(1, std::min<uint64_t>(W, PART_WGS));
             const double pc = (double)(P << fb) / (double)m;
             const uint64_t cap1 = region_cap((double)n / W * pc);
-            if ((st = ensure(&ws_->Z, &ws_->capZ, C * W * cap1, "partition Z")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->Z, &ws_->capZ, C * W * cap1 + 16, "partition Z")) != MPHF_OK) return st;
+            uint64_t* const Z = line_align(ws_->Z);
             if ((st = ensure(&ws_->cntZ, &ws_->capCntZ, C * W + 1, "counts Z")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
-                                     fb, false, 0, C, ws_->Z, cap1, (uint32_t)W, ws_->cntZ, ovf, s_),
+                                     fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, s_),
                     "partition 1");
             HIP_TRY(launch_zero32(ws_->cntZ + C * W, 1, s_), "zero count tail");
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
             if ((st = prefix(ws_->cntZ, C * W, ws_->preZ)) != MPHF_OK) return st;
-            uint64_t K = 768 / C;
-            K = std::max<uint64_t>(1, std::min<uint64_t>(K, 64));
+            const uint64_t K = slots_per_group(C, n);
             const double bin_keys = (double)n * pc;
             const double e2 = bin_keys / (double)K / (double)(1ull << fb) * (1.0 + 8.0 / std::sqrt(bin_keys));
             const uint64_t cap2 = region_cap(e2);
-            if ((st = ensure(&ws_->X, &ws_->capX, B * K * cap2, "partition X")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->X, &ws_->capX, B * K * cap2 + 16, "partition X")) != MPHF_OK) return st;
+            X = line_align(ws_->X);
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
-            HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, ws_->Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
-                                     (uint32_t)K, L, pb, 0, true, fb, B, ws_->X, cap2, (uint32_t)K,
+            HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
+                                     (uint32_t)K, L, pb, 0, true, fb, B, X, cap2, (uint32_t)K,
                                      ws_->cntX, ovf, s_),
                     "partition 2");
             xcap = cap2;
@@ -624,7 +654,7 @@ class Builder {
         if ((st = ensure(&ws_->surv[yp], &ws_->capSurv[yp], B + 1, "survivor counts")) != MPHF_OK) return st;
         if ((st = ensure(&ws_->preY[yp], &ws_->capPreY[yp], B + 1, "survivor prefix")) != MPHF_OK) return st;
         uint64_t* C_level = coll_ ? coll_ + off / 64 : nullptr;
-        HIP_TRY(launch_bucket(ws_->X, xcap, ws_->cntX, S, B, L, pb, g.kcap, words_ + off / 64, C_level, wd,
+        HIP_TRY(launch_bucket(X, xcap, ws_->cntX, S, B, L, pb, g.kcap, words_ + off / 64, C_level, wd,
                               ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_),
                 "bucket");
         HIP_TRY(launch_zero32(ws_->surv[yp] + B, 1, s_), "zero count tail");

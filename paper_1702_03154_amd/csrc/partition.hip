@@ -32,6 +32,7 @@ namespace {
 constexpr int PT = 512;               // threads of the partition kernel
 constexpr int PITEMS = 8;             // keys per thread per tile
 constexpr int PTILE = PT * PITEMS;    // keys per tile
+constexpr int TSEG = 64;              // input segments one tile may span
 constexpr int BT = 1024;              // threads of the tail kernel
 constexpr int KT = 512;               // threads of the bucket kernel
 constexpr int POOL_WORDS = 19712;     // 154 KiB of LDS for the tail kernel's keys and bits
@@ -55,10 +56,20 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // pre[s+1] - pre[s]) and writes each key to output region (bin * S_out + slot), where
 // bin = (pos_d(key) >> pbits) >> out_shift.  In a second pass every group is one coarse bin of
 // the first, so its keys fall in bins (group << group_shift) + [0, 2^group_shift); otherwise
-// the bins start at 0.  Either way a workgroup sees at most 2^DBITS bins.  A tile never spans
-// two input segments, so its values are one contiguous, coalesced read.  The input holds keys
+// the bins start at 0.  Either way a workgroup sees at most 2^DBITS bins, and a key outside the
+// bins its group owns is a configuration error (flag 4), never written.  A tile is a dense index
+// range across up to TSEG input segments, so small segments still give full tiles (each run of a
+// segment is a contiguous, coalesced read).  The input holds keys
 // (HASHED = false: h = fmix64(x ^ s_d) is computed here) or already their level hashes; the
 // output always holds the level hashes.
+//
+// A tile is counting-sorted by bin in LDS.  With 2^8 bins (WC) a workgroup also keeps, per bin,
+// the keys of its last unfinished 16-key line in LDS, and a tile writes only whole lines: a
+// 128-byte line at a 128-byte boundary of the bin's region (out_cap is a multiple of 16), each
+// line written once, by 16 adjacent lanes.  The runs of a tile average 16 keys per bin, so
+// writing them where they fall would split most lines between two tiles and two writes.  The
+// unfinished lines go out at the end.  With 2^10 bins the per-bin lines would not fit in LDS and
+// the runs are written as they are.
 template <int DBITS, bool HASHED>
 __global__ void __launch_bounds__(PT)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
@@ -67,12 +78,22 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             uint64_t out_cap, uint32_t S_out, uint32_t* __restrict__ out_cnt,
             unsigned long long* overflow) {
     constexpr int NB = 1 << DBITS;
+    constexpr bool WC = DBITS == 8;
+    static_assert(!WC || PT >= NB, "one bin per thread in the line bookkeeping");
+    constexpr int LW = 16;                                   // keys per 128-byte line
+    constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
     __shared__ uint64_t skeys[PTILE];
-    __shared__ uint16_t sdig[PTILE];
+    __shared__ uint16_t sdig[WC ? 1 : PTILE];
+    __shared__ uint64_t carry[WC ? NB * LW : 1];             // unfinished line of each bin
     __shared__ uint32_t hist[NB];
     __shared__ uint32_t hoff[NB];
     __shared__ uint32_t run[NB];
+    __shared__ uint32_t rold[WC ? NB : 1];                   // run[] before the tile
+    __shared__ uint32_t fpre[WC ? NB : 1];                   // first flushed key of the bin in the tile's flush order
+    __shared__ uint16_t lbin[MAXL];                          // bin of each flushed line
     __shared__ uint32_t wsum[PT / 64 + 1];
+    __shared__ uint32_t s_nf;
+    __shared__ uint64_t sp[TSEG + 1];                        // pre[s .. s + TSEG] of the tile
 
     const uint32_t group = blockIdx.x / K;
     const uint32_t slot = blockIdx.x % K;
@@ -82,6 +103,11 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     const uint64_t lo = g0 + (uint64_t)slot * part < g1 ? g0 + (uint64_t)slot * part : g1;
     const uint64_t hi = lo + part < g1 ? lo + part : g1;
     const uint64_t bin_base = grouped ? (uint64_t)group << group_shift : 0;
+    // bins this workgroup may write: those its group owns, and only existing ones
+    const uint64_t owned = grouped ? (1ull << group_shift) : (uint64_t)NB;
+    const uint64_t lim = bin_base >= nbins ? 0 : (nbins - bin_base < owned ? nbins - bin_base : owned);
+    uint64_t* const obase = out + (bin_base * S_out + slot) * out_cap;   // region of digit d: + d*S_out*out_cap
+    const uint64_t ostride = (uint64_t)S_out * out_cap;
 
     for (int d = threadIdx.x; d < NB; d += PT) {
         hist[d] = 0;
@@ -89,22 +115,51 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     }
     __syncthreads();
 
+    // s: the segment holding t0.  A tile is the rest of that segment, up to PTILE keys, when that
+    // is at least half a tile (one contiguous read); otherwise it is a dense range across up to
+    // TSEG segments, each key found in the segment boundaries staged in LDS.
     uint32_t s = lo < hi ? find_segment(pre, s0, s1, lo) : s0;
+    uint64_t sb = pre[s], se = pre[s + 1];   // bounds of segment s, reloaded only when s moves
     uint64_t t0 = lo;
     while (t0 < hi) {
-        const uint64_t sb = pre[s], se = pre[s + 1] < hi ? pre[s + 1] : hi;
-        if (t0 >= se) {
+        while (se <= t0) {   // pre[s1] >= hi > t0 ends it
             ++s;
-            continue;
+            sb = se;
+            se = pre[s + 1];
         }
-        const uint32_t tn = (uint32_t)(se - t0 < (uint64_t)PTILE ? se - t0 : PTILE);
-        const uint64_t* src = in + (uint64_t)s * in_stride + (t0 - sb);
+        uint64_t te = t0 + PTILE < hi ? t0 + PTILE : hi;
         uint64_t k[PITEMS];
+        if (se - t0 >= (uint64_t)(PTILE / 2) || se >= te) {
+            if (se < te) te = se;
+            const uint32_t tn = (uint32_t)(te - t0);
+            const uint64_t* src = in + (uint64_t)s * in_stride + (t0 - sb);
 #pragma unroll
-        for (int it = 0; it < PITEMS; ++it) {
-            const uint32_t j = it * PT + threadIdx.x;
-            k[it] = j < tn ? src[j] : 0;
+            for (int it = 0; it < PITEMS; ++it) {
+                const uint32_t j = it * PT + threadIdx.x;
+                k[it] = j < tn ? src[j] : 0;
+            }
+        } else {
+            for (uint32_t q = threadIdx.x; q <= (uint32_t)TSEG; q += PT) sp[q] = pre[s + q < s1 ? s + q : s1];
+            __syncthreads();
+            if (sp[TSEG] < te) te = sp[TSEG];
+            const uint32_t tn = (uint32_t)(te - t0);
+            // segment of the thread's first key by binary search, later keys by stepping forward
+            const uint64_t i0 = t0 + threadIdx.x;
+            uint32_t q = 0;
+            for (uint32_t b = TSEG / 2; b > 0; b >>= 1)
+                if (sp[q + b] <= i0) q += b;
+#pragma unroll
+            for (int it = 0; it < PITEMS; ++it) {
+                const uint32_t j = it * PT + threadIdx.x;
+                k[it] = 0;
+                if (j < tn) {
+                    const uint64_t i = t0 + j;
+                    while (sp[q + 1] <= i) ++q;
+                    k[it] = in[(uint64_t)(s + q) * in_stride + (i - sp[q])];
+                }
+            }
         }
+        const uint32_t tn = (uint32_t)(te - t0);
         uint32_t dg[PITEMS], rk[PITEMS];
 #pragma unroll
         for (int it = 0; it < PITEMS; ++it) {
@@ -114,7 +169,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                 if (!HASHED) k[it] = fmix64(k[it] ^ L.seed);
                 const uint64_t pos = mod_invariant(k[it], L.m, L.magic, L.sh1, L.sh2);
                 const uint64_t bin = (pos >> pbits) >> out_shift;
-                if (bin >= bin_base && bin - bin_base < (uint64_t)NB) {
+                if (bin >= bin_base && bin - bin_base < lim) {
                     dg[it] = (uint32_t)(bin - bin_base);
                     rk[it] = atomicAdd(&hist[dg[it]], 1u);
                 } else {
@@ -123,60 +178,112 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             }
         }
         __syncthreads();
-        {   // exclusive scan of the tile histogram
-            constexpr int PER = NB / PT > 0 ? NB / PT : 1;
-            uint32_t v[PER];
-            uint32_t sum = 0;
-            const int b0 = threadIdx.x * PER;
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                v[q] = (b0 + q < NB) ? hist[b0 + q] : 0;
-                sum += v[q];
+        if constexpr (WC) {
+            // One scan gives both the tile's sorted offsets (low half) and the flush order of
+            // the lines it completes (high half): bin d completes the lines between
+            // floor(run/16) and floor((run + h)/16).  Both sums stay below 2^16.
+            const int d = threadIdx.x;
+            uint32_t h = 0, r = 0, f = 0;
+            if (d < NB) {
+                h = hist[d];
+                r = run[d];
+                f = ((r + h) & ~(uint32_t)(LW - 1)) - (r & ~(uint32_t)(LW - 1));
             }
             uint32_t tot;
-            uint32_t ex = block_exclusive_sum<PT>(sum, wsum, &tot);
+            const uint32_t ex = block_exclusive_sum<PT>(h | (f << 16), wsum, &tot);
+            if (d < NB) {
+                hoff[d] = ex & 0xFFFFu;
+                fpre[d] = ex >> 16;
+                rold[d] = r;
+                run[d] = r + h;
+                hist[d] = 0;
+                const uint32_t l0 = (ex >> 16) / LW;
+                for (uint32_t q = 0; q < f / LW; ++q) lbin[l0 + q] = (uint16_t)d;
+            }
+            if (threadIdx.x == 0) s_nf = tot >> 16;
+            __syncthreads();
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (b0 + q < NB) {
-                    hoff[b0 + q] = ex;
-                    ex += v[q];
+            for (int it = 0; it < PITEMS; ++it)
+                if (dg[it] < (uint32_t)NB) skeys[hoff[dg[it]] + rk[it]] = k[it];
+            __syncthreads();
+            // whole lines: key g of bin d comes from the unfinished line (g < run before the
+            // tile) or from the tile's sorted run
+            const uint32_t nf = s_nf;
+            for (uint32_t f = threadIdx.x; f < nf; f += PT) {
+                const uint32_t d = lbin[f / LW];
+                const uint32_t r = rold[d];
+                const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - fpre[d]);
+                const uint64_t v = g < r ? carry[d * LW + (g & (LW - 1))] : skeys[hoff[d] + (g - r)];
+                if (g < out_cap) obase[d * ostride + g] = v;
+            }
+            __syncthreads();
+            // keys past the last whole line start the bin's next unfinished line
+#pragma unroll
+            for (int it = 0; it < PITEMS; ++it) {
+                if (dg[it] < (uint32_t)NB) {
+                    const uint32_t r = rold[dg[it]];
+                    const uint32_t g = r + rk[it];
+                    if (g >= (run[dg[it]] & ~(uint32_t)(LW - 1)))   // run[] already counts the tile
+                        carry[dg[it] * LW + (g & (LW - 1))] = k[it];
                 }
-        }
-        __syncthreads();
+            }
+        } else {
+            {   // exclusive scan of the tile histogram
+                constexpr int PER = NB / PT > 0 ? NB / PT : 1;
+                uint32_t v[PER];
+                uint32_t sum = 0;
+                const int b0 = threadIdx.x * PER;
 #pragma unroll
-        for (int it = 0; it < PITEMS; ++it) {
-            if (dg[it] < (uint32_t)NB) {
-                const uint32_t p = hoff[dg[it]] + rk[it];
-                skeys[p] = k[it];
-                sdig[p] = (uint16_t)dg[it];
+                for (int q = 0; q < PER; ++q) {
+                    v[q] = (b0 + q < NB) ? hist[b0 + q] : 0;
+                    sum += v[q];
+                }
+                uint32_t tot;
+                uint32_t ex = block_exclusive_sum<PT>(sum, wsum, &tot);
+#pragma unroll
+                for (int q = 0; q < PER; ++q)
+                    if (b0 + q < NB) {
+                        hoff[b0 + q] = ex;
+                        ex += v[q];
+                    }
             }
-        }
-        __syncthreads();
-        // write the runs: position p of the sorted tile goes to its bin's region
-        for (uint32_t p = threadIdx.x; p < tn; p += PT) {
-            const uint32_t d = sdig[p];
-            const uint64_t o = (uint64_t)run[d] + (p - hoff[d]);
-            if (o < out_cap) {
-                out[((bin_base + d) * S_out + slot) * out_cap + o] = skeys[p];
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < PITEMS; ++it) {
+                if (dg[it] < (uint32_t)NB) {
+                    const uint32_t p = hoff[dg[it]] + rk[it];
+                    skeys[p] = k[it];
+                    sdig[p] = (uint16_t)dg[it];
+                }
             }
+            __syncthreads();
+            // write the runs: position p of the sorted tile goes to its bin's region
+            for (uint32_t p = threadIdx.x; p < tn; p += PT) {
+                const uint32_t d = sdig[p];
+                const uint64_t o = (uint64_t)run[d] + (p - hoff[d]);
+                if (o < out_cap) obase[d * ostride + o] = skeys[p];
+            }
+            __syncthreads();
+            for (int d = threadIdx.x; d < NB; d += PT) {
+                run[d] += hist[d];
+                hist[d] = 0;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int d = threadIdx.x; d < NB; d += PT) {
-            run[d] += hist[d];
-            hist[d] = 0;
-        }
-        __syncthreads();
-        t0 += tn;
+        t0 = te;
     }
-    // only the bins this workgroup's group owns (a second-pass group owns 2^group_shift bins;
-    // the neighbouring bins belong to other groups and must not be touched)
-    const uint32_t owned = grouped ? (1u << group_shift) : (uint32_t)NB;
-    for (int d = threadIdx.x; d < NB && (uint32_t)d < owned; d += PT) {
-        const uint64_t bin = bin_base + d;
-        if (bin < nbins) {
-            out_cnt[bin * S_out + slot] = run[d] < out_cap ? run[d] : (uint32_t)out_cap;
-            if (run[d] > out_cap) atomicOr(overflow, 1ull);
+    if constexpr (WC) {
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < NB * LW; e += PT) {   // the unfinished lines
+            const uint32_t d = e / LW;
+            const uint32_t r = run[d];
+            const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (e & (LW - 1));
+            if (g < r && g < out_cap) obase[d * ostride + g] = carry[e];
         }
+    }
+    for (uint64_t d = threadIdx.x; d < lim; d += PT) {
+        out_cnt[(bin_base + d) * S_out + slot] = run[d] < out_cap ? run[d] : (uint32_t)out_cap;
+        if (run[d] > out_cap) atomicOr(overflow, 1ull);
     }
 }
 
@@ -233,13 +340,18 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
     }
     const uint64_t pbase = b << pbits;
     uint64_t h[BI];
+    {
+        // segment of the thread's first key by binary search, later keys (KT further on each)
+        // by stepping forward; segoff[S] = nb ends every step
+        uint32_t q = threadIdx.x < nb ? seg_of(segoff, S, threadIdx.x) : 0;
 #pragma unroll
-    for (int it = 0; it < BI; ++it) {
-        const uint32_t i = it * KT + threadIdx.x;
-        h[it] = 0;
-        if (i < nb) {
-            const uint32_t q = seg_of(segoff, S, i);
-            h[it] = in[(b * S + q) * in_cap + (i - segoff[q])];
+        for (int it = 0; it < BI; ++it) {
+            const uint32_t i = it * KT + threadIdx.x;
+            h[it] = 0;
+            if (i < nb) {
+                while (segoff[q + 1] <= i) ++q;
+                h[it] = in[(b * S + q) * in_cap + (i - segoff[q])];
+            }
         }
     }
 #pragma unroll
@@ -283,11 +395,18 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
         }
     }
     uint32_t tot;
-    uint32_t o = block_exclusive_sum<KT>((uint32_t)__popcll(mask), wsum, &tot);
+    const uint32_t o = block_exclusive_sum<KT>((uint32_t)__popcll(mask), wsum, &tot);
+    // survivors in (wave, item, lane) order, so that each store of a wave is one contiguous run
+    uint32_t wo = __shfl(o, 0, 64);
+    const uint64_t below = (1ull << lane_id()) - 1;
     uint64_t* dst = Y + b * ycap;
 #pragma unroll
-    for (int it = 0; it < BI; ++it)
-        if ((mask >> it) & 1ull) dst[o++] = unfmix64(h[it]) ^ L.seed;
+    for (int it = 0; it < BI; ++it) {
+        const bool keep = (mask >> it) & 1ull;
+        const uint64_t bal = __ballot(keep);
+        if (keep) dst[wo + __popcll(bal & below)] = unfmix64(h[it]) ^ L.seed;
+        wo += (uint32_t)__popcll(bal);
+    }
     if (threadIdx.x == 0) surv[b] = tot;
 }
 
