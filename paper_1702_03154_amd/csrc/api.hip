@@ -612,7 +612,7 @@ class Builder {
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(B <= 256 ? 8 : 10, false, in.base, in.stride, in.pre, 1, in.nseg,
                                      (uint32_t)W, L, pb, 0, false, 0, B, X, cap, (uint32_t)W,
-                                     ws_->cntX, ovf, s_),
+                                     ws_->cntX, ovf, n, in.nseg, s_),
                     "partition");
             xcap = cap;
             S = (uint32_t)W;
@@ -628,7 +628,7 @@ class Builder {
             uint64_t* const Z = line_align(ws_->Z);
             if ((st = ensure(&ws_->cntZ, &ws_->capCntZ, C * W + 1, "counts Z")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
-                                     fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, s_),
+                                     fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, n, in.nseg, s_),
                     "partition 1");
             HIP_TRY(launch_zero32(ws_->cntZ + C * W, 1, s_), "zero count tail");
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
@@ -642,7 +642,7 @@ class Builder {
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
                                      (uint32_t)K, L, pb, 0, true, fb, B, X, cap2, (uint32_t)K,
-                                     ws_->cntX, ovf, s_),
+                                     ws_->cntX, ovf, n, C * W, s_),
                     "partition 2");
             xcap = cap2;
             S = (uint32_t)K;

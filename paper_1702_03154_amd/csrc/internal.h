@@ -120,7 +120,7 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
-                            hipStream_t s);
+                            uint64_t n_in, uint64_t nseg_in, hipStream_t s);
 hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
                          uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint32_t kcap,
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,

@@ -57,9 +57,7 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // bin = (pos_d(key) >> pbits) >> out_shift.  In a second pass every group is one coarse bin of
 // the first, so its keys fall in bins (group << group_shift) + [0, 2^group_shift); otherwise
 // the bins start at 0.  Either way a workgroup sees at most 2^DBITS bins, and a key outside the
-// bins its group owns is a configuration error (flag 4), never written.  A tile is a dense index
-// range across up to TSEG input segments, so small segments still give full tiles (each run of a
-// segment is a contiguous, coalesced read).  The input holds keys
+// bins its group owns is a configuration error (flag 4), never written.  The input holds keys
 // (HASHED = false: h = fmix64(x ^ s_d) is computed here) or already their level hashes; the
 // output always holds the level hashes.
 //
@@ -70,7 +68,161 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // writing them where they fall would split most lines between two tiles and two writes.  The
 // unfinished lines go out at the end.  With 2^10 bins the per-bin lines would not fit in LDS and
 // the runs are written as they are.
-template <int DBITS, bool HASHED>
+//
+// Tiles: with SPAN = false a tile is the rest of its segment, up to PTILE keys, one contiguous
+// read, and the next tile's keys are loaded while the current one is sorted and written.  With
+// SPAN = true (inputs of small segments) a tile is a dense range across up to TSEG segments, each
+// key found in the segment boundaries staged in LDS.
+
+constexpr int LW = 16;   // keys per 128-byte line
+
+template <int NB, bool WC>
+struct PartLds {
+    static constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
+    uint64_t skeys[PTILE];          // the tile, sorted by bin
+    uint16_t sdig[WC ? 1 : PTILE];  // bin of each sorted key (runs written as they are)
+    uint64_t carry[WC ? NB * LW : 1];   // unfinished line of each bin
+    uint32_t hist[NB];              // keys of the tile per bin
+    uint32_t hoff[NB];              // first sorted position of the bin
+    uint32_t run[NB];               // keys of the bin so far, this tile included once scanned
+    uint32_t rold[WC ? NB : 1];     // run[] before the tile
+    uint32_t fpre[WC ? NB : 1];     // first key of the bin in the tile's flush order
+    uint16_t lbin[MAXL];            // bin of each whole line the tile writes
+    uint32_t wsum[PT / 64 + 1];
+    uint32_t nf;                    // keys in whole lines this tile
+    uint64_t sp[TSEG + 1];          // pre[s .. s + TSEG] of a spanning tile
+};
+
+// One tile of tn keys.  k[] holds a value for every item (items j >= tn hold copies and are
+// ignored); every value is hashed, so that the tile's loads are consumed on every path.
+template <int NB, bool WC, bool HASHED>
+__device__ __forceinline__ void part_tile(PartLds<NB, WC>& S, uint64_t (&k)[PITEMS], uint32_t tn,
+                                          const LevelHash& L, uint32_t pbits, uint32_t out_shift,
+                                          uint64_t bin_base, uint64_t lim, uint64_t* __restrict__ obase,
+                                          uint64_t ostride, uint64_t out_cap,
+                                          unsigned long long* overflow) {
+    uint32_t dg[PITEMS], rk[PITEMS];
+#pragma unroll
+    for (int it = 0; it < PITEMS; ++it) {
+        const uint32_t j = it * PT + threadIdx.x;
+        const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
+        const uint64_t bin = (mod_invariant(h, L.m, L.magic, L.sh1, L.sh2) >> pbits) >> out_shift;
+        k[it] = h;
+        dg[it] = NB;
+        if (j < tn) {
+            if (bin >= bin_base && bin - bin_base < lim) {
+                dg[it] = (uint32_t)(bin - bin_base);
+                rk[it] = atomicAdd(&S.hist[dg[it]], 1u);
+            } else {
+                atomicOr(overflow, 4ull);   // a configuration error: never silently dropped
+            }
+        }
+    }
+    __syncthreads();
+    if constexpr (WC) {
+        // One scan gives both the tile's sorted offsets (low half) and the flush order of the
+        // lines it completes (high half): bin d completes the lines between floor(run/16) and
+        // floor((run + h)/16).  Both sums stay below 2^16.
+        const int d = threadIdx.x;
+        uint32_t h = 0, r = 0, f = 0;
+        if (d < NB) {
+            h = S.hist[d];
+            r = S.run[d];
+            f = ((r + h) & ~(uint32_t)(LW - 1)) - (r & ~(uint32_t)(LW - 1));
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum<PT>(h | (f << 16), S.wsum, &tot);
+        if (d < NB) {
+            S.hoff[d] = ex & 0xFFFFu;
+            S.fpre[d] = ex >> 16;
+            S.rold[d] = r;
+            S.run[d] = r + h;
+            S.hist[d] = 0;
+            const uint32_t l0 = (ex >> 16) / LW;
+            for (uint32_t q = 0; q < f / LW; ++q) S.lbin[l0 + q] = (uint16_t)d;
+        }
+        if (threadIdx.x == 0) S.nf = tot >> 16;
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < PITEMS; ++it)
+            if (dg[it] < (uint32_t)NB) S.skeys[S.hoff[dg[it]] + rk[it]] = k[it];
+        __syncthreads();
+        // whole lines: key g of bin d comes from the unfinished line (g < run before the tile)
+        // or from the tile's sorted run
+        const uint32_t nf = S.nf;
+        for (uint32_t f = threadIdx.x; f < nf; f += PT) {
+            const uint32_t d = S.lbin[f / LW];
+            const uint32_t r = S.rold[d];
+            const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - S.fpre[d]);
+            const uint64_t v = g < r ? S.carry[d * LW + (g & (LW - 1))] : S.skeys[S.hoff[d] + (g - r)];
+            if (g < out_cap) obase[d * ostride + g] = v;
+        }
+        __syncthreads();
+        // keys past the last whole line start the bin's next unfinished line (run[] already
+        // counts the tile)
+#pragma unroll
+        for (int it = 0; it < PITEMS; ++it) {
+            if (dg[it] < (uint32_t)NB) {
+                const uint32_t g = S.rold[dg[it]] + rk[it];
+                if (g >= (S.run[dg[it]] & ~(uint32_t)(LW - 1))) S.carry[dg[it] * LW + (g & (LW - 1))] = k[it];
+            }
+        }
+    } else {
+        {   // exclusive scan of the tile histogram
+            constexpr int PER = NB / PT > 0 ? NB / PT : 1;
+            uint32_t v[PER];
+            uint32_t sum = 0;
+            const int b0 = threadIdx.x * PER;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                v[q] = (b0 + q < NB) ? S.hist[b0 + q] : 0;
+                sum += v[q];
+            }
+            uint32_t tot;
+            uint32_t ex = block_exclusive_sum<PT>(sum, S.wsum, &tot);
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (b0 + q < NB) {
+                    S.hoff[b0 + q] = ex;
+                    ex += v[q];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < PITEMS; ++it) {
+            if (dg[it] < (uint32_t)NB) {
+                const uint32_t p = S.hoff[dg[it]] + rk[it];
+                S.skeys[p] = k[it];
+                S.sdig[p] = (uint16_t)dg[it];
+            }
+        }
+        __syncthreads();
+        // write the runs: position p of the sorted tile goes to its bin's region
+        for (uint32_t p = threadIdx.x; p < tn; p += PT) {
+            const uint32_t d = S.sdig[p];
+            const uint64_t o = (uint64_t)S.run[d] + (p - S.hoff[d]);
+            if (o < out_cap) obase[d * ostride + o] = S.skeys[p];
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < NB; d += PT) {
+            S.run[d] += S.hist[d];
+            S.hist[d] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Loads the tile [0, tn) of src (tn >= 1); items past the tile load the last key again.
+__device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t* __restrict__ src,
+                                          uint32_t tn) {
+#pragma unroll
+    for (int it = 0; it < PITEMS; ++it) {
+        const uint32_t j = it * PT + threadIdx.x;
+        k[it] = src[j < tn ? j : tn - 1];
+    }
+}
+
+template <int DBITS, bool HASHED, bool SPAN>
 __global__ void __launch_bounds__(PT)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
             uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift,
@@ -80,20 +232,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     constexpr int NB = 1 << DBITS;
     constexpr bool WC = DBITS == 8;
     static_assert(!WC || PT >= NB, "one bin per thread in the line bookkeeping");
-    constexpr int LW = 16;                                   // keys per 128-byte line
-    constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
-    __shared__ uint64_t skeys[PTILE];
-    __shared__ uint16_t sdig[WC ? 1 : PTILE];
-    __shared__ uint64_t carry[WC ? NB * LW : 1];             // unfinished line of each bin
-    __shared__ uint32_t hist[NB];
-    __shared__ uint32_t hoff[NB];
-    __shared__ uint32_t run[NB];
-    __shared__ uint32_t rold[WC ? NB : 1];                   // run[] before the tile
-    __shared__ uint32_t fpre[WC ? NB : 1];                   // first flushed key of the bin in the tile's flush order
-    __shared__ uint16_t lbin[MAXL];                          // bin of each flushed line
-    __shared__ uint32_t wsum[PT / 64 + 1];
-    __shared__ uint32_t s_nf;
-    __shared__ uint64_t sp[TSEG + 1];                        // pre[s .. s + TSEG] of the tile
+    __shared__ PartLds<NB, WC> S;
 
     const uint32_t group = blockIdx.x / K;
     const uint32_t slot = blockIdx.x % K;
@@ -110,180 +249,98 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     const uint64_t ostride = (uint64_t)S_out * out_cap;
 
     for (int d = threadIdx.x; d < NB; d += PT) {
-        hist[d] = 0;
-        run[d] = 0;
+        S.hist[d] = 0;
+        S.run[d] = 0;
     }
     __syncthreads();
 
-    // s: the segment holding t0.  A tile is the rest of that segment, up to PTILE keys, when that
-    // is at least half a tile (one contiguous read); otherwise it is a dense range across up to
-    // TSEG segments, each key found in the segment boundaries staged in LDS.
+    // s: the segment holding the tile start (its bounds sb, se are reloaded only when s moves)
     uint32_t s = lo < hi ? find_segment(pre, s0, s1, lo) : s0;
-    uint64_t sb = pre[s], se = pre[s + 1];   // bounds of segment s, reloaded only when s moves
-    uint64_t t0 = lo;
-    while (t0 < hi) {
-        while (se <= t0) {   // pre[s1] >= hi > t0 ends it
-            ++s;
-            sb = se;
-            se = pre[s + 1];
+    uint64_t sb = pre[s], se = pre[s + 1];
+    if constexpr (!SPAN) {
+        // the tile starting at t (< hi): the rest of its segment, up to PTILE keys
+        auto tile_end = [&](uint64_t t) {
+            while (se <= t) {   // pre[s1] >= hi > t ends it
+                ++s;
+                sb = se;
+                se = pre[s + 1];
+            }
+            const uint64_t e = t + PTILE < hi ? t + PTILE : hi;
+            return se < e ? se : e;
+        };
+        uint64_t kn[PITEMS];
+        uint64_t t0 = lo, te = lo;
+        if (t0 < hi) {
+            te = tile_end(t0);
+            load_tile(kn, in + (uint64_t)s * in_stride + (t0 - sb), (uint32_t)(te - t0));
         }
-        uint64_t te = t0 + PTILE < hi ? t0 + PTILE : hi;
-        uint64_t k[PITEMS];
-        if (se - t0 >= (uint64_t)(PTILE / 2) || se >= te) {
-            if (se < te) te = se;
+        while (t0 < hi) {
+            uint64_t k[PITEMS];
+#pragma unroll
+            for (int it = 0; it < PITEMS; ++it) k[it] = kn[it];
             const uint32_t tn = (uint32_t)(te - t0);
-            const uint64_t* src = in + (uint64_t)s * in_stride + (t0 - sb);
-#pragma unroll
-            for (int it = 0; it < PITEMS; ++it) {
-                const uint32_t j = it * PT + threadIdx.x;
-                k[it] = j < tn ? src[j] : 0;
+            const uint64_t t1 = te;
+            uint64_t te1 = t1;
+            if (t1 < hi) {   // the next tile's loads overlap this tile's sort and writes
+                te1 = tile_end(t1);
+                load_tile(kn, in + (uint64_t)s * in_stride + (t1 - sb), (uint32_t)(te1 - t1));
             }
-        } else {
-            for (uint32_t q = threadIdx.x; q <= (uint32_t)TSEG; q += PT) sp[q] = pre[s + q < s1 ? s + q : s1];
+            part_tile<NB, WC, HASHED>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
+                                      out_cap, overflow);
+            t0 = t1;
+            te = te1;
+        }
+    } else {
+        uint64_t t0 = lo;
+        while (t0 < hi) {
+            while (se <= t0) {
+                ++s;
+                sb = se;
+                se = pre[s + 1];
+            }
+            for (uint32_t q = threadIdx.x; q <= (uint32_t)TSEG; q += PT) S.sp[q] = pre[s + q < s1 ? s + q : s1];
             __syncthreads();
-            if (sp[TSEG] < te) te = sp[TSEG];
+            uint64_t te = t0 + PTILE < hi ? t0 + PTILE : hi;
+            if (S.sp[TSEG] < te) te = S.sp[TSEG];
             const uint32_t tn = (uint32_t)(te - t0);
-            // segment of the thread's first key by binary search, later keys by stepping forward
-            const uint64_t i0 = t0 + threadIdx.x;
-            uint32_t q = 0;
-            for (uint32_t b = TSEG / 2; b > 0; b >>= 1)
-                if (sp[q + b] <= i0) q += b;
+            uint64_t k[PITEMS];
+            {
+                // segment of the thread's first key by binary search, later keys by stepping
+                // forward; items past the tile read key t0 again
+                const uint64_t i0 = t0 + threadIdx.x;
+                uint32_t q = 0;
+                for (uint32_t b = TSEG / 2; b > 0; b >>= 1)
+                    if (S.sp[q + b] <= i0) q += b;
 #pragma unroll
-            for (int it = 0; it < PITEMS; ++it) {
-                const uint32_t j = it * PT + threadIdx.x;
-                k[it] = 0;
-                if (j < tn) {
-                    const uint64_t i = t0 + j;
-                    while (sp[q + 1] <= i) ++q;
-                    k[it] = in[(uint64_t)(s + q) * in_stride + (i - sp[q])];
-                }
-            }
-        }
-        const uint32_t tn = (uint32_t)(te - t0);
-        uint32_t dg[PITEMS], rk[PITEMS];
-#pragma unroll
-        for (int it = 0; it < PITEMS; ++it) {
-            const uint32_t j = it * PT + threadIdx.x;
-            dg[it] = NB;
-            if (j < tn) {
-                if (!HASHED) k[it] = fmix64(k[it] ^ L.seed);
-                const uint64_t pos = mod_invariant(k[it], L.m, L.magic, L.sh1, L.sh2);
-                const uint64_t bin = (pos >> pbits) >> out_shift;
-                if (bin >= bin_base && bin - bin_base < lim) {
-                    dg[it] = (uint32_t)(bin - bin_base);
-                    rk[it] = atomicAdd(&hist[dg[it]], 1u);
-                } else {
-                    atomicOr(overflow, 4ull);   // a configuration error: never silently dropped
-                }
-            }
-        }
-        __syncthreads();
-        if constexpr (WC) {
-            // One scan gives both the tile's sorted offsets (low half) and the flush order of
-            // the lines it completes (high half): bin d completes the lines between
-            // floor(run/16) and floor((run + h)/16).  Both sums stay below 2^16.
-            const int d = threadIdx.x;
-            uint32_t h = 0, r = 0, f = 0;
-            if (d < NB) {
-                h = hist[d];
-                r = run[d];
-                f = ((r + h) & ~(uint32_t)(LW - 1)) - (r & ~(uint32_t)(LW - 1));
-            }
-            uint32_t tot;
-            const uint32_t ex = block_exclusive_sum<PT>(h | (f << 16), wsum, &tot);
-            if (d < NB) {
-                hoff[d] = ex & 0xFFFFu;
-                fpre[d] = ex >> 16;
-                rold[d] = r;
-                run[d] = r + h;
-                hist[d] = 0;
-                const uint32_t l0 = (ex >> 16) / LW;
-                for (uint32_t q = 0; q < f / LW; ++q) lbin[l0 + q] = (uint16_t)d;
-            }
-            if (threadIdx.x == 0) s_nf = tot >> 16;
-            __syncthreads();
-#pragma unroll
-            for (int it = 0; it < PITEMS; ++it)
-                if (dg[it] < (uint32_t)NB) skeys[hoff[dg[it]] + rk[it]] = k[it];
-            __syncthreads();
-            // whole lines: key g of bin d comes from the unfinished line (g < run before the
-            // tile) or from the tile's sorted run
-            const uint32_t nf = s_nf;
-            for (uint32_t f = threadIdx.x; f < nf; f += PT) {
-                const uint32_t d = lbin[f / LW];
-                const uint32_t r = rold[d];
-                const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - fpre[d]);
-                const uint64_t v = g < r ? carry[d * LW + (g & (LW - 1))] : skeys[hoff[d] + (g - r)];
-                if (g < out_cap) obase[d * ostride + g] = v;
-            }
-            __syncthreads();
-            // keys past the last whole line start the bin's next unfinished line
-#pragma unroll
-            for (int it = 0; it < PITEMS; ++it) {
-                if (dg[it] < (uint32_t)NB) {
-                    const uint32_t r = rold[dg[it]];
-                    const uint32_t g = r + rk[it];
-                    if (g >= (run[dg[it]] & ~(uint32_t)(LW - 1)))   // run[] already counts the tile
-                        carry[dg[it] * LW + (g & (LW - 1))] = k[it];
-                }
-            }
-        } else {
-            {   // exclusive scan of the tile histogram
-                constexpr int PER = NB / PT > 0 ? NB / PT : 1;
-                uint32_t v[PER];
-                uint32_t sum = 0;
-                const int b0 = threadIdx.x * PER;
-#pragma unroll
-                for (int q = 0; q < PER; ++q) {
-                    v[q] = (b0 + q < NB) ? hist[b0 + q] : 0;
-                    sum += v[q];
-                }
-                uint32_t tot;
-                uint32_t ex = block_exclusive_sum<PT>(sum, wsum, &tot);
-#pragma unroll
-                for (int q = 0; q < PER; ++q)
-                    if (b0 + q < NB) {
-                        hoff[b0 + q] = ex;
-                        ex += v[q];
+                for (int it = 0; it < PITEMS; ++it) {
+                    const uint32_t j = it * PT + threadIdx.x;
+                    uint64_t i = t0;
+                    uint32_t qi = 0;
+                    if (j < tn) {
+                        i = t0 + j;
+                        while (S.sp[q + 1] <= i) ++q;
+                        qi = q;
                     }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int it = 0; it < PITEMS; ++it) {
-                if (dg[it] < (uint32_t)NB) {
-                    const uint32_t p = hoff[dg[it]] + rk[it];
-                    skeys[p] = k[it];
-                    sdig[p] = (uint16_t)dg[it];
+                    k[it] = in[(uint64_t)(s + qi) * in_stride + (i - S.sp[qi])];
                 }
             }
-            __syncthreads();
-            // write the runs: position p of the sorted tile goes to its bin's region
-            for (uint32_t p = threadIdx.x; p < tn; p += PT) {
-                const uint32_t d = sdig[p];
-                const uint64_t o = (uint64_t)run[d] + (p - hoff[d]);
-                if (o < out_cap) obase[d * ostride + o] = skeys[p];
-            }
-            __syncthreads();
-            for (int d = threadIdx.x; d < NB; d += PT) {
-                run[d] += hist[d];
-                hist[d] = 0;
-            }
-            __syncthreads();
+            part_tile<NB, WC, HASHED>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
+                                      out_cap, overflow);
+            t0 = te;
         }
-        t0 = te;
     }
     if constexpr (WC) {
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < NB * LW; e += PT) {   // the unfinished lines
             const uint32_t d = e / LW;
-            const uint32_t r = run[d];
+            const uint32_t r = S.run[d];
             const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (e & (LW - 1));
-            if (g < r && g < out_cap) obase[d * ostride + g] = carry[e];
+            if (g < r && g < out_cap) obase[d * ostride + g] = S.carry[e];
         }
     }
     for (uint64_t d = threadIdx.x; d < lim; d += PT) {
-        out_cnt[(bin_base + d) * S_out + slot] = run[d] < out_cap ? run[d] : (uint32_t)out_cap;
-        if (run[d] > out_cap) atomicOr(overflow, 1ull);
+        out_cnt[(bin_base + d) * S_out + slot] = S.run[d] < out_cap ? S.run[d] : (uint32_t)out_cap;
+        if (S.run[d] > out_cap) atomicOr(overflow, 1ull);
     }
 }
 
@@ -569,18 +626,27 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
-                            hipStream_t s) {
+                            uint64_t n_in, uint64_t nseg_in, hipStream_t s) {
     const dim3 grid(groups * K);
     const uint32_t gr = grouped ? 1u : 0u;
-#define MPHF_PART(DB, HS)                                                                       \
-    hipLaunchKernelGGL((k_partition<DB, HS>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
-                       pbits, out_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt,    \
-                       overflow)
+    // segments averaging under half a tile: tiles span segments
+    const bool span = nseg_in > 0 && n_in / nseg_in < (uint64_t)(PTILE / 2);
+#define MPHF_PART(DB, HS, SP)                                                                       \
+    hipLaunchKernelGGL((k_partition<DB, HS, SP>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
+                       pbits, out_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt, overflow)
+#define MPHF_PART2(DB, HS) \
+    do {                   \
+        if (span)          \
+            MPHF_PART(DB, HS, true); \
+        else               \
+            MPHF_PART(DB, HS, false); \
+    } while (0)
     if (dbits <= 8) {
-        if (hashed) MPHF_PART(8, true); else MPHF_PART(8, false);
+        if (hashed) MPHF_PART2(8, true); else MPHF_PART2(8, false);
     } else {
-        if (hashed) MPHF_PART(10, true); else MPHF_PART(10, false);
+        if (hashed) MPHF_PART2(10, true); else MPHF_PART2(10, false);
     }
+#undef MPHF_PART2
 #undef MPHF_PART
     return hipGetLastError();
 }
