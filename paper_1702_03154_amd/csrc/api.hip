@@ -1057,6 +1057,83 @@ const char* mphf_last_error(void) { return g_err.c_str(); }
 
 // ---------------------------------------------------------------- k-mer workload
 
+namespace {
+
+// Hash-set partition by radix passes over the top bits of h = fmix64(x ^ seed), written densely
+// into out: with bits <= 8 one pass over the keys; with 8 < bits <= 18 a pass into 2^8 coarse bins
+// (line-aligned regions of hashes) and a grouped pass over each coarse bin into its 2^(bits - 8)
+// sets.  The dense pass writes each workgroup's keys of a set at an offset counted beforehand over
+// the same input slices.  *ok = false if a region of the first pass overflowed (adversarial key
+// sets only): out is then incomplete and the caller redoes the partition another way.
+mphf_status partition_sets_radix(Arena& ar, const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed,
+                                 uint64_t* out, uint64_t* offsets, hipStream_t s, bool* ok) {
+    mphf_status st;
+    *ok = false;
+    const uint64_t nb = 1ull << bits;
+    const uint32_t sh = 64 - bits;   // set of x = fmix64(x ^ seed) >> sh
+    LevelHash L{};
+    L.seed = seed;
+    L.sh1 = sh;
+    uint64_t *pre0, *flag;
+    if ((st = ar.alloc(&pre0, 2, "partition prefix")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&flag, 1, "overflow flag")) != MPHF_OK) return st;
+    HIP_TRY(launch_pair(pre0, 0, n, s), "prefix");
+    HIP_TRY(launch_zero(flag, 1, s), "zero flag");
+    unsigned long long* ovf = (unsigned long long*)flag;
+    const uint64_t W = std::max<uint64_t>(1, std::min<uint64_t>(n / 65536, PART_WGS));
+    // the dense pass: input (in, stride, pre), groups x K workgroups
+    const uint64_t* in = keys;
+    uint64_t stride = 0, ngroups = 1, SG = 1, K = W, nseg = 1;
+    const uint64_t* pre = pre0;
+    uint32_t fb = 0;
+    if (bits > 8) {
+        fb = bits - 8;
+        const uint64_t C = 256;
+        const uint64_t cap1 = region_cap((double)n / (double)W / (double)C);
+        uint64_t *Zb, *preZ, *tz;
+        uint32_t* cntZ;
+        if ((st = ar.alloc(&Zb, C * W * cap1 + 16, "coarse regions")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&cntZ, C * W + 1, "coarse counts")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&preZ, C * W + 1, "coarse prefix")) != MPHF_OK) return st;
+        if ((st = ar.alloc(&tz, scan_tmp_tiles(C * W + 1), "scan tiles")) != MPHF_OK) return st;
+        uint64_t* const Z = line_align(Zb);
+        HIP_TRY(launch_partition(8, false, keys, 0, pre0, 1, 1, (uint32_t)W, L, 0, fb, false, 0, C, Z, cap1,
+                                 (uint32_t)W, cntZ, ovf, n, 1, s, 1),
+                "partition 1");
+        HIP_TRY(launch_zero32(cntZ + C * W, 1, s), "zero count tail");
+        HIP_TRY(launch_exclusive_scan(cntZ, preZ, C * W + 1, tz, s), "coarse prefix");
+        in = Z;
+        stride = cap1;
+        pre = preZ;
+        ngroups = C;
+        SG = W;
+        K = slots_per_group(C, n);
+        nseg = C * W;
+    }
+    uint32_t* cnt;
+    uint64_t *base, *tiles;
+    if ((st = ar.alloc(&cnt, nb * K + 1, "slice counts")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&base, nb * K + 1, "slice offsets")) != MPHF_OK) return st;
+    if ((st = ar.alloc(&tiles, scan_tmp_tiles(nb * K + 1), "scan tiles")) != MPHF_OK) return st;
+    HIP_TRY(launch_slice_counts(in, stride, pre, (uint32_t)ngroups, (uint32_t)SG, (uint32_t)K, seed, sh, bits > 8,
+                                bits > 8, fb, nb, cnt, s),
+            "slice counts");
+    HIP_TRY(launch_zero32(cnt + nb * K, 1, s), "zero count tail");
+    HIP_TRY(launch_exclusive_scan(cnt, base, nb * K + 1, tiles, s), "slice offsets");
+    HIP_TRY(launch_partition(bits > 8 && fb > 8 ? 10 : 8, bits > 8, in, stride, pre, (uint32_t)ngroups, (uint32_t)SG,
+                             (uint32_t)K, L, 0, 0, bits > 8, fb, nb, out, 0, (uint32_t)K, nullptr, ovf, n, nseg, s,
+                             2, base),
+            "dense partition");
+    HIP_TRY(launch_take_every(base, (uint32_t)K, nb, offsets, s), "offsets");
+    uint64_t h_flag = 0;
+    HIP_TRY(hipMemcpyAsync(&h_flag, flag, 8, hipMemcpyDeviceToHost, s), "read flag");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    *ok = h_flag == 0;
+    return MPHF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 mphf_status mphf_kmers(const uint64_t* seq, uint64_t nbases, uint32_t k, uint64_t* out, void* stream) {
@@ -1154,6 +1231,15 @@ mphf_status mphf_partition_sets(const uint64_t* keys, uint64_t n, uint32_t bits,
     const hipStream_t s = (hipStream_t)stream;
     mphf_status st;
     Arena ar(0, s);
+    if (bits <= 18 && n >= 65536) {
+        bool ok = false;
+        if ((st = partition_sets_radix(ar, keys, n, bits, seed, out, offsets, s, &ok)) != MPHF_OK) return st;
+        if (ok) {
+            HIP_TRY(hipStreamSynchronize(s), "sync");
+            return MPHF_OK;
+        }
+        // a region overflowed: the scatter below is exact for any key set
+    }
     const uint64_t nb = 1ull << bits;
     uint32_t* counts;
     unsigned long long* cursor;

@@ -73,10 +73,17 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // read, and the next tile's keys are loaded while the current one is sorted and written.  With
 // SPAN = true (inputs of small segments) a tile is a dense range across up to TSEG segments, each
 // key found in the segment boundaries staged in LDS.
+//
+// DIG = 1 or 2 partitions by the top bits of h instead of its level position: pos = h >> L.sh1
+// (the hash-set partition of a key set into 2^(64 - sh1) independent sets).  DIG = 2 writes the
+// keys themselves (not their hashes) densely: bin d of this workgroup starts at dbase[(bin_base +
+// d) * S_out + slot] of out, counted beforehand by k_slice_counts over the same slices.  With
+// lines combined (WC) the bin's lines are counted from the line holding that start, and only the
+// workgroup's own keys of its first and last lines are written.
 
 constexpr int LW = 16;   // keys per 128-byte line
 
-template <int NB, bool WC>
+template <int NB, bool WC, bool DENSE>
 struct PartLds {
     static constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
     uint64_t skeys[PTILE];          // the tile, sorted by bin
@@ -91,12 +98,14 @@ struct PartLds {
     uint32_t wsum[PT / 64 + 1];
     uint32_t nf;                    // keys in whole lines this tile
     uint64_t sp[TSEG + 1];          // pre[s .. s + TSEG] of a spanning tile
+    uint64_t dst[DENSE ? NB : 1];   // dense output: the bin's first key at dst + a0 (dst on a line)
+    uint32_t a0[DENSE ? NB : 1];
 };
 
 // One tile of tn keys.  k[] holds a value for every item (items j >= tn hold copies and are
 // ignored); every value is hashed, so that the tile's loads are consumed on every path.
-template <int NB, bool WC, bool HASHED>
-__device__ __forceinline__ void part_tile(PartLds<NB, WC>& S, uint64_t (&k)[PITEMS], uint32_t tn,
+template <int NB, bool WC, bool HASHED, int DIG>
+__device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t (&k)[PITEMS], uint32_t tn,
                                           const LevelHash& L, uint32_t pbits, uint32_t out_shift,
                                           uint64_t bin_base, uint64_t lim, uint64_t* __restrict__ obase,
                                           uint64_t ostride, uint64_t out_cap,
@@ -106,8 +115,13 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC>& S, uint64_t (&k)[PITE
     for (int it = 0; it < PITEMS; ++it) {
         const uint32_t j = it * PT + threadIdx.x;
         const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
-        const uint64_t bin = (mod_invariant(h, L.m, L.magic, L.sh1, L.sh2) >> pbits) >> out_shift;
-        k[it] = h;
+        const uint64_t pos = DIG ? h >> L.sh1 : mod_invariant(h, L.m, L.magic, L.sh1, L.sh2);
+        const uint64_t bin = (pos >> pbits) >> out_shift;
+        if (DIG == 2) {   // dense output holds the keys
+            if (HASHED) k[it] = unfmix64(h) ^ L.seed;
+        } else {
+            k[it] = h;
+        }
         dg[it] = NB;
         if (j < tn) {
             if (bin >= bin_base && bin - bin_base < lim) {
@@ -155,7 +169,11 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC>& S, uint64_t (&k)[PITE
             const uint32_t r = S.rold[d];
             const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - S.fpre[d]);
             const uint64_t v = g < r ? S.carry[d * LW + (g & (LW - 1))] : S.skeys[S.hoff[d] + (g - r)];
-            if (g < out_cap) obase[d * ostride + g] = v;
+            if (DIG == 2) {
+                if (g >= S.a0[d]) obase[S.dst[d] + g] = v;
+            } else if (g < out_cap) {
+                obase[d * ostride + g] = v;
+            }
         }
         __syncthreads();
         // keys past the last whole line start the bin's next unfinished line (run[] already
@@ -201,7 +219,8 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC>& S, uint64_t (&k)[PITE
         for (uint32_t p = threadIdx.x; p < tn; p += PT) {
             const uint32_t d = S.sdig[p];
             const uint64_t o = (uint64_t)S.run[d] + (p - S.hoff[d]);
-            if (o < out_cap) obase[d * ostride + o] = S.skeys[p];
+            if (DIG == 2) obase[S.dst[d] + o] = S.skeys[p];
+            else if (o < out_cap) obase[d * ostride + o] = S.skeys[p];
         }
         __syncthreads();
         for (int d = threadIdx.x; d < NB; d += PT) {
@@ -222,17 +241,18 @@ __device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t*
     }
 }
 
-template <int DBITS, bool HASHED, bool SPAN>
+template <int DBITS, bool HASHED, bool SPAN, int DIG>
 __global__ void __launch_bounds__(PT)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
             uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift,
             uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
             uint64_t out_cap, uint32_t S_out, uint32_t* __restrict__ out_cnt,
-            unsigned long long* overflow) {
+            unsigned long long* overflow, const uint64_t* __restrict__ dbase) {
     constexpr int NB = 1 << DBITS;
     constexpr bool WC = DBITS == 8;
+    constexpr bool DENSE = DIG == 2;
     static_assert(!WC || PT >= NB, "one bin per thread in the line bookkeeping");
-    __shared__ PartLds<NB, WC> S;
+    __shared__ PartLds<NB, WC, DENSE> S;
 
     const uint32_t group = blockIdx.x / K;
     const uint32_t slot = blockIdx.x % K;
@@ -245,12 +265,22 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     // bins this workgroup may write: those its group owns, and only existing ones
     const uint64_t owned = grouped ? (1ull << group_shift) : (uint64_t)NB;
     const uint64_t lim = bin_base >= nbins ? 0 : (nbins - bin_base < owned ? nbins - bin_base : owned);
-    uint64_t* const obase = out + (bin_base * S_out + slot) * out_cap;   // region of digit d: + d*S_out*out_cap
+    // regions: digit d writes at obase + d * ostride; dense: at out + dst[d] (+ a0[d] for the first)
+    uint64_t* const obase = DENSE ? out : out + (bin_base * S_out + slot) * out_cap;
     const uint64_t ostride = (uint64_t)S_out * out_cap;
 
     for (int d = threadIdx.x; d < NB; d += PT) {
         S.hist[d] = 0;
         S.run[d] = 0;
+        if constexpr (DENSE) {
+            // this workgroup's keys of bin d go to [dbase, dbase + count) of out; whole lines are
+            // counted from the line holding dbase, whose keys before dbase are not written
+            const uint64_t B = (uint64_t)d < lim ? dbase[(bin_base + d) * S_out + slot] : 0;
+            const uint32_t a = WC ? (uint32_t)(B & (LW - 1)) : 0u;
+            S.dst[d] = B - a;
+            S.a0[d] = a;
+            S.run[d] = a;
+        }
     }
     __syncthreads();
 
@@ -285,7 +315,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                 te1 = tile_end(t1);
                 load_tile(kn, in + (uint64_t)s * in_stride + (t1 - sb), (uint32_t)(te1 - t1));
             }
-            part_tile<NB, WC, HASHED>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
+            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
                                       out_cap, overflow);
             t0 = t1;
             te = te1;
@@ -324,7 +354,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                     k[it] = in[(uint64_t)(s + qi) * in_stride + (i - S.sp[qi])];
                 }
             }
-            part_tile<NB, WC, HASHED>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
+            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
                                       out_cap, overflow);
             t0 = te;
         }
@@ -335,13 +365,61 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             const uint32_t d = e / LW;
             const uint32_t r = S.run[d];
             const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (e & (LW - 1));
-            if (g < r && g < out_cap) obase[d * ostride + g] = S.carry[e];
+            if (DENSE) {
+                if (g < r && g >= S.a0[d]) obase[S.dst[d] + g] = S.carry[e];
+            } else if (g < r && g < out_cap) {
+                obase[d * ostride + g] = S.carry[e];
+            }
         }
     }
-    for (uint64_t d = threadIdx.x; d < lim; d += PT) {
-        out_cnt[(bin_base + d) * S_out + slot] = S.run[d] < out_cap ? S.run[d] : (uint32_t)out_cap;
-        if (S.run[d] > out_cap) atomicOr(overflow, 1ull);
+    if constexpr (!DENSE) {
+        for (uint64_t d = threadIdx.x; d < lim; d += PT) {
+            out_cnt[(bin_base + d) * S_out + slot] = S.run[d] < out_cap ? S.run[d] : (uint32_t)out_cap;
+            if (S.run[d] > out_cap) atomicOr(overflow, 1ull);
+        }
     }
+}
+
+// Keys per (bin, workgroup) of the top-bits partition that k_partition would write, over the same
+// input slices: cnt[(bin_base + d) * K + slot], bin = top bits of h (h = x, or fmix64(x ^ seed)
+// for keys).  The exclusive prefix of cnt gives every workgroup's dense output start per bin.
+__global__ void __launch_bounds__(256)
+k_slice_counts(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
+               uint32_t SG, uint32_t K, uint64_t seed, uint32_t sh, uint32_t hashed, uint32_t grouped,
+               uint32_t group_shift, uint64_t nbins, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t hist[1024];
+    const uint32_t group = blockIdx.x / K;
+    const uint32_t slot = blockIdx.x % K;
+    const uint32_t s0 = group * SG, s1 = s0 + SG;
+    const uint64_t g0 = pre[s0], g1 = pre[s1];
+    const uint64_t part = (g1 - g0 + K - 1) / K;
+    const uint64_t lo = g0 + (uint64_t)slot * part < g1 ? g0 + (uint64_t)slot * part : g1;
+    const uint64_t hi = lo + part < g1 ? lo + part : g1;
+    const uint64_t bin_base = grouped ? (uint64_t)group << group_shift : 0;
+    const uint64_t owned = grouped ? (1ull << group_shift) : 1024ull;
+    const uint64_t lim = bin_base >= nbins ? 0 : (nbins - bin_base < owned ? nbins - bin_base : owned);
+    for (uint32_t d = threadIdx.x; d < 1024; d += 256) hist[d] = 0;
+    __syncthreads();
+    uint32_t s = lo < hi ? find_segment(pre, s0, s1, lo) : s0;
+    for (uint64_t t = lo; t < hi; ++s) {
+        const uint64_t sb = pre[s], se = pre[s + 1] < hi ? pre[s + 1] : hi;
+        const uint64_t* src = in + (uint64_t)s * in_stride;
+        for (uint64_t i = t + threadIdx.x; i < se; i += 256) {
+            const uint64_t x = src[i - sb];
+            const uint64_t d = ((hashed ? x : fmix64(x ^ seed)) >> sh) - bin_base;
+            if (d < lim) atomicAdd(&hist[d], 1u);
+        }
+        if (se > t) t = se;
+    }
+    __syncthreads();
+    for (uint64_t d = threadIdx.x; d < lim; d += 256) cnt[(bin_base + d) * K + slot] = hist[d];
+}
+
+// offsets[i] = base[i * K] for i <= nsets (every K-th entry of the (set, workgroup) prefix).
+__global__ void k_take_every(const uint64_t* __restrict__ base, uint32_t K, uint64_t nsets,
+                             uint64_t* __restrict__ offsets) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= nsets) offsets[i] = base[i * K];
 }
 
 // The segment q < S holding index i of a bucket, from the LDS prefix off[0..S].
@@ -564,6 +642,13 @@ k_tail(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __re
     }
 }
 
+__global__ void k_pair(uint64_t* p, uint64_t a, uint64_t b) {
+    if (threadIdx.x == 0) {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
 // Dense copy of a segmented set (used before falling back to the global-atomic levels).
 __global__ void k_gather(const uint64_t* __restrict__ in, uint64_t in_stride,
                          const uint64_t* __restrict__ pre, uint32_t nseg, uint64_t* __restrict__ out) {
@@ -626,27 +711,35 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
-                            uint64_t n_in, uint64_t nseg_in, hipStream_t s) {
+                            uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig, const uint64_t* dbase) {
     const dim3 grid(groups * K);
     const uint32_t gr = grouped ? 1u : 0u;
     // segments averaging under half a tile: tiles span segments
     const bool span = nseg_in > 0 && n_in / nseg_in < (uint64_t)(PTILE / 2);
-#define MPHF_PART(DB, HS, SP)                                                                       \
-    hipLaunchKernelGGL((k_partition<DB, HS, SP>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
-                       pbits, out_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt, overflow)
-#define MPHF_PART2(DB, HS) \
-    do {                   \
-        if (span)          \
-            MPHF_PART(DB, HS, true); \
-        else               \
-            MPHF_PART(DB, HS, false); \
-    } while (0)
-    if (dbits <= 8) {
-        if (hashed) MPHF_PART2(8, true); else MPHF_PART2(8, false);
+#define MPHF_PART(DB, HS, SP, DG)                                                                     \
+    hipLaunchKernelGGL((k_partition<DB, HS, SP, DG>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
+                       pbits, out_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt, overflow, dbase)
+    if (dig == 1) {
+        // regions by the top bits: the first pass over a dense key array
+        if (hashed || dbits > 8 || span) return hipErrorInvalidValue;
+        MPHF_PART(8, false, false, 1);
+    } else if (dig == 2) {
+        // dense output by the top bits: one pass over dense keys, or a grouped pass over regions
+        if (!hashed) {
+            if (dbits > 8 || span) return hipErrorInvalidValue;
+            MPHF_PART(8, false, false, 2);
+        } else if (dbits <= 8) {
+            if (span) MPHF_PART(8, true, true, 2); else MPHF_PART(8, true, false, 2);
+        } else {
+            if (span) MPHF_PART(10, true, true, 2); else MPHF_PART(10, true, false, 2);
+        }
+    } else if (dbits <= 8) {
+        if (hashed) { if (span) MPHF_PART(8, true, true, 0); else MPHF_PART(8, true, false, 0); }
+        else { if (span) MPHF_PART(8, false, true, 0); else MPHF_PART(8, false, false, 0); }
     } else {
-        if (hashed) MPHF_PART2(10, true); else MPHF_PART2(10, false);
+        if (hashed) { if (span) MPHF_PART(10, true, true, 0); else MPHF_PART(10, true, false, 0); }
+        else { if (span) MPHF_PART(10, false, true, 0); else MPHF_PART(10, false, false, 0); }
     }
-#undef MPHF_PART2
 #undef MPHF_PART
     return hipGetLastError();
 }
@@ -657,6 +750,26 @@ hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cn
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
     hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
                        pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_counts(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t groups,
+                               uint32_t SG, uint32_t K, uint64_t seed, uint32_t sh, bool hashed, bool grouped,
+                               uint32_t group_shift, uint64_t nbins, uint32_t* cnt, hipStream_t s) {
+    if (!grouped && nbins > 1024) return hipErrorInvalidValue;
+    if (grouped && group_shift > 10) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_slice_counts, dim3(groups * K), dim3(256), 0, s, in, in_stride, pre, SG, K, seed, sh,
+                       hashed ? 1u : 0u, grouped ? 1u : 0u, group_shift, nbins, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_take_every(const uint64_t* base, uint32_t K, uint64_t nsets, uint64_t* offsets, hipStream_t s) {
+    hipLaunchKernelGGL(k_take_every, dim3((unsigned)((nsets + 256) / 256)), dim3(256), 0, s, base, K, nsets, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair(uint64_t* p, uint64_t a, uint64_t b, hipStream_t s) {
+    hipLaunchKernelGGL(k_pair, dim3(1), dim3(64), 0, s, p, a, b);
     return hipGetLastError();
 }
 

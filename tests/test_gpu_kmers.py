@@ -81,6 +81,28 @@ def test_partition_sets(M):
     assert np.array_equal(np.sort(host(out)), np.sort(host(keys)))
 
 
+@pytest.mark.parametrize("n,bits", [(65_536, 9), (300_000, 12), (1_000_003, 15), (500_000, 18),
+                                    (70_000, 16), (2_000_000, 10), (40_000, 12), (3_000_000, 8)])
+def test_partition_sets_against_host_set_ids(M, n, bits):
+    """Every set of the partition holds exactly the keys whose top `bits` bits of fmix64(x ^ seed)
+    name it (set ids computed on the host), whichever path the size selects: one or two radix
+    passes for n >= 65536 and bits <= 18, the atomic scatter otherwise."""
+    seed = 0x1234_5678_9ABC_DEF1
+    keys = I.keys(n, 40 + bits).cuda()
+    out, off = M.partition_sets(keys, bits, seed=seed)
+    offn = off.cpu().numpy().astype(np.int64)
+    k = host(keys)
+    ids = (O.fmix64(k ^ np.uint64(seed)) >> np.uint64(64 - bits)).astype(np.int64)
+    counts = np.bincount(ids, minlength=1 << bits)
+    assert offn[0] == 0 and np.array_equal(np.diff(offn), counts)
+    got = host(out)
+    order = np.argsort(ids, kind="stable")
+    want = k[order]
+    # same keys per set (order inside a set is free)
+    seg = np.repeat(np.arange(1 << bits), counts)
+    assert np.array_equal(got[np.lexsort((got, seg))], want[np.lexsort((want, seg))])
+
+
 def occupancy(n, m):
     """Exact mean and standard deviation of the number of cells hit exactly once when n keys fall
     uniformly into m cells (the textbook occupancy problem): E[X] = n (1-1/m)^(n-1) and
