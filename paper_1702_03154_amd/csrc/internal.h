@@ -33,17 +33,9 @@ struct SegDesc {
     uint32_t pad;
 };
 
-// The label of query x (Algorithm 3): the first level whose bit is set gives the ones of A before
-// it plus one; else the fallback table (ascending keys, labels N - nfb + 1 ..); else 0.
-__device__ __forceinline__ uint64_t label_of(uint64_t x, const DevLevel* __restrict__ lev, uint32_t nlev,
-                                             const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
-                                             const uint64_t* __restrict__ fbk, uint64_t nfb, uint64_t N) {
-    for (uint32_t d = 0; d < nlev; ++d) {
-        const DevLevel L = lev[d];
-        const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
-        uint64_t rank;
-        if (sector_rank(sec, super, g, &rank)) return rank + 1;
-    }
+// The label of x in the fallback table (ascending keys, labels N - nfb + 1 ..), else 0.
+__device__ __forceinline__ uint64_t fallback_label(uint64_t x, const uint64_t* __restrict__ fbk, uint64_t nfb,
+                                                   uint64_t N) {
     if (nfb) {
         uint64_t lo = 0, hi = nfb;   // first index with fbk[idx] >= x
         while (lo < hi) {
@@ -53,6 +45,63 @@ __device__ __forceinline__ uint64_t label_of(uint64_t x, const DevLevel* __restr
         if (lo < nfb && fbk[lo] == x) return N - nfb + 1 + lo;
     }
     return 0;
+}
+
+// The label of query x (Algorithm 3): the first level whose bit is set gives the ones of A before
+// it plus one; else the fallback table; else 0.
+__device__ __forceinline__ uint64_t label_of(uint64_t x, const DevLevel* __restrict__ lev, uint32_t nlev,
+                                             const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
+                                             const uint64_t* __restrict__ fbk, uint64_t nfb, uint64_t N) {
+    for (uint32_t d = 0; d < nlev; ++d) {
+        const DevLevel L = lev[d];
+        const uint64_t g = L.bit_off + mod_invariant(fmix64(x ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
+        uint64_t rank;
+        if (sector_rank(sec, super, g, &rank)) return rank + 1;
+    }
+    return fallback_label(x, fbk, nfb, N);
+}
+
+// The labels of QP queries of one function walked level by level in lockstep (Algorithm 3 for
+// each): every level's probes of the still pending queries are issued together, so a lane keeps
+// QP independent sector loads in flight.  res[u] gets the label when pend[u] (pend[u] false on
+// entry skips x[u]); queries that find no set bit stay pending for the fallback table.
+template <int QP>
+__device__ __forceinline__ void walk_levels(const uint64_t (&x)[QP], bool (&pend)[QP], uint64_t (&res)[QP],
+                                            const DevLevel* __restrict__ lev, uint32_t nlev,
+                                            const uint32_t* __restrict__ sec,
+                                            const uint64_t* __restrict__ super) {
+    for (uint32_t d = 0; d < nlev; ++d) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < QP; ++u) any |= pend[u];
+        if (!any) return;
+        const DevLevel L = lev[d];
+        uint4 v[QP][4];
+        uint64_t base[QP];
+        uint32_t r[QP];
+#pragma unroll
+        for (int u = 0; u < QP; ++u) {
+            const uint64_t g = L.bit_off + mod_invariant(fmix64(x[u] ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
+            const uint64_t j = g / SEC_BITS;
+            r[u] = (uint32_t)(g - j * SEC_BITS);
+            base[u] = 0;
+            if (pend[u]) {
+                base[u] = super[j >> SUPER_SHIFT];
+                sector_load(sec, j, v[u]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[u][c] = make_uint4(0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < QP; ++u) {
+            uint32_t c;
+            if (pend[u] && sector_count(v[u], r[u], &c)) {
+                res[u] = base[u] + c + 1;
+                pend[u] = false;
+            }
+        }
+    }
 }
 
 struct SeedTable {

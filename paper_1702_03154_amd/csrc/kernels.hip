@@ -307,13 +307,23 @@ __global__ void k_sector_write(const uint32_t* __restrict__ A32, uint64_t nwords
 
 // ---------------------------------------------------------------- lookup (Algorithm 3)
 
+// Two queries per lane (i and i + stride) walked in lockstep, which doubles the independent sector
+// loads a wave keeps in flight.  Queries and labels are streamed with non-temporal accesses so
+// that they do not displace the structure's lines from the caches.
 __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* __restrict__ out,
                          const DevLevel* __restrict__ lev, uint32_t nlev,
                          const uint32_t* __restrict__ sec, const uint64_t* __restrict__ super,
                          const uint64_t* __restrict__ fbk, uint64_t nfb, uint64_t N) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        out[i] = label_of(q[i], lev, nlev, sec, super, fbk, nfb, N);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += 2 * stride) {
+        const uint64_t i2 = i + stride;
+        bool pend[2] = {true, i2 < n};
+        const uint64_t x[2] = {__builtin_nontemporal_load(q + i), pend[1] ? __builtin_nontemporal_load(q + i2) : 0};
+        uint64_t res[2] = {0, 0};
+        walk_levels<2>(x, pend, res, lev, nlev, sec, super);
+        __builtin_nontemporal_store(pend[0] ? fallback_label(x[0], fbk, nfb, N) : res[0], out + i);
+        if (i2 < n) __builtin_nontemporal_store(pend[1] ? fallback_label(x[1], fbk, nfb, N) : res[1], out + i2);
+    }
 }
 
 __global__ void k_positions(const uint64_t* __restrict__ keys, uint64_t n, LevelHash L,
