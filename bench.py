@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 LINE_BYTES = 128               # a random read on gfx950 moves one 128-byte line from HBM (measured)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lookup_traffic.json")
+BUILD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "build_1e9_gamma2_traffic.json")
 
 
 def mean_probes(st) -> float:
@@ -68,6 +69,30 @@ def measured_traffic(n_queries: int):
     if t.get("source_sha256") != sha or t.get("queries") != n_queries:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+
+
+def measured_build_traffic(n_keys: int):
+    """HBM bytes of one plain build from the committed counter summary, if it was taken on the
+    current build sources and the same key count; else None."""
+    from paper_1702_03154_amd.profsum import BUILD_SOURCES, source_digest
+    try:
+        with open(BUILD_TRAFFIC_FILE) as f:
+            t = json.load(f)
+        sha = source_digest(BUILD_SOURCES)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != sha or t.get("keys") != n_keys:
+        return None
+    return t["bytes_per_build"]
+
+
+def build_algorithmic_bytes(st) -> float:
+    """Bytes the method itself moves in one build (the fused model of one pass per level): every
+    key of F_d read once, every survivor written once, the concatenated A and the rank table
+    written once (Sections 2.1, 2.2 and 3.1)."""
+    nd = st["level_n"][:st["num_levels"]]
+    survivors = sum(nd[1:]) + st["n_fallback"]
+    return 8.0 * sum(nd) + 8.0 * survivors + st["total_bits"] / 8.0 + 8.0 * st["rank_entries"]
 
 
 def cpu_baseline(n: int, gamma: float):
@@ -706,6 +731,8 @@ def main():
     lookup_bytes = n * (16.0 + LINE_BYTES * probes)
     achieved = lookup_bytes / (tl / 1e3) / 1e9
     traffic = measured_traffic(n)
+    build_bytes = build_algorithmic_bytes(stats)
+    build_traffic = measured_build_traffic(n)
     res = {
         "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
         "value": n * args.steps / (total_ms / 1e3),
@@ -727,6 +754,14 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_lookup",
                      "algorithmic_bytes_per_query": 16.0 + LINE_BYTES * probes},
+        # The build beside the same roofline: the method's own bytes (one pass per level) over
+        # the build time, and the bytes the build's kernels move (two radix passes and the
+        # bucket pass per level instead of global atomics).
+        "build_roofline": {"bound": "hbm", "achieved": build_bytes / (tb / 1e3) / 1e9,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": build_bytes / (tb / 1e3) / 1e9 / HBM_PEAK_GBS,
+                           "traffic": build_traffic,
+                           "algorithmic_bytes_per_key": build_bytes / n},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(int(args.cpu_sample), args.gamma)

@@ -5,6 +5,8 @@
     python -m paper_1702_03154_amd.profsum traffic <fetch.db> <write.db> <kernel> <queries> <out.json>
         HBM bytes of one launch of <kernel>, each counter scaled by what it reads for the
         1 GiB calibration copy (bench.py --calibrate-copy) run in the same process
+    python -m paper_1702_03154_amd.profsum build-traffic <fetch.db> <write.db> <keys> <out.json>
+        the same for every library kernel of the one build before the first lookup
 
 Kernel names are shortened (namespace and argument list dropped).
 """
@@ -47,15 +49,16 @@ def pmc(db: str, counter: str, out=sys.stdout):
 
 
 SOURCES = ("kernels.hip", "device.h")   # the lookup kernel and the device helpers it inlines
+BUILD_SOURCES = ("kernels.hip", "partition.hip", "device.h", "internal.h", "api.hip")   # the build
 
 
-def source_digest() -> str:
-    """SHA-256 over the sources the lookup kernel is built from."""
+def source_digest(sources=SOURCES) -> str:
+    """SHA-256 over the sources a kernel (by default the lookup kernel) is built from."""
     import hashlib
     import os
     h = hashlib.sha256()
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-    for f in SOURCES:
+    for f in sources:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -96,6 +99,30 @@ def traffic(fetch_db: str, write_db: str, kernel: str, queries: int, out_json: s
     print(json.dumps(res, indent=1))
 
 
+def build_traffic(fetch_db: str, write_db: str, keys: int, out_json: str):
+    """HBM bytes of one build: every library kernel dispatched before the first lookup, each counter
+    scaled by the calibration copy."""
+    import json
+    f_rows = _per_dispatch(fetch_db, "FETCH_SIZE")
+    w_rows = _per_dispatch(write_db, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    fs = gib_kib / _calibration(f_rows)
+    ws = gib_kib / _calibration(w_rows)
+
+    def build_kib(rows):
+        end = next(r[0] for r in rows if short(r[1]) == "k_lookup")
+        return sum(r[2] for r in rows if "mphfk" in r[1] and r[0] < end)
+
+    fk, wk = build_kib(f_rows), build_kib(w_rows)
+    res = {"what": "one plain build", "keys": keys, "fetch_kib": fk, "write_kib": wk,
+           "fetch_scale": fs, "write_scale": ws, "bytes_per_build": (fk * fs + wk * ws) * 1024.0,
+           "source_sha256": source_digest(BUILD_SOURCES)}
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+        f.write("\n")
+    print(json.dumps(res, indent=1))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
@@ -103,5 +130,7 @@ if __name__ == "__main__":
         pmc(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(float(sys.argv[5])), sys.argv[6])
+    elif sys.argv[1] == "build-traffic":
+        build_traffic(sys.argv[2], sys.argv[3], int(float(sys.argv[4])), sys.argv[5])
     else:
         raise SystemExit(__doc__)
