@@ -164,12 +164,16 @@ typedef struct mphf_key_stream {
 } mphf_key_stream;
 
 /* Build over the n keys of `src`.  While more than resident_keys keys are left, a level re-generates
- * every key, skips those placed at an earlier level (a lookup walk over the finished levels) and
- * marks the others with global test-and-set: the re-scan strategy of Section 3.4, which stores no
- * F_d.  Then the survivors are collected (8 bytes each) and the build continues in memory.  The
+ * every key and skips those placed at an earlier level (a lookup walk over the finished levels):
+ * the re-scan strategy of Section 3.4, which stores no F_d.  The others are taken in chunks of
+ * max(resident_keys, 2^20) stream keys: each chunk's are collected, radix-partitioned by position
+ * bucket and added to the level's A and C bits bucket by bucket in LDS.  Levels beyond 2^36
+ * positions, or flags = MPHF_FLAG_ATOMIC_LEVELS, mark the keys with global test-and-set instead.
+ * Then the survivors are collected (8 bytes each) and the build continues in memory.  The
  * function, its levels and labels equal those of mphf_build_ex on the materialized keys.  Device
- * memory: the structure, 2 gamma n bits for the first level's A and C, and the survivors.
- * flags must be 0.  Synchronous, like mphf_build_ex. */
+ * memory: the structure, 2 gamma n bits for the first level's A and C, the survivors and, for a
+ * chunk, its keys and two partition buffers of about 9 bytes per key.  flags: 0 or
+ * MPHF_FLAG_ATOMIC_LEVELS.  Synchronous, like mphf_build_ex. */
 mphf_status mphf_build_stream(const mphf_key_stream* src, uint64_t n, double gamma, uint64_t seed,
                               const mphf_opts* opts, uint64_t resident_keys, void* stream, mphf_t** out);
 

@@ -315,6 +315,9 @@ class Builder {
         uint64_t* W = nullptr;
         uint32_t d = 0;
         uint64_t off = 0, nd = n;
+        const BucketGeometry geo = bucket_geometry(gamma_);
+        uint64_t* chunk = nullptr;   // the unplaced keys of one chunk of the stream
+        uint64_t* pre0 = nullptr;
         while (nd > 0 && d < D && nd > budget) {
             const uint64_t m = level_size(gamma_, nd);
             const uint64_t wd = (m + 63) / 64;
@@ -322,7 +325,21 @@ class Builder {
             const LevelHash L = make_level_hash(seeds_.s[d], m, off);
             if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
             HIP_TRY(launch_zero(W, 2 * wd, s_), "zero W");
-            HIP_TRY(launch_stream_fill(kseed, kstart, n, lev, d, words_, W, L, s_), "stream fill");
+            // Buckets of 2^pb positions, at most 2^18 of them, so that each chunk takes two radix
+            // passes at most; a level beyond 2^36 positions, or the atomic-only option, takes
+            // global atomics over the whole stream instead.
+            uint32_t pb = geo.pbits ? geo.pbits : 15;
+            while (pb < 18 && ceil_log2((m + (1ull << pb) - 1) >> pb) > 18) ++pb;
+            bool accumulated = false;
+            if (!(o_.flags & MPHF_FLAG_ATOMIC_LEVELS) && ceil_log2((m + (1ull << pb) - 1) >> pb) <= 18) {
+                if ((st = accumulate_stream_level(kseed, kstart, n, lev, d, L, m, pb, budget, W, wd, &chunk, &pre0,
+                                                  &accumulated)) != MPHF_OK)
+                    return st;
+            }
+            if (!accumulated) {
+                HIP_TRY(launch_zero(W, 2 * wd, s_), "zero W");
+                HIP_TRY(launch_stream_fill(kseed, kstart, n, lev, d, words_, W, L, s_), "stream fill");
+            }
             HIP_TRY(launch_finalize(W, wd, words_ + off / 64, coll_ ? coll_ + off / 64 : nullptr, counters + d, s_),
                     "finalize");
             if ((st = read_back(counters + d, 8)) != MPHF_OK) return st;
@@ -340,6 +357,7 @@ class Builder {
             tr_.mark("streamed level", (long)(d - 1));
         }
         if (W) ar_.release(W);
+        if (chunk) ar_.release(chunk);
         if (!nd) {
             h_->total_words = h_->total_bits / 64;
             return finish();
@@ -353,6 +371,49 @@ class Builder {
         if (host_[0] != nd) return fail(MPHF_E_DEVICE, "collected survivors differ from the level counts");
         tr_.mark("collect", (long)nd);
         return levels_and_finish(dense, nd, d, off);
+    }
+
+    // Level d of a generated stream added to W chunk by chunk: the unplaced keys of up to `budget`
+    // stream keys at a time are collected, partitioned by bucket of 2^pb positions and accumulated
+    // (no global atomics).  *done = false if a region overflowed (adversarial streams only): W is
+    // then partial and the caller fills the level with global atomics.
+    mphf_status accumulate_stream_level(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
+                                        const LevelHash& L, uint64_t m, uint32_t pb, uint64_t budget, uint64_t* W,
+                                        uint64_t wd, uint64_t** chunk, uint64_t** pre0, bool* done) {
+        mphf_status st;
+        *done = false;
+        const uint64_t ch = std::min<uint64_t>(n, std::max<uint64_t>(budget, 1ull << 20));
+        if (!*chunk && (st = ar_.alloc(chunk, ch, "stream chunk")) != MPHF_OK) return st;
+        if (!*pre0 && (st = ar_.alloc(pre0, 2, "chunk prefix")) != MPHF_OK) return st;
+        HIP_TRY(accumulate_setup(), "accumulate setup");
+        unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
+        unsigned long long* cnt = (unsigned long long*)(dev_ + 300);
+        HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
+        const uint64_t B = (m + (1ull << pb) - 1) >> pb;
+        for (uint64_t c0 = 0; c0 < n; c0 += ch) {
+            const uint64_t c = std::min<uint64_t>(ch, n - c0);
+            HIP_TRY(launch_zero(dev_ + 300, 1, s_), "zero count");
+            HIP_TRY(launch_stream_collect(kseed, kstart + c0, c, lev, d, words_, *chunk, ch, cnt, s_), "collect");
+            if ((st = read_back(dev_ + 300, 8)) != MPHF_OK) return st;
+            const uint64_t nc = host_[0];
+            if (nc > c) return fail(MPHF_E_DEVICE, "collected more keys than the chunk holds");
+            if (!nc) continue;
+            HIP_TRY(launch_pair(*pre0, 0, nc, s_), "chunk prefix");
+            KeySet in;
+            in.base = *chunk;
+            in.pre = *pre0;
+            in.nseg = 1;
+            in.n = nc;
+            uint64_t* X = nullptr;
+            uint64_t xcap = 0;
+            uint32_t S = 0;
+            if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, ovf)) != MPHF_OK) return st;
+            HIP_TRY(launch_accumulate(X, xcap, ws_->cntX, S, B, L, pb, W, 2 * wd, ovf, s_), "accumulate");
+            tr_.mark("accumulated chunk", (long)nc);
+        }
+        if ((st = read_back(dev_ + 129, 8)) != MPHF_OK) return st;
+        *done = host_[0] == 0;
+        return MPHF_OK;
     }
 
     // Sizes, seeds, counters and the concatenated A reserved for n keys.
@@ -480,7 +541,8 @@ class Builder {
     SeedTable seeds_{};
     uint64_t* host_ = nullptr;
     uint64_t* dev_ = nullptr;        // [0..63] weights, [64..127] survivor counts, [128] dup flag,
-                                     // [129] overflow flag, [130..132] tail summary
+                                     // [129] overflow flag, [130..132] tail summary, [200] streamed
+                                     // survivors, [300] keys collected from a stream chunk
     TailLevel* tail_rec_ = nullptr;
     uint64_t* words_ = nullptr;
     uint64_t* coll_ = nullptr;
@@ -580,42 +642,32 @@ class Builder {
         return MPHF_OK;
     }
 
-    // One level by radix partition + per-bucket LDS pass.  *ok = false means a region or a
-    // bucket overflowed its capacity (only for adversarial key sets): nothing of the level is
-    // kept and the caller redoes it with global atomics.
-    mphf_status partitioned_level(const KeySet& in, uint32_t d, uint64_t off, const BucketGeometry& g,
-                                  KeySet* out, bool* ok) {
+    // The keys of `in` radix-partitioned by bucket of 2^pb positions of a level of m positions
+    // (ceil(m / 2^pb) <= 2^18 buckets): one pass, or coarse bins then buckets.  *X gets the
+    // regions (xcap keys each, *S per bucket) with their counts in ws_->cntX; region overflows
+    // and configuration errors are flagged in *ovf.
+    mphf_status partition_buckets(const KeySet& in, const LevelHash& L, uint64_t m, uint32_t pb, uint64_t** X,
+                                  uint64_t* xcap, uint32_t* S, unsigned long long* ovf) {
         mphf_status st;
-        *ok = false;
         const uint64_t n = in.n;
-        const uint64_t m = level_size(gamma_, n);
-        const uint64_t wd = (m + 63) / 64;
-        if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
-        const LevelHash L = make_level_hash(seeds_.s[d], m, off);
-        const uint32_t pb = g.pbits;
         const uint64_t P = 1ull << pb;
         const uint64_t B = (m + P - 1) / P;
         const uint32_t lb = ceil_log2(B);
-        if (lb > 18) return MPHF_OK;   // beyond two passes: use the atomic levels
-        unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
-        HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
-        uint64_t xcap;
-        uint32_t S;
-        uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
+        if (lb > 18) return fail(MPHF_E_INVALID, "more than 2^18 buckets");
         if (B <= 1024) {
             // one pass: every workgroup scatters its share straight into the buckets
             uint64_t W = (n + 8191) / 8192;
             W = std::max<uint64_t>(1, std::min<uint64_t>(W, 256));
             const uint64_t cap = region_cap((double)n / W * (double)P / (double)m);
             if ((st = ensure(&ws_->X, &ws_->capX, B * W * cap + 16, "partition X")) != MPHF_OK) return st;
-            X = line_align(ws_->X);
+            *X = line_align(ws_->X);
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(B <= 256 ? 8 : 10, false, in.base, in.stride, in.pre, 1, in.nseg,
-                                     (uint32_t)W, L, pb, 0, false, 0, B, X, cap, (uint32_t)W,
+                                     (uint32_t)W, L, pb, 0, false, 0, B, *X, cap, (uint32_t)W,
                                      ws_->cntX, ovf, n, in.nseg, s_),
                     "partition");
-            xcap = cap;
-            S = (uint32_t)W;
+            *xcap = cap;
+            *S = (uint32_t)W;
         } else {
             // two passes: coarse bins of 2^fb buckets, then the buckets of each coarse bin
             const uint32_t fb = lb - 8;
@@ -638,15 +690,41 @@ class Builder {
             const double e2 = bin_keys / (double)K / (double)(1ull << fb) * (1.0 + 8.0 / std::sqrt(bin_keys));
             const uint64_t cap2 = region_cap(e2);
             if ((st = ensure(&ws_->X, &ws_->capX, B * K * cap2 + 16, "partition X")) != MPHF_OK) return st;
-            X = line_align(ws_->X);
+            *X = line_align(ws_->X);
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
-                                     (uint32_t)K, L, pb, 0, true, fb, B, X, cap2, (uint32_t)K,
+                                     (uint32_t)K, L, pb, 0, true, fb, B, *X, cap2, (uint32_t)K,
                                      ws_->cntX, ovf, n, C * W, s_),
                     "partition 2");
-            xcap = cap2;
-            S = (uint32_t)K;
+            *xcap = cap2;
+            *S = (uint32_t)K;
         }
+        return MPHF_OK;
+    }
+
+    // One level by radix partition + per-bucket LDS pass.  *ok = false means a region or a
+    // bucket overflowed its capacity (only for adversarial key sets): nothing of the level is
+    // kept and the caller redoes it with global atomics.
+    mphf_status partitioned_level(const KeySet& in, uint32_t d, uint64_t off, const BucketGeometry& g,
+                                  KeySet* out, bool* ok) {
+        mphf_status st;
+        *ok = false;
+        const uint64_t n = in.n;
+        const uint64_t m = level_size(gamma_, n);
+        const uint64_t wd = (m + 63) / 64;
+        if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
+        const LevelHash L = make_level_hash(seeds_.s[d], m, off);
+        const uint32_t pb = g.pbits;
+        const uint64_t P = 1ull << pb;
+        const uint64_t B = (m + P - 1) / P;
+        const uint32_t lb = ceil_log2(B);
+        if (lb > 18) return MPHF_OK;   // beyond two passes: use the atomic levels
+        unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
+        HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
+        uint64_t xcap;
+        uint32_t S;
+        uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
+        if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, ovf)) != MPHF_OK) return st;
         // buckets: fill, finalize and filter in LDS
         const int yp = ypar_;
         ypar_ ^= 1;
@@ -900,7 +978,7 @@ mphf_status mphf_build_stream(const mphf_key_stream* src, uint64_t n, double gam
     mphf_opts o;
     if (opts) o = *opts;
     else mphf_default_opts(&o);
-    if (o.flags) return fail(MPHF_E_INVALID, "flags are not supported for streamed builds");
+    if (o.flags & ~MPHF_FLAG_ATOMIC_LEVELS) return fail(MPHF_E_INVALID, "unknown flags");
     return build_stream_impl(src->seed, src->start, n, gamma, seed, o, resident_keys, (hipStream_t)stream, out);
 }
 

@@ -545,6 +545,63 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
     if (threadIdx.x == 0) surv[b] = tot;
 }
 
+// ---------------------------------------------------------------- accumulating a level by chunks
+//
+// Workgroup b owns positions [b << pbits, (b+1) << pbits) of a level held in interleaved A/C words
+// W (word p >> 5: the A bits of 32 positions in bits 0..31, their C bits in 32..63).  It reads the
+// bucket's words into LDS, applies the test-and-set of Algorithm 2 for every key of its regions,
+// and writes the words back.  The final A and C do not depend on the order of the keys, so a
+// level's keys can be added chunk by chunk, each chunk partitioned by bucket first: a level whose
+// keys are never all in memory is filled without global atomics.
+constexpr int AT = 512;
+
+__global__ void __launch_bounds__(AT)
+k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __restrict__ cnt, uint32_t S,
+             LevelHash L, uint32_t pbits, uint64_t* __restrict__ W, uint64_t wwords,
+             unsigned long long* overflow) {
+    extern __shared__ uint32_t acc[];   // A bits [0, nw), C bits [nw, 2 nw)
+    const uint64_t b = blockIdx.x;
+    const uint32_t P = 1u << pbits;
+    const uint32_t nw = P >> 5;
+    uint32_t* Ab = acc;
+    uint32_t* Cb = acc + nw;
+    const uint64_t w0 = b * nw;
+    for (uint32_t j = threadIdx.x; j < nw; j += AT) {
+        const uint64_t v = w0 + j < wwords ? W[w0 + j] : 0;
+        Ab[j] = (uint32_t)v;
+        Cb[j] = (uint32_t)(v >> 32);
+    }
+    __syncthreads();
+    const uint64_t pbase = b << pbits;
+    for (uint32_t q = 0; q < S; ++q) {
+        const uint32_t c = cnt[b * S + q];
+        const uint64_t* src = in + (b * S + q) * in_cap;
+        for (uint32_t i0 = 0; i0 < c; i0 += 4 * AT) {
+            uint64_t h[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = i0 + u * AT + threadIdx.x;
+                h[u] = i < c ? src[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i0 + u * AT + threadIdx.x >= c) continue;
+                const uint64_t p = mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
+                if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
+                    atomicOr(overflow, 8ull);
+                    continue;
+                }
+                const uint32_t bit = 1u << (p & 31);
+                const uint32_t old = atomicOr(&Ab[p >> 5], bit);
+                if (old & bit) atomicOr(&Cb[p >> 5], bit);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nw; j += AT)
+        if (w0 + j < wwords) W[w0 + j] = (uint64_t)Ab[j] | ((uint64_t)Cb[j] << 32);
+}
+
 // ---------------------------------------------------------------- small levels in one workgroup
 //
 // Builds levels d0, d0+1, ... of a set of n <= kcap keys (segments of the partitioned layout or a
@@ -750,6 +807,22 @@ hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cn
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
     hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
                        pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+    return hipGetLastError();
+}
+
+hipError_t accumulate_setup() {
+    // up to 2^18 positions per bucket: 64 KiB of A and C bits
+    return hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+}
+
+hipError_t launch_accumulate(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
+                             uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint64_t* W, uint64_t wwords,
+                             unsigned long long* overflow, hipStream_t s) {
+    if (pbits < 5 || pbits > 18) return hipErrorInvalidValue;
+    if (!nbuckets) return hipSuccess;
+    const size_t lds = (size_t)(1u << pbits) / 4;   // 2 bits per position
+    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)nbuckets), dim3(AT), lds, s, in, in_cap, cnt, S, L, pbits,
+                       W, wwords, overflow);
     return hipGetLastError();
 }
 

@@ -372,11 +372,12 @@ def positions(keys: torch.Tensor, level_seed: int, m: int, stream=None) -> torch
 
 
 def build_stream(n: int, key_seed: int, gamma: float = 2.0, seed: int = 0, resident_keys: int = 1 << 31,
-                 start: int = 0, max_levels: int = 25, rank_sample: int = 512, device=None, stream=None) -> "MPHF":
+                 start: int = 0, max_levels: int = 25, rank_sample: int = 512, atomic_levels: bool = False,
+                 device=None, stream=None) -> "MPHF":
     """Streaming build over keys generated on the fly (mphf_build_stream): key i is output start+i of
     the SplitMix64 stream of key_seed; no more than resident_keys survivors are ever stored."""
     L = lib()
-    o = Opts(max_levels, rank_sample, 0, 0, 0)
+    o = Opts(max_levels, rank_sample, 0, 0, 1 if atomic_levels else 0)
     src = KeyStream(key_seed & (2**64 - 1), start)
     h = C.c_void_p()
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())

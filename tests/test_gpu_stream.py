@@ -24,9 +24,9 @@ def host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-def check(M, n, gamma, resident, key_seed=1, start=0, max_levels=25, rank_sample=512):
+def check(M, n, gamma, resident, key_seed=1, start=0, max_levels=25, rank_sample=512, atomic=False):
     h = M.build_stream(n, key_seed, gamma, 0, resident_keys=resident, start=start, max_levels=max_levels,
-                       rank_sample=rank_sample)
+                       rank_sample=rank_sample, atomic_levels=atomic)
     keys = I.splitmix64(key_seed, n, start=start).numpy().view(np.uint64)
     st = O.build(keys, gamma, 0, max_levels=max_levels, rank_sample=rank_sample)
     s = h.stats()
@@ -60,6 +60,14 @@ def test_streamed_levels_with_a_fallback_table(M):
     # three levels, all streamed: the leftovers are collected from the stream for the fallback table
     check(M, 100_000, 2.0, 0, max_levels=3)
     check(M, 100_000, 1.0, 10, max_levels=2, rank_sample=1024)
+
+
+def test_streamed_levels_in_several_chunks(M):
+    """3e6 keys, every level streamed in chunks of 2^20 stream keys (partitioned and accumulated
+    bucket by bucket), and the same build with global atomics: both equal the oracle."""
+    check(M, 3_000_000, 2.0, 0)
+    check(M, 3_000_000, 2.0, 0, atomic=True)
+    check(M, 1_500_000, 1.0, 100_000, key_seed=4)
 
 
 def test_stream_offset_and_keys(M):
