@@ -82,11 +82,12 @@ def test_partition_sets(M):
 
 
 @pytest.mark.parametrize("n,bits", [(65_536, 9), (300_000, 12), (1_000_003, 15), (500_000, 18),
-                                    (70_000, 16), (2_000_000, 10), (40_000, 12), (3_000_000, 8)])
+                                    (70_000, 16), (2_000_000, 10), (40_000, 12), (3_000_000, 8),
+                                    (200_000, 20)])
 def test_partition_sets_against_host_set_ids(M, n, bits):
     """Every set of the partition holds exactly the keys whose top `bits` bits of fmix64(x ^ seed)
     name it (set ids computed on the host), whichever path the size selects: one or two radix
-    passes for n >= 65536 and bits <= 18, the atomic scatter otherwise."""
+    passes for n >= 65536 and bits <= 18, the atomic scatter otherwise (fewer keys, more sets)."""
     seed = 0x1234_5678_9ABC_DEF1
     keys = I.keys(n, 40 + bits).cuda()
     out, off = M.partition_sets(keys, bits, seed=seed)
