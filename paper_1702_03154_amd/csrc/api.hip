@@ -407,8 +407,9 @@ class Builder {
             uint64_t* X = nullptr;
             uint64_t xcap = 0;
             uint32_t S = 0;
-            if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, ovf)) != MPHF_OK) return st;
-            HIP_TRY(launch_accumulate(X, xcap, ws_->cntX, S, B, L, pb, W, 2 * wd, ovf, s_), "accumulate");
+            bool packed = false;
+            if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, &packed, ovf)) != MPHF_OK) return st;
+            HIP_TRY(launch_accumulate(X, xcap, ws_->cntX, S, B, L, pb, packed, W, 2 * wd, ovf, s_), "accumulate");
             tr_.mark("accumulated chunk", (long)nc);
         }
         if ((st = read_back(dev_ + 129, 8)) != MPHF_OK) return st;
@@ -644,10 +645,11 @@ class Builder {
 
     // The keys of `in` radix-partitioned by bucket of 2^pb positions of a level of m positions
     // (ceil(m / 2^pb) <= 2^18 buckets): one pass, or coarse bins then buckets.  *X gets the
-    // regions (xcap keys each, *S per bucket) with their counts in ws_->cntX; region overflows
-    // and configuration errors are flagged in *ovf.
+    // regions (xcap records each, *S per bucket) with their counts in ws_->cntX; region overflows
+    // and configuration errors are flagged in *ovf.  A record is the level hash h (one pass) or,
+    // *packed, (q << pb) | (pos mod 2^pb) for h = q m + pos (two passes).
     mphf_status partition_buckets(const KeySet& in, const LevelHash& L, uint64_t m, uint32_t pb, uint64_t** X,
-                                  uint64_t* xcap, uint32_t* S, unsigned long long* ovf) {
+                                  uint64_t* xcap, uint32_t* S, bool* packed, unsigned long long* ovf) {
         mphf_status st;
         const uint64_t n = in.n;
         const uint64_t P = 1ull << pb;
@@ -668,6 +670,7 @@ class Builder {
                     "partition");
             *xcap = cap;
             *S = (uint32_t)W;
+            *packed = false;
         } else {
             // two passes: coarse bins of 2^fb buckets, then the buckets of each coarse bin
             const uint32_t fb = lb - 8;
@@ -679,8 +682,11 @@ class Builder {
             if ((st = ensure(&ws_->Z, &ws_->capZ, C * W * cap1 + 16, "partition Z")) != MPHF_OK) return st;
             uint64_t* const Z = line_align(ws_->Z);
             if ((st = ensure(&ws_->cntZ, &ws_->capCntZ, C * W + 1, "counts Z")) != MPHF_OK) return st;
+            // records (q << (pb + fb)) | (pos mod 2^(pb + fb)): B > 1024 buckets make m at least
+            // 2^7 times the coarse bin, so q < 2^64 / m fits above it
             HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
-                                     fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, n, in.nseg, s_),
+                                     fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, n, in.nseg, s_,
+                                     3, nullptr, pb + fb),
                     "partition 1");
             HIP_TRY(launch_zero32(ws_->cntZ + C * W, 1, s_), "zero count tail");
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
@@ -694,10 +700,11 @@ class Builder {
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
                                      (uint32_t)K, L, pb, 0, true, fb, B, *X, cap2, (uint32_t)K,
-                                     ws_->cntX, ovf, n, C * W, s_),
+                                     ws_->cntX, ovf, n, C * W, s_, 4, nullptr, pb + fb),
                     "partition 2");
             *xcap = cap2;
             *S = (uint32_t)K;
+            *packed = true;
         }
         return MPHF_OK;
     }
@@ -724,7 +731,8 @@ class Builder {
         uint64_t xcap;
         uint32_t S;
         uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
-        if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, ovf)) != MPHF_OK) return st;
+        bool packed = false;
+        if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, &packed, ovf)) != MPHF_OK) return st;
         // buckets: fill, finalize and filter in LDS
         const int yp = ypar_;
         ypar_ ^= 1;
@@ -732,7 +740,7 @@ class Builder {
         if ((st = ensure(&ws_->surv[yp], &ws_->capSurv[yp], B + 1, "survivor counts")) != MPHF_OK) return st;
         if ((st = ensure(&ws_->preY[yp], &ws_->capPreY[yp], B + 1, "survivor prefix")) != MPHF_OK) return st;
         uint64_t* C_level = coll_ ? coll_ + off / 64 : nullptr;
-        HIP_TRY(launch_bucket(X, xcap, ws_->cntX, S, B, L, pb, g.kcap, words_ + off / 64, C_level, wd,
+        HIP_TRY(launch_bucket(X, xcap, ws_->cntX, S, B, L, pb, packed, g.kcap, words_ + off / 64, C_level, wd,
                               ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_),
                 "bucket");
         HIP_TRY(launch_zero32(ws_->surv[yp] + B, 1, s_), "zero count tail");

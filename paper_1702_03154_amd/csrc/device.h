@@ -47,6 +47,14 @@ __device__ __forceinline__ uint64_t mod_invariant(uint64_t n, uint64_t m, uint64
     return n - q * m;
 }
 
+// n mod m, with *q = floor(n / m) (the same exact division).
+__device__ __forceinline__ uint64_t divmod_invariant(uint64_t n, uint64_t m, uint64_t magic, uint32_t sh1,
+                                                     uint32_t sh2, uint64_t* q) {
+    const uint64_t t = __umul64hi(magic, n);
+    *q = (t + ((n - t) >> sh1)) >> sh2;
+    return n - *q * m;
+}
+
 __device__ __forceinline__ uint64_t level_pos(uint64_t key, const LevelHash& L) {
     return mod_invariant(fmix64(key ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
 }

@@ -170,7 +170,7 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
                             uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig = 0,
-                            const uint64_t* dbase = nullptr);
+                            const uint64_t* dbase = nullptr, uint32_t pack_shift = 0);
 // Hash-set partition helpers: keys per (set, workgroup) over the slices of a partition pass, every
 // K-th entry of their prefix (the set offsets), and a two-word device write.
 hipError_t launch_slice_counts(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t groups,
@@ -182,10 +182,10 @@ hipError_t launch_pair(uint64_t* p, uint64_t a, uint64_t b, hipStream_t s);
 // words W of a level, one workgroup per bucket (accumulate_setup once per device first).
 hipError_t accumulate_setup();
 hipError_t launch_accumulate(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
-                             uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint64_t* W, uint64_t wwords,
-                             unsigned long long* overflow, hipStream_t s);
+                             uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint64_t* W,
+                             uint64_t wwords, unsigned long long* overflow, hipStream_t s);
 hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
-                         uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint32_t kcap,
+                         uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint32_t kcap,
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s);
 hipError_t launch_gather(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,

@@ -74,6 +74,13 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // SPAN = true (inputs of small segments) a tile is a dense range across up to TSEG segments, each
 // key found in the segment boundaries staged in LDS.
 //
+// DIG = 3 (first of two passes) writes, instead of h, the packed record (q << pack_shift) |
+// (pos mod 2^pack_shift) where h = q m + pos: with pack_shift = the coarse bin's bits the record
+// keeps everything the later passes need (q < 2^64 / m fits above them, the bin is the region) and
+// spares them the division.  DIG = 4 (second pass) reads such records and writes
+// (q << pbits) | (pos mod 2^pbits) for the bucket pass; h = q m + pos is recovered there for the
+// keys that survive.
+//
 // DIG = 1 or 2 partitions by the top bits of h instead of its level position: pos = h >> L.sh1
 // (the hash-set partition of a key set into 2^(64 - sh1) independent sets).  DIG = 2 writes the
 // keys themselves (not their hashes) densely: bin d of this workgroup starts at dbase[(bin_base +
@@ -107,20 +114,37 @@ struct PartLds {
 template <int NB, bool WC, bool HASHED, int DIG>
 __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t (&k)[PITEMS], uint32_t tn,
                                           const LevelHash& L, uint32_t pbits, uint32_t out_shift,
-                                          uint64_t bin_base, uint64_t lim, uint64_t* __restrict__ obase,
-                                          uint64_t ostride, uint64_t out_cap,
+                                          uint32_t pack_shift, uint64_t bin_base, uint64_t lim,
+                                          uint64_t* __restrict__ obase, uint64_t ostride, uint64_t out_cap,
                                           unsigned long long* overflow) {
     uint32_t dg[PITEMS], rk[PITEMS];
 #pragma unroll
     for (int it = 0; it < PITEMS; ++it) {
         const uint32_t j = it * PT + threadIdx.x;
-        const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
-        const uint64_t pos = DIG ? h >> L.sh1 : mod_invariant(h, L.m, L.magic, L.sh1, L.sh2);
-        const uint64_t bin = (pos >> pbits) >> out_shift;
-        if (DIG == 2) {   // dense output holds the keys
-            if (HASHED) k[it] = unfmix64(h) ^ L.seed;
+        uint64_t bin;
+        if constexpr (DIG == 4) {
+            // packed input (q << pack_shift) | position inside the coarse bin bin_base >> ...:
+            // the bucket is known without a division; the output keeps q and the position inside
+            // the bucket
+            const uint64_t local = k[it] & ((1ull << pack_shift) - 1);
+            bin = bin_base + (local >> pbits);
+            k[it] = ((k[it] >> pack_shift) << pbits) | (local & ((1ull << pbits) - 1));
+        } else if constexpr (DIG == 3) {
+            // level position of h = q * m + pos, written as (q << pack_shift) | (pos mod 2^pack_shift)
+            const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
+            uint64_t q;
+            const uint64_t pos = divmod_invariant(h, L.m, L.magic, L.sh1, L.sh2, &q);
+            bin = (pos >> pbits) >> out_shift;
+            k[it] = (q << pack_shift) | (pos & ((1ull << pack_shift) - 1));
         } else {
-            k[it] = h;
+            const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
+            const uint64_t pos = DIG ? h >> L.sh1 : mod_invariant(h, L.m, L.magic, L.sh1, L.sh2);
+            bin = (pos >> pbits) >> out_shift;
+            if (DIG == 2) {   // dense output holds the keys
+                if (HASHED) k[it] = unfmix64(h) ^ L.seed;
+            } else {
+                k[it] = h;
+            }
         }
         dg[it] = NB;
         if (j < tn) {
@@ -241,10 +265,11 @@ __device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t*
     }
 }
 
+// (at least 4 waves per SIMD: two workgroups per compute unit, as the LDS allows)
 template <int DBITS, bool HASHED, bool SPAN, int DIG>
-__global__ void __launch_bounds__(PT)
+__global__ void __launch_bounds__(PT, 4)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
-            uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift,
+            uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift, uint32_t pack_shift,
             uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
             uint64_t out_cap, uint32_t S_out, uint32_t* __restrict__ out_cnt,
             unsigned long long* overflow, const uint64_t* __restrict__ dbase) {
@@ -315,7 +340,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                 te1 = tile_end(t1);
                 load_tile(kn, in + (uint64_t)s * in_stride + (t1 - sb), (uint32_t)(te1 - t1));
             }
-            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
+            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase, ostride,
                                       out_cap, overflow);
             t0 = t1;
             te = te1;
@@ -354,7 +379,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                     k[it] = in[(uint64_t)(s + qi) * in_stride + (i - S.sp[qi])];
                 }
             }
-            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, bin_base, lim, obase, ostride,
+            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase, ostride,
                                       out_cap, overflow);
             t0 = te;
         }
@@ -434,13 +459,15 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t S, uint
 
 // ---------------------------------------------------------------- bucket pass
 //
-// Workgroup b owns positions [b << pbits, (b+1) << pbits) of level d.  It reads the level hashes
-// of the bucket's keys (regions b*S .. b*S+S-1) once into registers, writes their positions
-// inside the bucket to LDS, fills A and C there with LDS atomics, writes the finalized A words of
-// its positions, and writes the keys whose A bit is 0 (F_{d+1}, recovered from their hashes) into
-// output region b of capacity ycap, with their number in surv[b].
+// Workgroup b owns positions [b << pbits, (b+1) << pbits) of level d.  It reads the records of
+// the bucket's keys (regions b*S .. b*S+S-1) once into registers, writes their positions inside
+// the bucket to LDS, fills A and C there with LDS atomics, writes the finalized A words of its
+// positions, and writes the keys whose A bit is 0 (F_{d+1}, recovered from their hashes) into
+// output region b of capacity ycap, with their number in surv[b].  A record is the level hash h,
+// or with PACKED the pair (q << pbits) | (pos mod 2^pbits) of h = q m + pos.
 constexpr int BI = 36;   // hashes held per thread: KT * BI >= the largest kcap
 
+template <bool PACKED>
 __global__ void __launch_bounds__(KT)
 k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __restrict__ cnt,
          uint32_t S, LevelHash L, uint32_t pbits, uint32_t kcap, uint64_t* __restrict__ A,
@@ -493,13 +520,20 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
     for (int it = 0; it < BI; ++it) {
         const uint32_t i = it * KT + threadIdx.x;
         if (i < nb) {
-            const uint64_t p = mod_invariant(h[it], L.m, L.magic, L.sh1, L.sh2) - pbase;
-            if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
-                atomicOr(overflow, 8ull);
-                lps[i] = 0;
-                continue;
+            uint64_t p;
+            if (PACKED) {   // the position inside the bucket; the hash q m + pos kept for survivors
+                p = h[it] & (P - 1);
+                lps[i] = (uint16_t)p;
+                h[it] = (h[it] >> pbits) * L.m + pbase + p;
+            } else {
+                p = mod_invariant(h[it], L.m, L.magic, L.sh1, L.sh2) - pbase;
+                if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
+                    atomicOr(overflow, 8ull);
+                    lps[i] = 0;
+                    continue;
+                }
+                lps[i] = (uint16_t)p;
             }
-            lps[i] = (uint16_t)p;
             const uint32_t bit = 1u << (p & 31);
             const uint32_t old = atomicOr(&Abits[p >> 5], bit);
             if (old & bit) atomicOr(&Cbits[p >> 5], bit);
@@ -555,6 +589,7 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
 // keys are never all in memory is filled without global atomics.
 constexpr int AT = 512;
 
+template <bool PACKED>
 __global__ void __launch_bounds__(AT)
 k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __restrict__ cnt, uint32_t S,
              LevelHash L, uint32_t pbits, uint64_t* __restrict__ W, uint64_t wwords,
@@ -586,7 +621,7 @@ k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* _
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (i0 + u * AT + threadIdx.x >= c) continue;
-                const uint64_t p = mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
+                const uint64_t p = PACKED ? h[u] & (P - 1) : mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
                 if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
                     atomicOr(overflow, 8ull);
                     continue;
@@ -768,14 +803,16 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             const LevelHash& L, uint32_t pbits, uint32_t out_shift, bool grouped,
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
-                            uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig, const uint64_t* dbase) {
+                            uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig, const uint64_t* dbase,
+                            uint32_t pack_shift) {
     const dim3 grid(groups * K);
     const uint32_t gr = grouped ? 1u : 0u;
     // segments averaging under half a tile: tiles span segments
     const bool span = nseg_in > 0 && n_in / nseg_in < (uint64_t)(PTILE / 2);
 #define MPHF_PART(DB, HS, SP, DG)                                                                     \
     hipLaunchKernelGGL((k_partition<DB, HS, SP, DG>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
-                       pbits, out_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt, overflow, dbase)
+                       pbits, out_shift, pack_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt,  \
+                       overflow, dbase)
     if (dig == 1) {
         // regions by the top bits: the first pass over a dense key array
         if (hashed || dbits > 8 || span) return hipErrorInvalidValue;
@@ -790,11 +827,19 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
         } else {
             if (span) MPHF_PART(10, true, true, 2); else MPHF_PART(10, true, false, 2);
         }
-    } else if (dbits <= 8) {
-        if (hashed) { if (span) MPHF_PART(8, true, true, 0); else MPHF_PART(8, true, false, 0); }
-        else { if (span) MPHF_PART(8, false, true, 0); else MPHF_PART(8, false, false, 0); }
+    } else if (dig == 3) {
+        // packed records: the first of two passes over keys
+        if (hashed || dbits > 8 || pack_shift > 56) return hipErrorInvalidValue;
+        if (span) MPHF_PART(8, false, true, 3); else MPHF_PART(8, false, false, 3);
+    } else if (dig == 4) {
+        // packed records in and out: the second pass
+        if (!hashed || pack_shift > 56 || pack_shift < pbits) return hipErrorInvalidValue;
+        if (dbits <= 8) { if (span) MPHF_PART(8, true, true, 4); else MPHF_PART(8, true, false, 4); }
+        else { if (span) MPHF_PART(10, true, true, 4); else MPHF_PART(10, true, false, 4); }
     } else {
-        if (hashed) { if (span) MPHF_PART(10, true, true, 0); else MPHF_PART(10, true, false, 0); }
+        // level hashes: one pass over keys
+        if (hashed) return hipErrorInvalidValue;
+        if (dbits <= 8) { if (span) MPHF_PART(8, false, true, 0); else MPHF_PART(8, false, false, 0); }
         else { if (span) MPHF_PART(10, false, true, 0); else MPHF_PART(10, false, false, 0); }
     }
 #undef MPHF_PART
@@ -802,27 +847,38 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
 }
 
 hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
-                         uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint32_t kcap,
+                         uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint32_t kcap,
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
-    hipLaunchKernelGGL(k_bucket, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
-                       pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+    if (packed)
+        hipLaunchKernelGGL(k_bucket<true>, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
+                           pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+    else
+        hipLaunchKernelGGL(k_bucket<false>, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
+                           pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
     return hipGetLastError();
 }
 
 hipError_t accumulate_setup() {
     // up to 2^18 positions per bucket: 64 KiB of A and C bits
-    return hipFuncSetAttribute((const void*)k_accumulate, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+    hipError_t e = hipFuncSetAttribute((const void*)k_accumulate<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       65536);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_accumulate<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
 }
 
 hipError_t launch_accumulate(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
-                             uint64_t nbuckets, const LevelHash& L, uint32_t pbits, uint64_t* W, uint64_t wwords,
-                             unsigned long long* overflow, hipStream_t s) {
+                             uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint64_t* W,
+                             uint64_t wwords, unsigned long long* overflow, hipStream_t s) {
     if (pbits < 5 || pbits > 18) return hipErrorInvalidValue;
     if (!nbuckets) return hipSuccess;
     const size_t lds = (size_t)(1u << pbits) / 4;   // 2 bits per position
-    hipLaunchKernelGGL(k_accumulate, dim3((unsigned)nbuckets), dim3(AT), lds, s, in, in_cap, cnt, S, L, pbits,
-                       W, wwords, overflow);
+    if (packed)
+        hipLaunchKernelGGL(k_accumulate<true>, dim3((unsigned)nbuckets), dim3(AT), lds, s, in, in_cap, cnt, S, L,
+                           pbits, W, wwords, overflow);
+    else
+        hipLaunchKernelGGL(k_accumulate<false>, dim3((unsigned)nbuckets), dim3(AT), lds, s, in, in_cap, cnt, S, L,
+                           pbits, W, wwords, overflow);
     return hipGetLastError();
 }
 
