@@ -9,9 +9,10 @@
 // same as with any other order of insertion, because a bit of A_d survives iff exactly one key
 // of F_d lands on it.
 //
-// The partition passes and the bucket pass carry h_d(x) = fmix64(x ^ s_d) instead of the key x:
-// the position is h_d(x) mod m_d, and the bucket pass gets x back for the survivors with the
-// exact inverse of fmix64, so every record stays 8 bytes.
+// The partition passes and the bucket pass carry, instead of the key x, the level hash
+// h = fmix64(x ^ s_d) (one pass) or the pair (q, pos) with h = q m_d + pos (two passes, packed into
+// 8 bytes below): the bucket pass gets h and then x back for the survivors with the exact inverse
+// of fmix64, so every record stays 8 bytes and only the first pass divides by m_d.
 //
 // Data layout of a partitioned set: "regions" of fixed capacity `cap` keys, region r starting at
 // base + r * cap, with its key count in cnt[r] (counts above cap mean the region overflowed and
@@ -58,8 +59,9 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // the first, so its keys fall in bins (group << group_shift) + [0, 2^group_shift); otherwise
 // the bins start at 0.  Either way a workgroup sees at most 2^DBITS bins, and a key outside the
 // bins its group owns is a configuration error (flag 4), never written.  The input holds keys
-// (HASHED = false: h = fmix64(x ^ s_d) is computed here) or already their level hashes; the
-// output always holds the level hashes.
+// (HASHED = false: h = fmix64(x ^ s_d) is computed here) or the records of an earlier pass
+// (HASHED = true); DIG says what the bins and the output records are: DIG = 0 bins by level
+// position and writes h.
 //
 // A tile is counting-sorted by bin in LDS.  With 2^8 bins (WC) a workgroup also keeps, per bin,
 // the keys of its last unfinished 16-key line in LDS, and a tile writes only whole lines: a
@@ -110,7 +112,8 @@ struct PartLds {
 };
 
 // One tile of tn keys.  k[] holds a value for every item (items j >= tn hold copies and are
-// ignored); every value is hashed, so that the tile's loads are consumed on every path.
+// ignored); every value goes through the digit computation, so that the tile's loads are
+// consumed on every path.
 template <int NB, bool WC, bool HASHED, int DIG>
 __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t (&k)[PITEMS], uint32_t tn,
                                           const LevelHash& L, uint32_t pbits, uint32_t out_shift,
@@ -123,9 +126,9 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         const uint32_t j = it * PT + threadIdx.x;
         uint64_t bin;
         if constexpr (DIG == 4) {
-            // packed input (q << pack_shift) | position inside the coarse bin bin_base >> ...:
-            // the bucket is known without a division; the output keeps q and the position inside
-            // the bucket
+            // packed input (q << pack_shift) | (position inside the group's coarse bin): the
+            // bucket is known without a division; the output keeps q and the position inside the
+            // bucket
             const uint64_t local = k[it] & ((1ull << pack_shift) - 1);
             bin = bin_base + (local >> pbits);
             k[it] = ((k[it] >> pack_shift) << pbits) | (local & ((1ull << pbits) - 1));
