@@ -165,10 +165,11 @@ typedef struct mphf_key_stream {
 
 /* Build over the n keys of `src`.  While more than resident_keys keys are left, a level re-generates
  * every key and skips those placed at an earlier level (a lookup walk over the finished levels):
- * the re-scan strategy of Section 3.4, which stores no F_d.  The others are taken in chunks of
- * max(resident_keys, 2^20) stream keys: each chunk's are collected, radix-partitioned by position
- * bucket and added to the level's A and C bits bucket by bucket in LDS.  Levels beyond 2^36
- * positions, or flags = MPHF_FLAG_ATOMIC_LEVELS, mark the keys with global test-and-set instead.
+ * the re-scan strategy of Section 3.4, which stores no F_d.  The stream is taken in chunks of
+ * max(resident_keys, 2^20) keys: a chunk's keys are radix-partitioned by bucket of each finished
+ * level and tested against its bits in LDS, and the unplaced ones partitioned by bucket of the
+ * current level and added to its A and C bits in LDS.  Levels beyond 2^36 positions, or flags =
+ * MPHF_FLAG_ATOMIC_LEVELS, walk by random reads and mark with global test-and-set instead.
  * Then the survivors are collected (8 bytes each) and the build continues in memory.  The
  * function, its levels and labels equal those of mphf_build_ex on the materialized keys.  Device
  * memory: the structure, 2 gamma n bits for the first level's A and C, the survivors and, for a

@@ -315,9 +315,9 @@ class Builder {
         uint64_t* W = nullptr;
         uint32_t d = 0;
         uint64_t off = 0, nd = n;
-        const BucketGeometry geo = bucket_geometry(gamma_);
-        uint64_t* chunk = nullptr;   // the unplaced keys of one chunk of the stream
+        uint64_t* chunk = nullptr;   // the keys of one chunk of the stream
         uint64_t* pre0 = nullptr;
+        bool walkable = true;        // every finished level has a bucket geometry (no atomic fill)
         while (nd > 0 && d < D && nd > budget) {
             const uint64_t m = level_size(gamma_, nd);
             const uint64_t wd = (m + 63) / 64;
@@ -328,15 +328,15 @@ class Builder {
             // Buckets of 2^pb positions, at most 2^18 of them, so that each chunk takes two radix
             // passes at most; a level beyond 2^36 positions, or the atomic-only option, takes
             // global atomics over the whole stream instead.
-            uint32_t pb = geo.pbits ? geo.pbits : 15;
-            while (pb < 18 && ceil_log2((m + (1ull << pb) - 1) >> pb) > 18) ++pb;
+            const uint32_t pb = stream_bucket_bits(m);
             bool accumulated = false;
-            if (!(o_.flags & MPHF_FLAG_ATOMIC_LEVELS) && ceil_log2((m + (1ull << pb) - 1) >> pb) <= 18) {
+            if (!(o_.flags & MPHF_FLAG_ATOMIC_LEVELS) && pb && walkable) {
                 if ((st = accumulate_stream_level(kseed, kstart, n, lev, d, L, m, pb, budget, W, wd, &chunk, &pre0,
                                                   &accumulated)) != MPHF_OK)
                     return st;
             }
             if (!accumulated) {
+                walkable = false;   // the later scans walk by random reads too
                 HIP_TRY(launch_zero(W, 2 * wd, s_), "zero W");
                 HIP_TRY(launch_stream_fill(kseed, kstart, n, lev, d, words_, W, L, s_), "stream fill");
             }
@@ -357,8 +357,8 @@ class Builder {
             tr_.mark("streamed level", (long)(d - 1));
         }
         if (W) ar_.release(W);
-        if (chunk) ar_.release(chunk);
         if (!nd) {
+            if (chunk) ar_.release(chunk);
             h_->total_words = h_->total_bits / 64;
             return finish();
         }
@@ -366,11 +366,94 @@ class Builder {
         uint64_t* dense = nullptr;
         if ((st = ar_.alloc(&dense, nd, "streamed survivors")) != MPHF_OK) return st;
         tr_.mark("collect alloc", (long)nd);
-        HIP_TRY(launch_stream_collect(kseed, kstart, n, lev, d, words_, dense, nd, counters + 200, s_), "collect");
-        if ((st = read_back(counters + 200, 8)) != MPHF_OK) return st;
-        if (host_[0] != nd) return fail(MPHF_E_DEVICE, "collected survivors differ from the level counts");
+        bool collected = false;
+        if (chunk && walkable && !(o_.flags & MPHF_FLAG_ATOMIC_LEVELS)) {
+            // chunk by chunk, the levels walked by bucket
+            unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
+            HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
+            const uint64_t ch = std::min<uint64_t>(n, std::max<uint64_t>(budget, 1ull << 20));
+            uint64_t got = 0;
+            bool fits = true;
+            for (uint64_t c0 = 0; c0 < n && fits; c0 += ch) {
+                const uint64_t c = std::min<uint64_t>(ch, n - c0);
+                KeySet in;
+                if ((st = stream_unplaced(kseed, kstart, c0, c, d, chunk, pre0, &in, ovf)) != MPHF_OK) return st;
+                if (got + in.n > nd) {
+                    fits = false;
+                    break;
+                }
+                if (in.n) HIP_TRY(launch_gather(in.base, in.stride, in.pre, in.nseg, in.n, dense + got, s_), "gather");
+                got += in.n;
+            }
+            if ((st = read_back(dev_ + 129, 8)) != MPHF_OK) return st;
+            collected = fits && host_[0] == 0 && got == nd;
+        }
+        if (!collected) {
+            HIP_TRY(launch_zero(dev_ + 200, 1, s_), "zero count");
+            HIP_TRY(launch_stream_collect(kseed, kstart, n, lev, d, words_, dense, nd, counters + 200, s_),
+                    "collect");
+            if ((st = read_back(counters + 200, 8)) != MPHF_OK) return st;
+            if (host_[0] != nd) return fail(MPHF_E_DEVICE, "collected survivors differ from the level counts");
+        }
+        if (chunk) ar_.release(chunk);
         tr_.mark("collect", (long)nd);
         return levels_and_finish(dense, nd, d, off);
+    }
+
+    // Bucket bits for a level of m positions: the bucket geometry's, raised until two radix passes
+    // reach every bucket (at most 2^18 buckets); 0 if no bucket of at most 2^18 positions does.
+    uint32_t stream_bucket_bits(uint64_t m) const {
+        const BucketGeometry geo = bucket_geometry(gamma_);
+        uint32_t pb = geo.pbits ? geo.pbits : 15;
+        while (pb < 18 && ceil_log2((m + (1ull << pb) - 1) >> pb) > 18) ++pb;
+        return ceil_log2((m + (1ull << pb) - 1) >> pb) <= 18 ? pb : 0;
+    }
+
+    // The keys of stream chunk [c0, c0 + c) that no finished level 0..d-1 placed (the walk of
+    // Algorithm 3 over those levels), found by bucket: the chunk is generated into `chunk`, and for
+    // each finished level j its keys are partitioned by bucket of level j and tested against A_j
+    // in LDS (k_bucket_test).  *out gets them as the regions of ws_->Y[0] with prefix ws_->preY[0].
+    // Region overflows (adversarial streams only) are flagged in *ovf.
+    mphf_status stream_unplaced(uint64_t kseed, uint64_t kstart, uint64_t c0, uint64_t c, uint32_t d,
+                                uint64_t* chunk, uint64_t* pre0, KeySet* out, unsigned long long* ovf) {
+        mphf_status st;
+        HIP_TRY(launch_stream_keys(kseed, kstart + c0, c, chunk, s_), "chunk keys");
+        HIP_TRY(launch_pair(pre0, 0, c, s_), "chunk prefix");
+        KeySet cur;
+        cur.base = chunk;
+        cur.pre = pre0;
+        cur.nseg = 1;
+        cur.n = c;
+        for (uint32_t j = 0; j < d && cur.n > 0; ++j) {
+            const uint64_t m = h_->level_m[j];
+            const uint32_t pb = stream_bucket_bits(m);
+            if (!pb || pb < 6) return fail(MPHF_E_INVALID, "no bucket geometry for a streamed level");
+            const LevelHash L = make_level_hash(seeds_.s[j], m, h_->level_offset[j]);
+            uint64_t* X = nullptr;
+            uint64_t xcap = 0;
+            uint32_t S = 0;
+            bool packed = false;
+            if ((st = partition_buckets(cur, L, m, pb, &X, &xcap, &S, &packed, ovf)) != MPHF_OK) return st;
+            const uint64_t B = (m + (1ull << pb) - 1) >> pb;
+            const uint64_t ycap = (uint64_t)S * xcap;   // a bucket keeps at most its records
+            if ((st = ensure(&ws_->Y[0], &ws_->capY[0], B * ycap, "unplaced keys")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->surv[0], &ws_->capSurv[0], B + 1, "unplaced counts")) != MPHF_OK) return st;
+            if ((st = ensure(&ws_->preY[0], &ws_->capPreY[0], B + 1, "unplaced prefix")) != MPHF_OK) return st;
+            HIP_TRY(launch_bucket_test(X, xcap, ws_->cntX, S, B, L, pb, packed, words_, h_->level_offset[j],
+                                       (m + 63) / 64, ws_->Y[0], ycap, ws_->surv[0], ovf, s_),
+                    "bucket test");
+            HIP_TRY(launch_zero32(ws_->surv[0] + B, 1, s_), "zero count tail");
+            if ((st = prefix(ws_->surv[0], B, ws_->preY[0])) != MPHF_OK) return st;
+            if ((st = read_back(ws_->preY[0] + B, 8)) != MPHF_OK) return st;
+            cur.base = ws_->Y[0];
+            cur.stride = ycap;
+            cur.pre = ws_->preY[0];
+            cur.nseg = (uint32_t)B;
+            cur.n = host_[0];
+            if (cur.n > c) return fail(MPHF_E_DEVICE, "more unplaced keys than the chunk holds");
+        }
+        *out = cur;
+        return MPHF_OK;
     }
 
     // Level d of a generated stream added to W chunk by chunk: the unplaced keys of up to `budget`
@@ -386,24 +469,16 @@ class Builder {
         if (!*chunk && (st = ar_.alloc(chunk, ch, "stream chunk")) != MPHF_OK) return st;
         if (!*pre0 && (st = ar_.alloc(pre0, 2, "chunk prefix")) != MPHF_OK) return st;
         HIP_TRY(accumulate_setup(), "accumulate setup");
+        HIP_TRY(bucket_test_setup(), "bucket test setup");
         unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
-        unsigned long long* cnt = (unsigned long long*)(dev_ + 300);
         HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
         const uint64_t B = (m + (1ull << pb) - 1) >> pb;
         for (uint64_t c0 = 0; c0 < n; c0 += ch) {
             const uint64_t c = std::min<uint64_t>(ch, n - c0);
-            HIP_TRY(launch_zero(dev_ + 300, 1, s_), "zero count");
-            HIP_TRY(launch_stream_collect(kseed, kstart + c0, c, lev, d, words_, *chunk, ch, cnt, s_), "collect");
-            if ((st = read_back(dev_ + 300, 8)) != MPHF_OK) return st;
-            const uint64_t nc = host_[0];
-            if (nc > c) return fail(MPHF_E_DEVICE, "collected more keys than the chunk holds");
-            if (!nc) continue;
-            HIP_TRY(launch_pair(*pre0, 0, nc, s_), "chunk prefix");
             KeySet in;
-            in.base = *chunk;
-            in.pre = *pre0;
-            in.nseg = 1;
-            in.n = nc;
+            if ((st = stream_unplaced(kseed, kstart, c0, c, d, *chunk, *pre0, &in, ovf)) != MPHF_OK) return st;
+            const uint64_t nc = in.n;
+            if (!nc) continue;
             uint64_t* X = nullptr;
             uint64_t xcap = 0;
             uint32_t S = 0;

@@ -178,6 +178,14 @@ hipError_t launch_slice_counts(const uint64_t* in, uint64_t in_stride, const uin
                                uint32_t group_shift, uint64_t nbins, uint32_t* cnt, hipStream_t s);
 hipError_t launch_take_every(const uint64_t* base, uint32_t K, uint64_t nsets, uint64_t* offsets, hipStream_t s);
 hipError_t launch_pair(uint64_t* p, uint64_t a, uint64_t b, hipStream_t s);
+// Keys partitioned by bucket of 2^pbits positions (6 <= pbits <= 18) tested against the finished
+// level whose A starts at bit `off` of words (level_words words): the keys whose bit is 0 go to
+// region b of Y (ycap keys each), their number to surv[b] (bucket_test_setup once per device first).
+hipError_t bucket_test_setup();
+hipError_t launch_bucket_test(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
+                              uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed,
+                              const uint64_t* words, uint64_t off, uint64_t level_words, uint64_t* Y, uint64_t ycap,
+                              uint32_t* surv, unsigned long long* overflow, hipStream_t s);
 // Keys partitioned by bucket of 2^pbits positions (5 <= pbits <= 18) added to the interleaved A/C
 // words W of a level, one workgroup per bucket (accumulate_setup once per device first).
 hipError_t accumulate_setup();

@@ -640,6 +640,80 @@ k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* _
         if (w0 + j < wwords) W[w0 + j] = (uint64_t)Ab[j] | ((uint64_t)Cb[j] << 32);
 }
 
+// ---------------------------------------------------------------- testing keys against a finished level
+//
+// The walk over finished levels (Algorithm 3's loop, used by the streaming build to skip keys
+// placed earlier) done by bucket instead of by random reads: workgroup b reads the 2^pbits A bits
+// of its positions of finished level d (A_d at bit offset `off` of words) into LDS once, tests
+// every key of its regions, and writes the keys whose bit is 0 (not placed at d) into output
+// region b (capacity ycap) with their number in surv[b].  Records as in k_bucket.
+constexpr int TT = 512;
+
+template <bool PACKED>
+__global__ void __launch_bounds__(TT)
+k_bucket_test(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __restrict__ cnt, uint32_t S,
+              LevelHash L, uint32_t pbits, const uint64_t* __restrict__ words, uint64_t off, uint64_t level_words,
+              uint64_t* __restrict__ Y, uint64_t ycap, uint32_t* __restrict__ surv,
+              unsigned long long* overflow) {
+    extern __shared__ uint32_t abits[];   // 2^pbits bits of A_d
+    __shared__ uint32_t wsum[TT / 64 + 1];
+    const uint64_t b = blockIdx.x;
+    const uint32_t P = 1u << pbits;
+    const uint64_t w0 = (off >> 6) + (b << (pbits - 6));   // off and b * 2^pbits are multiples of 64
+    const uint64_t wend = (off >> 6) + level_words;
+    for (uint32_t j = threadIdx.x; j < (P >> 6); j += TT) {
+        const uint64_t w = w0 + j < wend ? words[w0 + j] : 0;
+        abits[2 * j] = (uint32_t)w;
+        abits[2 * j + 1] = (uint32_t)(w >> 32);
+    }
+    __syncthreads();
+    const uint64_t pbase = b << pbits;
+    uint64_t* dst = Y + b * ycap;
+    uint32_t o = 0;   // survivors written so far (uniform)
+    bool full = false;
+    for (uint32_t q = 0; q < S && !full; ++q) {
+        const uint32_t c = cnt[b * S + q];
+        const uint64_t* src = in + (b * S + q) * in_cap;
+        for (uint32_t i0 = 0; i0 < c; i0 += 4 * TT) {
+            uint64_t h[4];
+            uint32_t keep = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t i = i0 + u * TT + threadIdx.x;
+                h[u] = i < c ? src[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i0 + u * TT + threadIdx.x >= c) continue;
+                uint64_t p;
+                if (PACKED) {
+                    p = h[u] & (P - 1);
+                    h[u] = (h[u] >> pbits) * L.m + pbase + p;
+                } else {
+                    p = mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
+                    if (p >= P) {   // not this bucket's key: the partition was wrong
+                        atomicOr(overflow, 8ull);
+                        continue;
+                    }
+                }
+                if (!((abits[p >> 5] >> (p & 31)) & 1u)) keep |= 1u << u;
+            }
+            uint32_t tot;
+            uint32_t e = block_exclusive_sum<TT>((uint32_t)__popc(keep), wsum, &tot);
+            if (o + tot > ycap) {   // cannot happen: survivors are at most the bucket's records
+                if (threadIdx.x == 0) atomicOr(overflow, 2ull);
+                full = true;   // uniform: the count below stays within the region
+                break;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if ((keep >> u) & 1u) dst[o + e++] = unfmix64(h[u]) ^ L.seed;
+            o += tot;
+        }
+    }
+    if (threadIdx.x == 0) surv[b] = o;
+}
+
 // ---------------------------------------------------------------- small levels in one workgroup
 //
 // Builds levels d0, d0+1, ... of a set of n <= kcap keys (segments of the partitioned layout or a
@@ -882,6 +956,29 @@ hipError_t launch_accumulate(const uint64_t* in, uint64_t in_cap, const uint32_t
     else
         hipLaunchKernelGGL(k_accumulate<false>, dim3((unsigned)nbuckets), dim3(AT), lds, s, in, in_cap, cnt, S, L,
                            pbits, W, wwords, overflow);
+    return hipGetLastError();
+}
+
+hipError_t bucket_test_setup() {
+    hipError_t e = hipFuncSetAttribute((const void*)k_bucket_test<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       32768);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_bucket_test<true>, hipFuncAttributeMaxDynamicSharedMemorySize, 32768);
+}
+
+hipError_t launch_bucket_test(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
+                              uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed,
+                              const uint64_t* words, uint64_t off, uint64_t level_words, uint64_t* Y, uint64_t ycap,
+                              uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
+    if (pbits < 6 || pbits > 18 || (off & 63)) return hipErrorInvalidValue;
+    if (!nbuckets) return hipSuccess;
+    const size_t lds = (size_t)(1u << pbits) / 8;
+    if (packed)
+        hipLaunchKernelGGL(k_bucket_test<true>, dim3((unsigned)nbuckets), dim3(TT), lds, s, in, in_cap, cnt, S, L,
+                           pbits, words, off, level_words, Y, ycap, surv, overflow);
+    else
+        hipLaunchKernelGGL(k_bucket_test<false>, dim3((unsigned)nbuckets), dim3(TT), lds, s, in, in_cap, cnt, S, L,
+                           pbits, words, off, level_words, Y, ycap, surv, overflow);
     return hipGetLastError();
 }
 
