@@ -331,7 +331,7 @@ class Builder {
             const uint32_t pb = stream_bucket_bits(m);
             bool accumulated = false;
             if (!(o_.flags & MPHF_FLAG_ATOMIC_LEVELS) && pb && walkable) {
-                if ((st = accumulate_stream_level(kseed, kstart, n, lev, d, L, m, pb, budget, W, wd, &chunk, &pre0,
+                if ((st = accumulate_stream_level(kseed, kstart, n, d, L, m, pb, budget, W, wd, &chunk, &pre0,
                                                   &accumulated)) != MPHF_OK)
                     return st;
             }
@@ -460,7 +460,7 @@ class Builder {
     // stream keys at a time are collected, partitioned by bucket of 2^pb positions and accumulated
     // (no global atomics).  *done = false if a region overflowed (adversarial streams only): W is
     // then partial and the caller fills the level with global atomics.
-    mphf_status accumulate_stream_level(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
+    mphf_status accumulate_stream_level(uint64_t kseed, uint64_t kstart, uint64_t n, uint32_t d,
                                         const LevelHash& L, uint64_t m, uint32_t pb, uint64_t budget, uint64_t* W,
                                         uint64_t wd, uint64_t** chunk, uint64_t** pre0, bool* done) {
         mphf_status st;
