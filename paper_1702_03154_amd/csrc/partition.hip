@@ -35,7 +35,7 @@ constexpr int PITEMS = 8;             // keys per thread per tile
 constexpr int PTILE = PT * PITEMS;    // keys per tile
 constexpr int TSEG = 64;              // input segments one tile may span
 constexpr int BT = 1024;              // threads of the tail kernel
-constexpr int KT = 512;               // threads of the bucket kernel
+constexpr int KT = 1024;              // threads of the bucket kernel
 constexpr int POOL_WORDS = 19712;     // 154 KiB of LDS for the tail kernel's keys and bits
 constexpr int BUCKET_LDS = 49152;     // bytes of LDS for a bucket's local positions and bits
 
@@ -468,7 +468,9 @@ __device__ __forceinline__ uint32_t seg_of(const uint32_t* off, uint32_t S, uint
 // positions, and writes the keys whose A bit is 0 (F_{d+1}, recovered from their hashes) into
 // output region b of capacity ycap, with their number in surv[b].  A record is the level hash h,
 // or with PACKED the pair (q << pbits) | (pos mod 2^pbits) of h = q m + pos.
-constexpr int BI = 36;   // hashes held per thread: KT * BI >= the largest kcap
+// 1024 threads holding 18 records each: at 62 VGPRs two workgroups fill a CU with 8 waves per SIMD
+// (512 threads with 36 records each needed 91 VGPRs and ran 4 waves per SIMD).
+constexpr int BI = 18;   // hashes held per thread: KT * BI >= the largest kcap
 
 template <bool PACKED>
 __global__ void __launch_bounds__(KT)
