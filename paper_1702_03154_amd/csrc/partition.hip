@@ -121,6 +121,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
                                           uint64_t* __restrict__ obase, uint64_t ostride, uint64_t out_cap,
                                           unsigned long long* overflow) {
     uint32_t dg[PITEMS], rk[PITEMS];
+    bool bad = false;
 #pragma unroll
     for (int it = 0; it < PITEMS; ++it) {
         const uint32_t j = it * PT + threadIdx.x;
@@ -149,16 +150,15 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
                 k[it] = h;
             }
         }
-        dg[it] = NB;
-        if (j < tn) {
-            if (bin >= bin_base && bin - bin_base < lim) {
-                dg[it] = (uint32_t)(bin - bin_base);
-                rk[it] = atomicAdd(&S.hist[dg[it]], 1u);
-            } else {
-                atomicOr(overflow, 4ull);   // a configuration error: never silently dropped
-            }
-        }
+        // bin - bin_base wraps above lim (<= 2^DBITS) for a bin below the group's first
+        const uint64_t rel = bin - bin_base;
+        const bool ok = j < tn && rel < lim;
+        bad |= j < tn && !ok;
+        dg[it] = ok ? (uint32_t)rel : (uint32_t)NB;
+        rk[it] = 0;
+        if (ok) rk[it] = atomicAdd(&S.hist[dg[it]], 1u);
     }
+    if (bad) atomicOr(overflow, 4ull);   // a configuration error: never silently dropped
     __syncthreads();
     if constexpr (WC) {
         // One scan gives both the tile's sorted offsets (low half) and the flush order of the
@@ -929,6 +929,10 @@ hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cn
                          uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint32_t kcap,
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
+    // local positions are 16-bit, and the A and C bits and the positions must fit the LDS pool
+    if (pbits < 10 || pbits > 16 || kcap > (uint32_t)(KT * BI) ||
+        (1u << pbits) / 4 + 2ull * kcap > (uint64_t)BUCKET_LDS)
+        return hipErrorInvalidValue;
     if (packed)
         hipLaunchKernelGGL(k_bucket<true>, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
                            pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
