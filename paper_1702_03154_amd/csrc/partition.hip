@@ -95,9 +95,10 @@ constexpr int LW = 16;   // keys per 128-byte line
 template <int NB, bool WC, bool DENSE>
 struct PartLds {
     static constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
-    uint64_t skeys[PTILE];          // the tile, sorted by bin
+    // the tile sorted by bin in kbuf[0, PTILE); with WC, the unfinished line of bin d in
+    // kbuf[PTILE + d * LW, PTILE + d * LW + LW) (one array, so a key is read from either by index)
+    uint64_t kbuf[PTILE + (WC ? NB * LW : 0)];
     uint16_t sdig[WC ? 1 : PTILE];  // bin of each sorted key (runs written as they are)
-    uint64_t carry[WC ? NB * LW : 1];   // unfinished line of each bin
     uint32_t hist[NB];              // keys of the tile per bin
     uint32_t hoff[NB];              // first sorted position of the bin
     uint32_t run[NB];               // keys of the bin so far, this tile included once scanned
@@ -107,7 +108,7 @@ struct PartLds {
     uint32_t wsum[PT / 64 + 1];
     uint32_t nf;                    // keys in whole lines this tile
     uint64_t sp[TSEG + 1];          // pre[s .. s + TSEG] of a spanning tile
-    uint64_t dst[DENSE ? NB : 1];   // dense output: the bin's first key at dst + a0 (dst on a line)
+    uint64_t dst[NB];               // the bin's output at obase + dst (dense: first key at dst + a0, dst on a line)
     uint32_t a0[DENSE ? NB : 1];
 };
 
@@ -118,7 +119,7 @@ template <int NB, bool WC, bool HASHED, int DIG>
 __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t (&k)[PITEMS], uint32_t tn,
                                           const LevelHash& L, uint32_t pbits, uint32_t out_shift,
                                           uint32_t pack_shift, uint64_t bin_base, uint64_t lim,
-                                          uint64_t* __restrict__ obase, uint64_t ostride, uint64_t out_cap,
+                                          uint64_t* __restrict__ obase, uint64_t out_cap,
                                           unsigned long long* overflow) {
     uint32_t dg[PITEMS], rk[PITEMS];
     bool bad = false;
@@ -186,7 +187,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         __syncthreads();
 #pragma unroll
         for (int it = 0; it < PITEMS; ++it)
-            if (dg[it] < (uint32_t)NB) S.skeys[S.hoff[dg[it]] + rk[it]] = k[it];
+            if (dg[it] < (uint32_t)NB) S.kbuf[S.hoff[dg[it]] + rk[it]] = k[it];
         __syncthreads();
         // whole lines: key g of bin d comes from the unfinished line (g < run before the tile)
         // or from the tile's sorted run
@@ -195,12 +196,12 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
             const uint32_t d = S.lbin[f / LW];
             const uint32_t r = S.rold[d];
             const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - S.fpre[d]);
-            const uint64_t v = g < r ? S.carry[d * LW + (g & (LW - 1))] : S.skeys[S.hoff[d] + (g - r)];
-            if (DIG == 2) {
-                if (g >= S.a0[d]) obase[S.dst[d] + g] = v;
-            } else if (g < out_cap) {
-                obase[d * ostride + g] = v;
-            }
+            // the key's index in the unfinished line (g < r) or in the sorted tile, blended with a
+            // mask rather than a branch (the lanes of a line take both sides)
+            const uint32_t ic = PTILE + d * LW + (g & (LW - 1));
+            const uint32_t it = S.hoff[d] + (g - r);
+            const uint64_t v = S.kbuf[ic + ((it - ic) & (0u - (uint32_t)(g >= r)))];
+            if (DIG == 2 ? g >= S.a0[d] : g < out_cap) obase[S.dst[d] + g] = v;
         }
         __syncthreads();
         // keys past the last whole line start the bin's next unfinished line (run[] already
@@ -209,7 +210,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         for (int it = 0; it < PITEMS; ++it) {
             if (dg[it] < (uint32_t)NB) {
                 const uint32_t g = S.rold[dg[it]] + rk[it];
-                if (g >= (S.run[dg[it]] & ~(uint32_t)(LW - 1))) S.carry[dg[it] * LW + (g & (LW - 1))] = k[it];
+                if (g >= (S.run[dg[it]] & ~(uint32_t)(LW - 1))) S.kbuf[PTILE + dg[it] * LW + (g & (LW - 1))] = k[it];
             }
         }
     } else {
@@ -237,7 +238,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         for (int it = 0; it < PITEMS; ++it) {
             if (dg[it] < (uint32_t)NB) {
                 const uint32_t p = S.hoff[dg[it]] + rk[it];
-                S.skeys[p] = k[it];
+                S.kbuf[p] = k[it];
                 S.sdig[p] = (uint16_t)dg[it];
             }
         }
@@ -246,8 +247,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         for (uint32_t p = threadIdx.x; p < tn; p += PT) {
             const uint32_t d = S.sdig[p];
             const uint64_t o = (uint64_t)S.run[d] + (p - S.hoff[d]);
-            if (DIG == 2) obase[S.dst[d] + o] = S.skeys[p];
-            else if (o < out_cap) obase[d * ostride + o] = S.skeys[p];
+            if (DIG == 2 || o < out_cap) obase[S.dst[d] + o] = S.kbuf[p];
         }
         __syncthreads();
         for (int d = threadIdx.x; d < NB; d += PT) {
@@ -293,7 +293,8 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     // bins this workgroup may write: those its group owns, and only existing ones
     const uint64_t owned = grouped ? (1ull << group_shift) : (uint64_t)NB;
     const uint64_t lim = bin_base >= nbins ? 0 : (nbins - bin_base < owned ? nbins - bin_base : owned);
-    // regions: digit d writes at obase + d * ostride; dense: at out + dst[d] (+ a0[d] for the first)
+    // regions: digit d writes at obase + dst[d] = obase + d * ostride; dense: at out + dst[d] (+ a0[d]
+    // for the first)
     uint64_t* const obase = DENSE ? out : out + (bin_base * S_out + slot) * out_cap;
     const uint64_t ostride = (uint64_t)S_out * out_cap;
 
@@ -308,6 +309,8 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             S.dst[d] = B - a;
             S.a0[d] = a;
             S.run[d] = a;
+        } else {
+            S.dst[d] = (uint64_t)d * ostride;
         }
     }
     __syncthreads();
@@ -343,7 +346,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                 te1 = tile_end(t1);
                 load_tile(kn, in + (uint64_t)s * in_stride + (t1 - sb), (uint32_t)(te1 - t1));
             }
-            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase, ostride,
+            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase,
                                       out_cap, overflow);
             t0 = t1;
             te = te1;
@@ -382,7 +385,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
                     k[it] = in[(uint64_t)(s + qi) * in_stride + (i - S.sp[qi])];
                 }
             }
-            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase, ostride,
+            part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase,
                                       out_cap, overflow);
             t0 = te;
         }
@@ -393,11 +396,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             const uint32_t d = e / LW;
             const uint32_t r = S.run[d];
             const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (e & (LW - 1));
-            if (DENSE) {
-                if (g < r && g >= S.a0[d]) obase[S.dst[d] + g] = S.carry[e];
-            } else if (g < r && g < out_cap) {
-                obase[d * ostride + g] = S.carry[e];
-            }
+            if (g < r && (DENSE ? g >= S.a0[d] : g < out_cap)) obase[S.dst[d] + g] = S.kbuf[PTILE + e];
         }
     }
     if constexpr (!DENSE) {
