@@ -505,6 +505,7 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
         return;
     }
     const uint64_t pbase = b << pbits;
+    bool bad = false;
     uint64_t h[BI];
     {
         // segment of the thread's first key by binary search, later keys (KT further on each)
@@ -531,18 +532,18 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
                 h[it] = (h[it] >> pbits) * L.m + pbase + p;
             } else {
                 p = mod_invariant(h[it], L.m, L.magic, L.sh1, L.sh2) - pbase;
-                if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
-                    atomicOr(overflow, 8ull);
-                    lps[i] = 0;
-                    continue;
-                }
-                lps[i] = (uint16_t)p;
+                // not this bucket's key: the partition was wrong; never touch LDS with it
+                const bool out = p >= P;
+                bad |= out;
+                lps[i] = out ? 0 : (uint16_t)p;
+                if (out) continue;
             }
             const uint32_t bit = 1u << (p & 31);
             const uint32_t old = atomicOr(&Abits[p >> 5], bit);
             if (old & bit) atomicOr(&Cbits[p >> 5], bit);
         }
     }
+    if (bad) atomicOr(overflow, 8ull);
     __syncthreads();
     // finalize: A &= ~C, written as 64-bit words of the level
     const uint64_t w0 = b << (pbits - 6);
@@ -612,6 +613,7 @@ k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* _
     }
     __syncthreads();
     const uint64_t pbase = b << pbits;
+    bool bad = false;   // a key outside the bucket: the partition was wrong; never touch LDS with it
     for (uint32_t q = 0; q < S; ++q) {
         const uint32_t c = cnt[b * S + q];
         const uint64_t* src = in + (b * S + q) * in_cap;
@@ -625,10 +627,14 @@ k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* _
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (i0 + u * AT + threadIdx.x >= c) continue;
-                const uint64_t p = PACKED ? h[u] & (P - 1) : mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
-                if (p >= P) {   // not this bucket's key: the partition was wrong; never touch LDS with it
-                    atomicOr(overflow, 8ull);
-                    continue;
+                uint32_t p;
+                if (PACKED) {
+                    p = (uint32_t)h[u] & (P - 1);
+                } else {
+                    const uint64_t pl = mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
+                    bad |= pl >= P;
+                    if (pl >= P) continue;
+                    p = (uint32_t)pl;
                 }
                 const uint32_t bit = 1u << (p & 31);
                 const uint32_t old = atomicOr(&Ab[p >> 5], bit);
@@ -636,6 +642,7 @@ k_accumulate(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* _
             }
         }
     }
+    if (bad) atomicOr(overflow, 8ull);
     __syncthreads();
     for (uint32_t j = threadIdx.x; j < nw; j += AT)
         if (w0 + j < wwords) W[w0 + j] = (uint64_t)Ab[j] | ((uint64_t)Cb[j] << 32);
@@ -672,6 +679,7 @@ k_bucket_test(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* 
     uint64_t* dst = Y + b * ycap;
     uint32_t o = 0;   // survivors written so far (uniform)
     bool full = false;
+    bool bad = false;   // a key outside the bucket: the partition was wrong
     for (uint32_t q = 0; q < S && !full; ++q) {
         const uint32_t c = cnt[b * S + q];
         const uint64_t* src = in + (b * S + q) * in_cap;
@@ -692,10 +700,8 @@ k_bucket_test(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* 
                     h[u] = (h[u] >> pbits) * L.m + pbase + p;
                 } else {
                     p = mod_invariant(h[u], L.m, L.magic, L.sh1, L.sh2) - pbase;
-                    if (p >= P) {   // not this bucket's key: the partition was wrong
-                        atomicOr(overflow, 8ull);
-                        continue;
-                    }
+                    bad |= p >= P;
+                    if (p >= P) continue;
                 }
                 if (!((abits[p >> 5] >> (p & 31)) & 1u)) keep |= 1u << u;
             }
@@ -712,6 +718,7 @@ k_bucket_test(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* 
             o += tot;
         }
     }
+    if (bad) atomicOr(overflow, 8ull);
     if (threadIdx.x == 0) surv[b] = o;
 }
 
