@@ -1,6 +1,8 @@
 // Host runtime and C ABI: the level driver of the build (Algorithm 1), the fallback table,
 // the rank table and the lookup entry points.  Every step of the method runs in the kernels of
-// kernels.hip; the host only sizes levels, allocates, and reads one count back per level.
+// kernels.hip and partition.hip (batch.hip, stream.hip, kmer.hip and server.hip for the batched,
+// streamed, k-mer and serving paths); the host only sizes levels, allocates, and reads one count
+// back per level.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
