@@ -215,7 +215,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         }
     } else {
         {   // exclusive scan of the tile histogram
-            constexpr int PER = NB / PT > 0 ? NB / PT : 1;
+            constexpr int PER = (NB + PT - 1) / PT;   // bins per thread
             uint32_t v[PER];
             uint32_t sum = 0;
             const int b0 = threadIdx.x * PER;
