@@ -80,8 +80,8 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // (pos mod 2^pack_shift) where h = q m + pos: with pack_shift = the coarse bin's bits the record
 // keeps everything the later passes need (q < 2^64 / m fits above them, the bin is the region) and
 // spares them the division.  DIG = 4 (second pass) reads such records and writes
-// (q << pbits) | (pos mod 2^pbits) for the bucket pass; h = q m + pos is recovered there for the
-// keys that survive.
+// (q << pbits) | (pos mod 2^pbits) for the bucket pass, which forms h = q m + pos again and
+// recovers the surviving keys from it.
 //
 // DIG = 1 or 2 partitions by the top bits of h instead of its level position: pos = h >> L.sh1
 // (the hash-set partition of a key set into 2^(64 - sh1) independent sets).  DIG = 2 writes the
