@@ -657,7 +657,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=float, default=1e9)
     ap.add_argument("--gamma", type=float, default=2.0)
-    ap.add_argument("--cpu-sample", type=float, default=5e7)
+    ap.add_argument("--cpu-sample", type=float, default=1e8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size kernel for counter scaling)")
