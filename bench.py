@@ -663,8 +663,8 @@ def main():
                     help="also run one plain 1 GiB device copy (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported on this build "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path is built "
+              "and timed on a single GPU; no multi-GPU sharding is implemented)", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
