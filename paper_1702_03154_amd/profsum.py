@@ -48,7 +48,7 @@ def pmc(db: str, counter: str, out=sys.stdout):
         print(f"{short(n):60s} {k:10d} {a:14.1f} {lo:14.1f} {hi:14.1f}", file=out)
 
 
-SOURCES = ("kernels.hip", "device.h")   # the lookup kernel and the device helpers it inlines
+SOURCES = ("kernels.hip", "device.h", "internal.h")   # the lookup kernel and the device code it inlines
 BUILD_SOURCES = ("kernels.hip", "partition.hip", "device.h", "internal.h", "api.hip")   # the build
 
 
