@@ -266,11 +266,9 @@ constexpr uint64_t PART_WGS = 512;
 
 // Workgroups per coarse bin in the second partition pass over n keys (the bucket pass then reads
 // that many regions per bucket).  The C * K workgroups run in ceil(C * K / PART_WGS) rounds, each
-// doing 1 / (C * K) of the keys, so K minimizes rounds / (C * K): C = 188 gives K = 8 or 16 (1504
-// or 3008 workgroups in 3 or 6 rounds) rather than K = 2 (376 workgroups, a quarter of the slots
-// idle).  Among equal choices the largest K wins: its last, partly filled round is shortest, and a
-// compute unit left with one workgroup then waits least (C = 239 at 1e9 keys: K = 16, not 2, saves
-// 0.2 ms).  A workgroup keeps at least 16 tiles of work while there are more workgroups than slots.
+// doing 1 / (C * K) of the keys, so K minimizes rounds / (C * K): C = 188 gives K = 8 (1504
+// workgroups in 3 rounds) rather than K = 2 (376 workgroups, a quarter of the slots idle).  A
+// workgroup keeps at least 16 tiles of work while there are more workgroups than slots.
 uint64_t slots_per_group(uint64_t C, uint64_t n) {
     const uint64_t cap = std::max<uint64_t>(PART_WGS, n / 65536) / C;
     const uint64_t kmax = std::max<uint64_t>(1, std::min<uint64_t>(16, cap));
@@ -278,7 +276,7 @@ uint64_t slots_per_group(uint64_t C, uint64_t n) {
     double best_t = 1e300;
     for (uint64_t K = 1; K <= kmax; ++K) {
         const double t = (double)((C * K + PART_WGS - 1) / PART_WGS) / (double)(C * K);
-        if (t <= best_t * 1.001) {   // ties go to more, smaller workgroups: a shorter tail
+        if (t < best_t * 0.999) {
             best_t = t;
             best = K;
         }
