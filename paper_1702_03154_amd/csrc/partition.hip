@@ -30,8 +30,8 @@ namespace mphfk {
 
 namespace {
 
-constexpr int PT = 512;               // threads of the partition kernel
-constexpr int PITEMS = 8;             // keys per thread per tile
+constexpr int PT = 768;               // threads of the partition kernel
+constexpr int PITEMS = 4;             // keys per thread per tile
 constexpr int PTILE = PT * PITEMS;    // keys per tile
 constexpr int TSEG = 64;              // input segments one tile may span
 constexpr int BT = 1024;              // threads of the tail kernel
@@ -66,7 +66,7 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // A tile is counting-sorted by bin in LDS.  With 2^8 bins (WC) a workgroup also keeps, per bin,
 // the keys of its last unfinished 16-key line in LDS, and a tile writes only whole lines: a
 // 128-byte line at a 128-byte boundary of the bin's region (out_cap is a multiple of 16), each
-// line written once, by 16 adjacent lanes.  The runs of a tile average 16 keys per bin, so
+// line written once, by 16 adjacent lanes.  The runs of a tile average 12 keys per bin, so
 // writing them where they fall would split most lines between two tiles and two writes.  The
 // unfinished lines go out at the end.  With 2^10 bins the per-bin lines would not fit in LDS and
 // the runs are written as they are.
@@ -268,9 +268,9 @@ __device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t*
     }
 }
 
-// (at least 4 waves per SIMD: two workgroups per compute unit, as the LDS allows)
+// (6 waves per SIMD: two workgroups of 12 waves per compute unit, as the LDS allows, at 80 VGPRs)
 template <int DBITS, bool HASHED, bool SPAN, int DIG>
-__global__ void __launch_bounds__(PT, 4)
+__global__ void __launch_bounds__(PT, 6)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
             uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift, uint32_t pack_shift,
             uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
