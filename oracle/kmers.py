@@ -10,7 +10,7 @@ Written from the definitions with strings, not bit arithmetic:
 * the first occurrences of a key sequence keep each distinct key at its first position, in
   order, up to a target count.
 
-Pure Python loops: small inputs only.
+Pure Python: a few million positions at most.
 """
 from __future__ import annotations
 
@@ -18,22 +18,21 @@ import numpy as np
 
 LETTERS = "ACGT"
 _COMPLEMENT = str.maketrans("ACGT", "TGCA")
+_TO_DIGITS = str.maketrans("ACGT", "0123")
+_TO_LETTERS = str.maketrans("0123", "ACGT")
 
 
 def decode(seq_words, nbases: int) -> str:
-    out = []
-    for i in range(nbases):
-        w = int(seq_words[i // 32])
-        shift = 62 - 2 * (i % 32)
-        out.append(LETTERS[(w >> shift) & 3])
-    return "".join(out)
+    """Each word written as its 32 base-4 digits, first digit most significant, then the digits
+    0..3 read as A, C, G, T."""
+    digits = "".join(np.base_repr(int(w), 4).rjust(32, "0") for w in seq_words[:(nbases + 31) // 32])
+    return digits[:nbases].translate(_TO_LETTERS)
 
 
 def encode(s: str) -> int:
-    v = 0
-    for c in s:
-        v = 4 * v + LETTERS.index(c)
-    return v
+    """The base-4 number whose digits are the letters of s (A=0, C=1, G=2, T=3), first letter most
+    significant."""
+    return int(s.translate(_TO_DIGITS), 4) if s else 0
 
 
 def reverse_complement(s: str) -> str:
