@@ -64,7 +64,13 @@ typedef struct mphf_opts {
     uint32_t batch_threads;
     uint32_t batch_items;
     uint32_t batch_wgs_per_cu;
-    uint32_t reserved;        /* 0 */
+    uint32_t bucket_bits;     /* log2 of the positions per bucket of the partitioned levels of a
+                                 single build: 0 (default) = the largest bucket whose keys fit one
+                                 workgroup's LDS (2^14 positions at gamma = 1, 2^15 at gamma = 2,
+                                 2^16 from gamma = 4.3),
+                                 else 6..16 and at most that default.  Smaller buckets make a level
+                                 take more buckets and wider partition passes with the same result;
+                                 for checks of those paths on small key sets. */
 } mphf_opts;
 
 /* Build every level by global atomic test-and-set on the interleaved A/C words instead of the
@@ -91,7 +97,27 @@ typedef struct mphf_stats {
     uint64_t peak_bytes;                      /* most device bytes the build held at once */
     uint64_t lookup_bytes;                    /* the lookup's copy of A: 64-byte sectors that each hold a
                                                  32-bit rank counter and 480 bits, plus superblock counters */
+    uint32_t level_path[MPHF_MAX_LEVELS];     /* how level d was built: one of MPHF_PATH_* */
+    uint32_t bucket_bits;                     /* log2 of the bucket size of the partitioned levels */
+    uint32_t reserved;
 } mphf_stats_t;
+
+/* Values of mphf_stats_t.level_path.  Every path gives the same bits (a position keeps its 1 iff
+ * exactly one key lands on it, whatever the order of insertion).  A level of m positions in buckets
+ * of 2^b positions (b = bucket_bits) has B = ceil(m / 2^b) buckets:
+ *   B <= 1024: one radix pass into the buckets;
+ *   1024 < B <= 2^16: a pass into coarse bins, then 2^8 buckets per bin;
+ *   2^16 < B <= 2^18: the same with 2^9 or 2^10 buckets per bin (the wide second pass);
+ *   B > 2^18 (more than 2^(18+b) positions, e.g. about 4.3e9 keys per level at gamma = 2):
+ *   global atomic test-and-set over the whole level, also used after a region overflow (adversarial
+ *   key sets) and with MPHF_FLAG_ATOMIC_LEVELS. */
+#define MPHF_PATH_TAIL 1            /* every remaining level in one workgroup's LDS (small levels) */
+#define MPHF_PATH_ONE_PASS 2
+#define MPHF_PATH_TWO_PASS 3
+#define MPHF_PATH_TWO_PASS_WIDE 4
+#define MPHF_PATH_ATOMIC 5
+#define MPHF_PATH_STREAMED 6        /* streaming build: chunks partitioned and added in LDS */
+#define MPHF_PATH_STREAMED_ATOMIC 7 /* streaming build: global test-and-set over the stream */
 
 /* Read-only device views of a built function (owned by the handle). */
 typedef struct mphf_view {

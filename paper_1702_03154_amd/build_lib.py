@@ -10,6 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SOURCES = ["kernels.hip", "partition.hip", "batch.hip", "kmer.hip", "stream.hip", "server.hip", "api.hip"]
 LIB = os.path.join(PKG, "libmphf.so")
+OBJ_DIR = os.path.join(PKG, "_build")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
@@ -26,19 +27,38 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, *srcs]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                      if "packed-fp32-ops" not in l and l.strip())
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + msgs)
-    if verbose and msgs:
-        print(msgs)
+    return r.returncode, msgs
+
+
+def build(verbose: bool = False) -> str:
+    """Every source compiled to an object in parallel (the kernels of one file call no device code
+    of another), then linked into the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
+        jobs.append((obj, [hipcc(), *compile_flags, *inc, "-c", "-o", obj, os.path.join(CSRC, src)]))
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda j: _run(j[1], verbose), jobs))
+    for (obj, _), (rc, msgs) in zip(jobs, results):
+        if rc != 0:
+            raise RuntimeError(f"hipcc failed on {os.path.basename(obj)}:\n" + msgs)
+        if verbose and msgs:
+            print(msgs)
+    tmp = LIB + ".tmp"
+    rc, msgs = _run([hipcc(), *HIPCC_FLAGS, "-o", tmp, *(o for o, _ in jobs)], verbose)
+    if rc != 0:
+        raise RuntimeError("hipcc link failed:\n" + msgs)
     os.replace(tmp, LIB)
     return LIB
 

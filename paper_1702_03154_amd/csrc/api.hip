@@ -31,6 +31,8 @@ struct mphf {
     uint64_t level_weight[MPHF_MAX_LEVELS] = {};
     uint64_t level_offset[MPHF_MAX_LEVELS] = {};
     uint64_t level_seed[MPHF_MAX_LEVELS] = {};
+    uint32_t level_path[MPHF_MAX_LEVELS] = {};   // MPHF_PATH_* of each level
+    uint32_t bucket_bits = 0;
     uint64_t total_bits = 0;
     uint64_t total_words = 0;
     uint64_t* words = nullptr;
@@ -241,6 +243,8 @@ mphf_status check_opts(const mphf_opts& o) {
     if (o.rank_sample != 512 && o.rank_sample != 1024)
         return fail(MPHF_E_INVALID, "rank_sample must be 512 or 1024");
     if (o.flags & ~(uint32_t)MPHF_FLAG_ATOMIC_LEVELS) return fail(MPHF_E_INVALID, "unknown flags");
+    if (o.bucket_bits && (o.bucket_bits < 6 || o.bucket_bits > 16))
+        return fail(MPHF_E_INVALID, "bucket_bits must be 0 or 6..16");
     return MPHF_OK;
 }
 
@@ -347,7 +351,7 @@ class Builder {
             if ((st = read_back(counters + d, 8)) != MPHF_OK) return st;
             const uint64_t weight = host_[0];
             if (weight > nd) return fail(MPHF_E_DEVICE, "level weight exceeds the level's keys");
-            record(d, nd, m, weight, off);
+            record(d, nd, m, weight, off, accumulated ? MPHF_PATH_STREAMED : MPHF_PATH_STREAMED_ATOMIC);
             // the level joins the walk of the next scans
             DevLevel* hl = (DevLevel*)(host_ + 64);
             *hl = DevLevel{L.seed, L.m, L.magic, L.bit_off, L.sh1, L.sh2};
@@ -405,8 +409,7 @@ class Builder {
     // Bucket bits for a level of m positions: the bucket geometry's, raised until two radix passes
     // reach every bucket (at most 2^18 buckets); 0 if no bucket of at most 2^18 positions does.
     uint32_t stream_bucket_bits(uint64_t m) const {
-        const BucketGeometry geo = bucket_geometry(gamma_);
-        uint32_t pb = geo.pbits ? geo.pbits : 15;
+        uint32_t pb = geo_.pbits ? geo_.pbits : 15;
         while (pb < 18 && ceil_log2((m + (1ull << pb) - 1) >> pb) > 18) ++pb;
         return ceil_log2((m + (1ull << pb) - 1) >> pb) <= 18 ? pb : 0;
     }
@@ -498,6 +501,10 @@ class Builder {
     mphf_status setup(uint64_t n, double gamma) {
         mphf_status st;
         gamma_ = gamma;
+        geo_ = bucket_geometry(gamma, o_.bucket_bits);
+        if (o_.bucket_bits && !geo_.pbits)
+            return fail(MPHF_E_INVALID, "bucket_bits: the keys of such a bucket do not fit one workgroup at this gamma");
+        h_->bucket_bits = geo_.pbits;
         acquire_workspace();
         level_seeds(h_->seed, o_.max_levels, seeds_.s);
         if (cached_ && ws_->host) {
@@ -540,7 +547,7 @@ class Builder {
         const uint32_t D = o_.max_levels;
         const double gamma = gamma_;
         const uint32_t tk = tail_capacity(gamma);
-        const BucketGeometry geo = bucket_geometry(gamma);
+        const BucketGeometry geo = geo_;
         bool fallback = atomic_only || geo.pbits == 0;
         while (!fallback && cur.n > 0 && d < D) {
             if (cur.n <= tk) {
@@ -616,6 +623,7 @@ class Builder {
     Arena ar_;
     Trace tr_;
     double gamma_ = 0;
+    BucketGeometry geo_{};
     SeedTable seeds_{};
     uint64_t* host_ = nullptr;
     uint64_t* dev_ = nullptr;        // [0..63] weights, [64..127] survivor counts, [128] dup flag,
@@ -634,7 +642,8 @@ class Builder {
     std::unique_lock<std::mutex> lock_;
     int ypar_ = 0;
 
-    void record(uint32_t d, uint64_t n, uint64_t m, uint64_t weight, uint64_t off) {
+    void record(uint32_t d, uint64_t n, uint64_t m, uint64_t weight, uint64_t off, uint32_t path) {
+        h_->level_path[d] = path;
         h_->level_n[d] = n;
         h_->level_m[d] = m;
         h_->level_weight[d] = weight;
@@ -827,7 +836,8 @@ class Builder {
         if (host_[0]) return MPHF_OK;   // overflow: redo with atomics
         const uint64_t nnext = host_[1];
         if (nnext > n) return fail(MPHF_E_DEVICE, "survivors exceed the level's keys");
-        record(d, n, m, n - nnext, off);
+        record(d, n, m, n - nnext, off,
+               B <= 1024 ? MPHF_PATH_ONE_PASS : lb - 8 > 8 ? MPHF_PATH_TWO_PASS_WIDE : MPHF_PATH_TWO_PASS);
         out->base = ws_->Y[yp];
         out->stride = g.kcap;
         out->pre = ws_->preY[yp];
@@ -853,7 +863,8 @@ class Builder {
         std::vector<TailLevel> rec(MPHF_MAX_LEVELS);
         HIP_TRY(hipMemcpy(rec.data(), tail_rec_, sizeof(TailLevel) * MPHF_MAX_LEVELS, hipMemcpyDeviceToHost),
                 "read tail records");
-        for (uint64_t d = d0; d < end; ++d) record((uint32_t)d, rec[d].n, rec[d].m, rec[d].weight, rec[d].offset);
+        for (uint64_t d = d0; d < end; ++d)
+            record((uint32_t)d, rec[d].n, rec[d].m, rec[d].weight, rec[d].offset, MPHF_PATH_TAIL);
         h_->total_bits = bit_end;
         if (nleft) {
             left_ = left;
@@ -889,7 +900,7 @@ class Builder {
             if ((st = read_back(counters + d, 8)) != MPHF_OK) return st;
             const uint64_t weight = host_[0];
             if (weight > nd) return fail(MPHF_E_DEVICE, "level weight exceeds the level's keys");
-            record(d, nd, m, weight, off);
+            record(d, nd, m, weight, off, MPHF_PATH_ATOMIC);
             const uint64_t nnext = nd - weight;
             const uint64_t off_next = off + 64 * wd;
             off = off_next;
@@ -1138,7 +1149,9 @@ mphf_status mphf_stats(const mphf_t* h, mphf_stats_t* st) {
         st->level_weight[d] = h->level_weight[d];
         st->level_offset[d] = h->level_offset[d];
         st->level_seed[d] = h->level_seed[d];
+        st->level_path[d] = h->level_path[d];
     }
+    st->bucket_bits = h->bucket_bits;
     st->n_fallback = h->nfb;
     st->total_bits = h->total_bits;
     st->rank_entries = h->nrank;

@@ -161,7 +161,9 @@ struct BucketGeometry {
     uint32_t pbits;
     uint32_t kcap;
 };
-BucketGeometry bucket_geometry(double gamma);
+// pbits = 0: the largest bucket that fits; else exactly 2^pbits positions (a result with pbits = 0
+// if that does not fit).
+BucketGeometry bucket_geometry(double gamma, uint32_t pbits = 0);
 uint32_t tail_capacity(double gamma);
 
 hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t in_stride,

@@ -863,12 +863,14 @@ hipError_t launch_tail(const uint64_t* in, uint64_t in_stride, const uint64_t* p
     return hipGetLastError();
 }
 
-BucketGeometry bucket_geometry(double gamma) {
+BucketGeometry bucket_geometry(double gamma, uint32_t pbits) {
     // Largest power-of-two bucket (at most 2^16 positions, so a local position fits 16 bits)
     // whose expected keys (P / gamma, plus 8 standard deviations and a margin) fit the LDS
-    // budget together with the bucket's A and C bits.
+    // budget together with the bucket's A and C bits; with pbits != 0, that size if it fits.
     BucketGeometry g{};
-    for (uint32_t pb = 16; pb >= 10; --pb) {
+    const uint32_t hi = pbits ? pbits : 16, lo = pbits ? pbits : 10;
+    if (pbits && (pbits < 6 || pbits > 16)) return g;
+    for (uint32_t pb = hi; pb >= lo; --pb) {
         const double P = (double)(1u << pb);
         const double mu = P / gamma;
         const double kc = std::ceil(mu + 8.0 * std::sqrt(mu) + 128.0);
@@ -936,7 +938,7 @@ hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cn
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
                          uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
     // local positions are 16-bit, and the A and C bits and the positions must fit the LDS pool
-    if (pbits < 10 || pbits > 16 || kcap > (uint32_t)(KT * BI) ||
+    if (pbits < 6 || pbits > 16 || kcap > (uint32_t)(KT * BI) ||
         (1u << pbits) / 4 + 2ull * kcap > (uint64_t)BUCKET_LDS)
         return hipErrorInvalidValue;
     if (packed)

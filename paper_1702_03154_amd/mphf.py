@@ -33,7 +33,7 @@ class Opts(C.Structure):
     _fields_ = [("max_levels", C.c_uint32), ("rank_sample", C.c_uint32),
                 ("mem_budget", C.c_uint64), ("keep_collisions", C.c_uint32),
                 ("flags", C.c_uint32), ("batch_threads", C.c_uint32), ("batch_items", C.c_uint32),
-                ("batch_wgs_per_cu", C.c_uint32), ("reserved", C.c_uint32)]
+                ("batch_wgs_per_cu", C.c_uint32), ("bucket_bits", C.c_uint32)]
 
 
 _U64L = C.c_uint64 * MAX_LEVELS
@@ -46,7 +46,12 @@ class Stats(C.Structure):
                 ("level_offset", _U64L), ("level_seed", _U64L),
                 ("n_fallback", C.c_uint64), ("total_bits", C.c_uint64),
                 ("rank_entries", C.c_uint64), ("structure_bytes", C.c_uint64),
-                ("bits_per_key", C.c_double), ("peak_bytes", C.c_uint64), ("lookup_bytes", C.c_uint64)]
+                ("bits_per_key", C.c_double), ("peak_bytes", C.c_uint64), ("lookup_bytes", C.c_uint64),
+                ("level_path", C.c_uint32 * MAX_LEVELS), ("bucket_bits", C.c_uint32), ("reserved", C.c_uint32)]
+
+# values of Stats.level_path (how a level was built)
+PATH_NAMES = {1: "tail", 2: "one_pass", 3: "two_pass", 4: "two_pass_wide", 5: "atomic", 6: "streamed",
+              7: "streamed_atomic"}
 
 
 class SetInfo(C.Structure):
@@ -179,12 +184,13 @@ class MPHF:
     @classmethod
     def build(cls, keys: torch.Tensor, gamma: float = 2.0, seed: int = 0, max_levels: int = 25,
               rank_sample: int = 512, mem_budget: int = 0, keep_collisions: bool = False,
-              stream=None) -> "MPHF":
+              bucket_bits: int = 0, atomic_levels: bool = False, stream=None) -> "MPHF":
         L = lib()
         ptr = _dev(keys, "keys") if keys.numel() else (keys.data_ptr() if keys.is_cuda else 0)
         if not keys.is_cuda:
             raise ValueError("keys must be a tensor in GPU memory")
-        o = Opts(max_levels, rank_sample, mem_budget, 1 if keep_collisions else 0, 0)
+        o = Opts(max_levels, rank_sample, mem_budget, 1 if keep_collisions else 0, 1 if atomic_levels else 0)
+        o.bucket_bits = bucket_bits
         h = C.c_void_p()
         with torch.cuda.device(keys.device):
             _check(L.mphf_build_ex(ptr, keys.numel(), float(gamma), seed & (2**64 - 1), C.byref(o),
@@ -212,6 +218,7 @@ class MPHF:
             "total_bits": s.total_bits, "rank_entries": s.rank_entries,
             "structure_bytes": s.structure_bytes, "bits_per_key": s.bits_per_key,
             "peak_bytes": s.peak_bytes, "lookup_bytes": s.lookup_bytes,
+            "level_path": [PATH_NAMES.get(v, str(v)) for v in s.level_path[:L]], "bucket_bits": s.bucket_bits,
         }
 
     def export(self) -> dict:

@@ -11,6 +11,7 @@ import torch
 from oracle import kmers as K
 from oracle import mphf_oracle as O
 from paper_1702_03154_amd import inputs as I
+from tests.parity import check_against_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +62,8 @@ def test_first_occurrences_equal_the_oracle(M, target):
     words = low_complexity(6000, 3)
     kmers = M.kmers(torch.from_numpy(words.view(np.int64)).cuda(), 6000, 21)
     got = host(M.first_occurrences(kmers, target))
-    assert np.array_equal(got, K.first_occurrences(host(kmers), target))
+    want_kmers = K.canonical_kmers(words, 6000, 21)       # the oracle's own k-mers, not the GPU's
+    assert np.array_equal(got, K.first_occurrences(want_kmers, target))
 
 
 def test_first_occurrences_of_random_keys_keep_everything(M):
@@ -131,16 +133,39 @@ def test_levels_of_kmer_keys_follow_the_occupancy_statistics(M):
     assert torch.equal(torch.sort(lab).values, torch.arange(1, keys.numel() + 1, device=lab.device))
 
 
+def oracle_kmer_keys(nb, seed, target):
+    """The first `target` distinct canonical 31-mers of the seeded sequence, from the string oracle
+    (the oracle's inputs never come from the HIP path)."""
+    words = I.dna_sequence(nb, seed=seed).numpy().view(np.uint64)
+    return K.first_occurrences(K.canonical_kmers(words, nb, 31), target)
+
+
+def test_plain_build_on_kmer_keys_equals_the_oracle(M):
+    """2e6 k-mer keys (structured: overlapping windows of one sequence): every bit array, collision
+    array, rank counter and label of the plain build equals the oracle's."""
+    keys = oracle_kmer_keys(2_000_100, 11, 2_000_000)
+    assert len(keys) == 2_000_000
+    check_against_oracle(M, keys, 2.0, queries_np=I.keys(50_000, 71).numpy().view(np.uint64))
+
+
 def test_batched_path_over_hash_sets(M):
-    nb = 1_200_000
-    keys = M.first_occurrences(M.kmers(I.dna_sequence(nb, seed=12).cuda(), nb, 31), 1_000_000)
+    """k-mer keys hash-partitioned into 64 sets and built as one batch: each label is a bijection
+    within its set, and sampled sets equal the oracle built on the keys the oracle assigns to them
+    (top 6 bits of fmix64(x ^ seed))."""
+    kn = oracle_kmer_keys(1_000_050, 12, 1_000_000)
+    keys = torch.from_numpy(kn.view(np.int64)).cuda()
     grouped, off = M.partition_sets(keys, 6, seed=5)
+    sid = (O.fmix64(kn ^ np.uint64(5)) >> np.uint64(58)).astype(np.int64)
+    assert np.array_equal(np.diff(off.cpu().numpy()), np.bincount(sid, minlength=64))
     b = M.build_batch(grouped, off, 2.0, 0)
     ids = M.set_ids(keys, 6, seed=5)
+    assert np.array_equal(ids.cpu().numpy(), sid)
     lab = b.lookup(ids, keys)
     glob = off[ids] + lab - 1
     assert torch.equal(torch.sort(glob).values, torch.arange(keys.numel(), device=glob.device))
+    labn = host(lab)
     for s in (0, 17, 63):
-        ks = host(grouped[int(off[s]):int(off[s + 1])])
+        ks = kn[sid == s]
         st = O.build(ks, 2.0, 0)
         assert np.array_equal(b.export_set(s)["words"], st.words)
+        assert np.array_equal(labn[sid == s], O.lookup(st, ks))

@@ -26,44 +26,7 @@ def M():
     return mphf
 
 
-def host(t):
-    return t.cpu().numpy().view(np.uint64)
-
-
-def check_against_oracle(M, keys_np, gamma, seed=0, max_levels=25, rank_sample=512,
-                         queries_np=None):
-    keys = torch.from_numpy(keys_np.view(np.int64)).cuda()
-    h = M.build(keys, gamma, seed, max_levels=max_levels, rank_sample=rank_sample,
-                keep_collisions=True)
-    st = O.build(keys_np, gamma, seed, max_levels=max_levels, rank_sample=rank_sample)
-    s = h.stats()
-    assert s["num_levels"] == st.num_levels
-    assert s["level_n"] == [l.n for l in st.levels]
-    assert s["level_m"] == [l.m for l in st.levels]
-    assert s["level_weight"] == [l.weight for l in st.levels]
-    assert s["level_offset"] == [l.offset for l in st.levels]
-    assert s["level_seed"] == [l.seed for l in st.levels]
-    assert s["total_bits"] == st.total_bits
-    assert s["n_fallback"] == len(st.fallback_keys)
-    ex = h.export()
-    assert np.array_equal(ex["words"], st.words)
-    assert np.array_equal(ex["rank"], st.rank)
-    assert np.array_equal(ex["fallback_keys"], st.fallback_keys)
-    for d in range(st.num_levels):
-        assert np.array_equal(h.export_collisions(d), O.collision_words(st, d)), d
-    lab = host(h.lookup(keys))
-    want = O.lookup(st, keys_np)
-    assert np.array_equal(lab, want)
-    if queries_np is not None:
-        q = torch.from_numpy(queries_np.view(np.int64)).cuda()
-        assert np.array_equal(host(h.lookup(q)), O.lookup(st, queries_np))
-    assert abs(s["bits_per_key"] - st.bits_per_key) < 1e-9
-    h.close()
-    return st
-
-
-def keys_np(n, seed=1):
-    return I.keys(n, seed).numpy().view(np.uint64)
+from tests.parity import check_against_oracle, host, keys_np  # noqa: E402
 
 
 # ------------------------------------------------------------ hash + exact mod
@@ -246,10 +209,52 @@ def unfmix64(y):
     return z ^ (z >> 33)
 
 
+def test_parity_one_pass_partition_with_wide_digits(M):
+    """N = 5e6 at gamma 2: level 0 has ceil(1e7 / 2^15) = 306 buckets of the default size, more
+    than 256 and at most 1024, so one radix pass with 10-bit digits."""
+    def want(p):
+        assert p[0] == "one_pass" and p[-1] == "tail", p
+    check_against_oracle(M, keys_np(5_000_000, seed=21), 2.0, paths=want)
+
+
 @pytest.mark.parametrize("gamma", [1.0, 2.0])
 def test_parity_two_pass_partition(M, gamma):
-    """N = 5e6: more than 256 position buckets at level 0, so two radix passes."""
-    check_against_oracle(M, keys_np(5_000_000, seed=21), gamma)
+    """N = 2e7: level 0 has ceil(gamma 2e7 / 2^b) = 1221 buckets of the default size (b = 14 at
+    gamma 1, 15 at gamma 2), more than 1024, so a pass into coarse bins and a second pass into the
+    buckets; the later levels take one pass, then the one-workgroup tail."""
+    def want(p):
+        assert p[0] == "two_pass" and "one_pass" in p and p[-1] == "tail", p
+    check_against_oracle(M, keys_np(20_000_000, seed=21), gamma, paths=want)
+
+
+@pytest.mark.parametrize("n,gamma,bits,first", [
+    (5_000_000, 2.0, 10, "two_pass"),          # 9766 buckets: 2^6 buckets per coarse bin
+    (5_000_000, 1.0, 8, "two_pass"),           # 19532 buckets: 2^7 per coarse bin
+    (10_000_000, 2.0, 8, "two_pass_wide"),     # 78125 buckets: 2^9 per coarse bin (10-bit pass)
+    (10_000_000, 2.0, 7, "two_pass_wide"),     # 156250 buckets: 2^10 per coarse bin
+    (10_000_000, 2.0, 6, "atomic"),            # 312500 > 2^18 buckets: global atomics
+])
+def test_parity_small_buckets(M, n, gamma, bits, first):
+    """Buckets smaller than the default make the level of a small key set as many buckets as a
+    level of 1e9-1e10 keys has: the two-pass partition with 2^9 and 2^10 buckets per coarse bin
+    (which the default buckets need only past about 2.1e9 keys per level), and past 2^18 buckets
+    the global-atomic levels.  Every bit, counter and label must still equal the oracle's."""
+    def want(p):
+        assert p[0] == first, p
+        if first != "atomic":
+            assert "one_pass" in p and p[-1] == "tail", p
+        else:
+            assert set(p) == {"atomic"}, p
+    check_against_oracle(M, keys_np(n, seed=22 + bits), gamma, bucket_bits=bits, paths=want,
+                         queries_np=keys_np(20_000, seed=99))
+
+
+def test_bucket_bits_rejected_when_too_large(M):
+    t = torch.from_numpy(keys_np(1000).view(np.int64)).cuda()
+    for bits in (5, 17, 16):          # 2^16 positions at gamma 2: 32768 keys, more than fit
+        with pytest.raises(M.MphfError) as e:
+            M.build(t, 2.0, bucket_bits=bits)
+        assert e.value.status == M.E_INVALID
 
 
 @pytest.mark.parametrize("n,gamma", [(1000, 2.0), (100_000, 2.0), (1_000_000, 1.0)])
@@ -257,12 +262,8 @@ def test_parity_atomic_levels(M, n, gamma):
     """The global-atomic build (MPHF_FLAG_ATOMIC_LEVELS) gives the same structure."""
     k = keys_np(n, seed=8)
     t = torch.from_numpy(k.view(np.int64)).cuda()
-    import ctypes
-    o = M.Opts(25, 512, 0, 0, 1)
-    h = ctypes.c_void_p()
-    st = M.lib().mphf_build_ex(t.data_ptr(), n, gamma, 0, ctypes.byref(o), None, ctypes.byref(h))
-    assert st == 0
-    ha = M.MPHF(h.value, t.device)
+    ha = M.build(t, gamma, 0, atomic_levels=True)
+    assert set(ha.stats()["level_path"]) == {"atomic"}
     hb = M.build(t, gamma, 0)
     assert ha.stats()["level_n"] == hb.stats()["level_n"]
     assert np.array_equal(ha.export()["words"], hb.export()["words"])
