@@ -368,6 +368,17 @@ mphf_status mphf_partition_sets(const uint64_t* keys, uint64_t n, uint32_t bits,
 mphf_status mphf_set_ids(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed, uint64_t* out,
                          void* stream);
 
+/* mphf_partition_sets for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same sets and offsets, with no device
+ * allocation and no host synchronization.  Its scratch (per-set counts and cursors, about 770 KiB)
+ * is a fixed array of the library that each device holds until the process ends, so 1 <= bits <= 16
+ * (MPHF_E_INVALID beyond).  The caller passes the keys, out (n keys) and offsets (2^bits + 1 u64),
+ * all device memory.  Asynchronous on `stream`.  Every call on a device shares that device's
+ * scratch: calls that overlap on one device (on different streams or threads) race and must be
+ * serialized by the caller.  The order of the keys inside a set is unspecified. */
+mphf_status mphf_partition_sets_noalloc(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed,
+                                        uint64_t* out, uint64_t* offsets, void* stream);
+
 /* Free the build temporaries the library keeps per device between builds (a few times the
  * largest key set built so far).  Must not overlap a build. */
 mphf_status mphf_trim(void);

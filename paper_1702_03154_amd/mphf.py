@@ -128,6 +128,7 @@ def lib() -> C.CDLL:
             "mphf_first_occurrences": (st, [vp, u64, u64, vp, C.POINTER(C.c_uint64), vp]),
             "mphf_partition_sets": (st, [vp, u64, u32, u64, vp, vp, vp]),
             "mphf_set_ids": (st, [vp, u64, u32, u64, vp, vp]),
+            "mphf_partition_sets_noalloc": (st, [vp, u64, u32, u64, vp, vp, vp]),
             "mphf_server_default_opts": (st, [C.POINTER(ServerOpts)]),
             "mphf_server_create": (st, [C.POINTER(ServerOpts), C.POINTER(vp)]),
             "mphf_server_register": (st, [vp, vp, C.POINTER(C.c_uint32)]),
@@ -437,6 +438,21 @@ def partition_sets(keys: torch.Tensor, bits: int, seed: int = 0, stream=None):
     _check(lib().mphf_partition_sets(kp, keys.numel(), bits, seed & (2**64 - 1), op, _dev(off, "offsets"),
                                      _stream(stream)))
     return out, off
+
+
+def partition_sets_noalloc(keys: torch.Tensor, bits: int, seed: int = 0, out: torch.Tensor | None = None,
+                           offsets: torch.Tensor | None = None, stream=None):
+    """mphf_partition_sets_noalloc: the library allocates nothing (its scratch is a fixed device
+    array); the caller's out and offsets tensors receive the result, asynchronously on the stream."""
+    if out is None:
+        out = torch.empty_like(keys)
+    if offsets is None:
+        offsets = torch.empty((1 << bits) + 1, dtype=torch.int64, device=keys.device)
+    kp = _dev(keys, "keys") if keys.numel() else 0
+    op = _dev(out, "out") if keys.numel() else 0
+    _check(lib().mphf_partition_sets_noalloc(kp, keys.numel(), bits, seed & (2**64 - 1), op,
+                                             _dev(offsets, "offsets"), _stream(stream)))
+    return out, offsets
 
 
 def set_ids(keys: torch.Tensor, bits: int, seed: int = 0, stream=None) -> torch.Tensor:
