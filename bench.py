@@ -2,12 +2,23 @@
 
 Default workload (plain): one step = one build (every level, the fallback table
 and the rank table) of N distinct 64-bit keys already resident in HBM, followed
-by the lookup of all N keys in a seeded shuffled order.
+by the lookup of all N keys in a seeded shuffled order.  The JSON line also
+carries, each measured in the same run:
 
---workload batch: one step = one batched build of 65,536 independent sets with
-log-uniform sizes in [16, 65536] (seeded) plus the lookup of every key of every
-set, shuffled, beside the same work done by a loop of plain per-set builds and
-lookups over a seeded sample of the sets.
+* roofline: the lookup (the dominant kernel) against HBM on its algorithmic
+  bytes (16 per query), its random probes against the measured random-sector
+  rate at the structure's footprint, and the lower bound T_lb over the measured
+  time; build_roofline the same for the build;
+* gamma1: the same build and lookup at gamma = 1;
+* batched: 65,536 independent sets (log-uniform sizes in [16, 65536]) built in
+  one launch and looked up, beside a loop of plain per-set builds and lookups;
+* served: 64 resident functions answering Poisson-arriving requests from host
+  memory through the serving loop, beside plain per-request lookups, with p50/p99
+  latency at fractions of the served and of the plain capacity;
+* cpu_baseline: the oracle (numpy, one core) on a sample, and the threaded CPU
+  build and lookup in the paper's style on every host core on the whole workload.
+
+--workload batch / serve: those parts alone (batch with the optional --tune).
 
 --workload kmer: the first 4e9 distinct canonical 31-mers of a 4.2e9-base random
 DNA sequence (32 GB of keys in HBM); plain build + lookup and the batched path
@@ -21,10 +32,9 @@ lookup of every key, regenerated chunk by chunk.
 --workload gamma: the plain build + lookup for gamma in 1..10 and with 1024-bit rank
 sampling, beside the space analysis (bits/key, probes per query).
 
---workload serve: 64 resident functions (log-uniform sizes in [1e6, 1e9]) answer
-Poisson-arriving lookup requests from host memory through the serving loop;
-throughput at saturation and p50/p99 latency at 0.5/0.8/0.95 of the plain
-per-request capacity, beside plain per-request lookups.
+--workload roofline: the memory-system microbenchmarks (streaming read and copy,
+random 8-byte and 64-byte-sector reads, random global and LDS atomicOr with
+return) over footprints from LDS to 5 GB.
 
 Prints one JSON line.
 """
@@ -41,8 +51,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 LINE_BYTES = 128               # a random read on gfx950 moves one 128-byte line from HBM (measured)
+LOOKUP_BYTES_PER_QUERY = 16.0  # the lookup's algorithmic bytes: the key read, the label written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lookup_traffic.json")
 BUILD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "build_1e9_gamma2_traffic.json")
+METRIC = "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain"
+
+
+def log(msg: str):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def mean_probes(st) -> float:
@@ -95,6 +111,38 @@ def build_algorithmic_bytes(st) -> float:
     return 8.0 * sum(nd) + 8.0 * survivors + st["total_bits"] / 8.0 + 8.0 * st["rank_entries"]
 
 
+def build_random_ops(st) -> int:
+    """The method's random accesses in one build: every key of every level is one test-and-set of
+    its position (Algorithm 2) and one read of its bit by the filter (Algorithm 1)."""
+    return 2 * sum(st["level_n"][:st["num_levels"]])
+
+
+# ---------------------------------------------------------------- host description and CPU baselines
+
+def host_info() -> dict:
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            models = [l.split(":", 1)[1].strip() for l in f if l.startswith("model name")]
+        if models:
+            info["cpu_model"] = models[0]
+            info["logical_cpus_listed"] = len(models)
+    except OSError:
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            for l in f:
+                if l.startswith("MemTotal"):
+                    info["mem_total_gib"] = round(int(l.split()[1]) / 2**20, 1)
+    except OSError:
+        pass
+    return info
+
+
 def cpu_baseline(n: int, gamma: float):
     """The oracle as it stands, on a bounded sample of the same workload, one host core."""
     import numpy as np
@@ -115,6 +163,30 @@ def cpu_baseline(n: int, gamma: float):
             "build_keys_per_s": n / (t1 - t0), "lookup_queries_per_s": n / (t2 - t1)}
 
 
+def threaded_baseline(keys_host, queries_host, gamma: float):
+    """The paper-style parallel CPU build (keys split over threads, atomic fetch-or on the shared
+    bit arrays) and lookup on every usable host core, on the whole workload."""
+    import numpy as np
+
+    from oracle import threaded as T
+
+    n = len(keys_host)
+    t0 = time.perf_counter()
+    f = T.Threaded(keys_host, gamma, 0)
+    t1 = time.perf_counter()
+    lab = f.lookup(queries_host)
+    t2 = time.perf_counter()
+    levels = f.sizes()[0]
+    f.close()
+    ok = int(lab.min()) == 1 and int(lab.max()) == n
+    del lab
+    return {"value": n / (t2 - t0), "unit": "keys/s", "cores": f.threads, "kind": "threaded",
+            "sample": f"the whole workload: {n} keys, gamma={gamma}, build + shuffled lookup of all keys",
+            "build_keys_per_s": n / (t1 - t0), "lookup_queries_per_s": n / (t2 - t1),
+            "build_s": t1 - t0, "lookup_s": t2 - t1, "levels": levels, "labels_in_range": ok,
+            "what": "std::thread over key chunks, __atomic_fetch_or on shared A_d and C_d (Section 3.2)"}
+
+
 def calibrate_copy():
     """One plain 1 GiB device-to-device copy: a kernel of known traffic for scaling HBM counters."""
     import torch
@@ -125,7 +197,67 @@ def calibrate_copy():
     del src, dst
 
 
-def bench_batch(args):
+# ---------------------------------------------------------------- roofline probes
+
+def probe_rate(kind: str, nbytes: int, ops: int = 0, reps: int = 3) -> dict:
+    """Median rate of one microbenchmark (bytes/s for the streaming kinds, operations/s for the
+    random ones), timed with events on the stream it is launched on."""
+    import statistics
+
+    import torch
+
+    from paper_1702_03154_amd import mphf
+
+    dev = torch.device("cuda:0")
+    buf = dst = None
+    if kind != "lds_atomic_or":
+        buf = torch.zeros((nbytes + 63) // 8 + 8, dtype=torch.int64, device=dev)
+        if kind == "stream_copy":
+            dst = torch.empty_like(buf)
+    s = torch.cuda.current_stream()
+    times, done = [], 0
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        done = mphf.probe(kind, buf, nbytes, dst, ops, seed=r + 1)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if r:
+            times.append(e0.elapsed_time(e1) / 1e3)
+    t = statistics.median(times)
+    del buf, dst
+    if kind in ("stream_read", "stream_copy"):
+        moved = nbytes * (2 if kind == "stream_copy" else 1)
+        return {"kind": kind, "footprint_bytes": nbytes, "bytes_per_s": moved / t, "ms": t * 1e3}
+    return {"kind": kind, "footprint_bytes": nbytes, "ops": done, "ops_per_s": done / t, "ms": t * 1e3}
+
+
+def bench_roofline(args):
+    """The microbenchmark sweep: each random kind over LDS / L2 / MALL / HBM footprints."""
+    foot = [("L2 (4 MiB)", 4 << 20), ("MALL (256 MiB)", 256 << 20), ("HBM (5 GiB)", 5 << 30)]
+    rows = [probe_rate("stream_read", 8 << 30), probe_rate("stream_copy", 4 << 30)]
+    for kind in ("random_read8", "random_sector64", "random_atomic_or"):
+        for name, b in foot:
+            r = probe_rate(kind, b, ops=1 << 29)
+            r["footprint"] = name
+            rows.append(r)
+            log(f"{kind} over {name}: {r['ops_per_s']:.3e} ops/s")
+    for b in (8192, 49152):
+        r = probe_rate("lds_atomic_or", b, ops=1 << 32)
+        r["footprint"] = f"LDS ({b // 1024} KiB per workgroup)"
+        rows.append(r)
+    res = {"metric": METRIC, "value": rows[1]["bytes_per_s"], "unit": "bytes/s",
+           "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": rows[1]["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "memory-system microbenchmarks: streaming read and copy, random 8-byte and "
+                                  "64-byte-sector reads, random atomicOr with return (global and LDS)"},
+           "rows": rows}
+    print(json.dumps(res))
+
+
+# ---------------------------------------------------------------- batched builds
+
+def run_batch(args, steps: int, warmup: int, graph: bool = True) -> dict:
     """Batched build + lookup of many independent sets against a loop of plain per-set calls."""
     import statistics
 
@@ -147,20 +279,20 @@ def bench_batch(args):
     del pi
     out = torch.empty(total, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-    print(f"# inputs ready: {nsets} sets, {total} keys", file=sys.stderr, flush=True)
+    log(f"batch inputs ready: {nsets} sets, {total} keys")
 
     launch, tune_rec = None, None
-    if args.tune:
+    if getattr(args, "tune", False):
         from paper_1702_03154_amd import autotune
         launch = autotune.batch_launch(off, args.gamma, verbose=True)
         cache = autotune._load()
         tune_rec = cache.get(autotune.device_key(), {}).get(autotune.workload_key(off, args.gamma, 25))
-        print(f"# tuned launch {launch}", file=sys.stderr, flush=True)
+        log(f"tuned launch {launch}")
 
     s = torch.cuda.current_stream()
     build_ms, lookup_ms, step_ms = [], [], []
     tot = None
-    for it in range(args.warmup + args.steps):
+    for it in range(warmup + steps):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         torch.cuda.synchronize()
         e0.record(s)
@@ -169,46 +301,50 @@ def bench_batch(args):
         b.lookup(q_ids, q_keys, out=out)
         e2.record(s)
         torch.cuda.synchronize()
-        if it >= args.warmup:
+        if it >= warmup:
             build_ms.append(e0.elapsed_time(e1))
             lookup_ms.append(e1.elapsed_time(e2))
             step_ms.append(e0.elapsed_time(e2))
         if tot is None:
             tot = b.totals()
         b.close()
-        print(f"# step {it}: batch build {e0.elapsed_time(e1):.3f} ms lookup {e1.elapsed_time(e2):.3f} ms",
-              file=sys.stderr, flush=True)
-    # the planned batch: rebuild + lookup captured once in a HIP graph and replayed
-    plan = mphf.Batch.plan(off, args.gamma, 0, launch=launch)
-    plan.rebuild(keys).lookup(q_ids, q_keys, out=out)
-    plan.status()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        plan.rebuild(keys)
-        plan.lookup(q_ids, q_keys, out=out)
-    graph_ms = []
-    for it in range(args.warmup + args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        log(f"batch step {it}: build {e0.elapsed_time(e1):.3f} ms lookup {e1.elapsed_time(e2):.3f} ms")
+    graph_rec = None
+    if graph:
+        # the planned batch: rebuild + lookup captured once in a HIP graph and replayed
+        plan = mphf.Batch.plan(off, args.gamma, 0, launch=launch)
+        plan.rebuild(keys).lookup(q_ids, q_keys, out=out)
+        plan.status()
         torch.cuda.synchronize()
-        e0.record(s)
-        g.replay()
-        e1.record(s)
-        torch.cuda.synchronize()
-        if it >= args.warmup:
-            graph_ms.append(e0.elapsed_time(e1))
-    plan.status()
-    del g
-    plan.close()
-    print(f"# graph replay {statistics.median(graph_ms):.3f} ms", file=sys.stderr, flush=True)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            plan.rebuild(keys)
+            plan.lookup(q_ids, q_keys, out=out)
+        graph_ms = []
+        for it in range(warmup + steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(s)
+            g.replay()
+            e1.record(s)
+            torch.cuda.synchronize()
+            if it >= warmup:
+                graph_ms.append(e0.elapsed_time(e1))
+        plan.status()
+        del g
+        plan.close()
+        gm = statistics.median(graph_ms)
+        log(f"graph replay {gm:.3f} ms")
+        graph_rec = {"value": total / (gm / 1e3), "unit": "keys/s", "ms": gm,
+                     "what": "planned batch: rebuild + lookup captured in one HIP graph, replayed"}
 
     # labels of every set are a bijection onto [1, n_s]: offset + label - 1 covers [0, total)
-    g = off[q_ids] + out - 1
+    gidx = off[q_ids] + out - 1
     seen = torch.zeros(total, dtype=torch.int8, device=dev)
-    ok = bool(((out >= 1) & (g < off[q_ids + 1])).all())
-    seen[g] = 1
+    ok = bool(((out >= 1) & (gidx < off[q_ids + 1])).all())
+    seen[gidx] = 1
     ok = ok and bool(seen.all())
-    del seen, g
+    del seen, gidx
 
     # the same work as a loop of plain one-set-per-launch calls, over a seeded sample of the sets
     sample = inputs.feistel_permutation(nsets, seed=6)[: int(args.plain_sample)].tolist()
@@ -226,15 +362,9 @@ def bench_batch(args):
     plain_s = time.perf_counter() - t0
 
     tb, tl = statistics.median(build_ms), statistics.median(lookup_ms)
-    total_ms = sum(step_ms)
-    value = total * args.steps / (total_ms / 1e3)
-    res = {
-        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
-        "value": value, "unit": "keys/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
+    value = total * steps / (sum(step_ms) / 1e3)
+    return {
+        "value": value, "unit": "keys/s", "ms_per_step": sum(step_ms) / steps, "steps": steps, "warmup": warmup,
         "config": {"workload": f"batched build + shuffled lookup of {nsets} independent sets, sizes "
                                f"log-uniform in [16, 65536] (seed 3), keys SplitMix64 per set (seed 4), "
                                f"gamma={args.gamma}", "sets": nsets, "keys": total, "gamma": args.gamma},
@@ -242,9 +372,7 @@ def bench_batch(args):
         "build_ms": tb, "lookup_ms": tl,
         "labels_bijective_per_set": ok,
         "bits_per_key": tot["bits_per_key"],
-        "graph_replay": {"value": total / (statistics.median(graph_ms) / 1e3), "unit": "keys/s",
-                         "ms": statistics.median(graph_ms),
-                         "what": "planned batch: rebuild + lookup captured in one HIP graph, replayed"},
+        "graph_replay": graph_rec,
         "launch": list(launch) if launch else "default (256 threads, 8 keys in flight)",
         "tuning": tune_rec and {"ms": tune_rec["ms"], "default_ms": tune_rec["default_ms"]},
         "plain_loop": {"value": plain_keys / plain_s, "unit": "keys/s", "sets": len(sample),
@@ -253,14 +381,23 @@ def bench_batch(args):
                                  "one lookup of its keys, host-timed including every launch"},
         "batched_over_plain": value / (plain_keys / plain_s),
     }
+
+
+def bench_batch(args):
+    r = run_batch(args, args.steps, args.warmup)
+    res = {"metric": METRIC, "value": r["value"], "unit": "keys/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": r["config"]}
+    res.update({k: v for k, v in r.items() if k not in res and k not in ("steps",)})
     print(json.dumps(res))
 
 
-def bench_serve(args):
-    """Serving: many resident functions, Poisson-arriving lookup requests from host memory, batched
-    as they arrive; p50/p99 latency and throughput beside plain per-request lookups."""
-    import threading
+# ---------------------------------------------------------------- serving
 
+def run_serve(args) -> dict:
+    """Serving: many resident functions, Poisson-arriving lookup requests from host memory, batched
+    as they arrive; throughput at saturation and p50/p99 latency at fractions of the served and of
+    the plain capacity, beside plain per-request lookups."""
     import numpy as np
     import torch
 
@@ -282,8 +419,8 @@ def bench_serve(args):
         fns.append(h)
         struct_bytes += h.stats()["structure_bytes"]
     torch.cuda.synchronize()
-    print(f"# {nfn} functions built ({sum(sizes)} keys, {struct_bytes / 2**30:.2f} GiB) in "
-          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    log(f"{nfn} functions built ({sum(sizes)} keys, {struct_bytes / 2**30:.2f} GiB) in "
+        f"{time.perf_counter() - t0:.1f} s")
 
     # requests: sizes floor(1e6^u), function uniform, 90% present keys (a uniform index into the
     # function's key stream), 10% absent keys (a separate stream); all in pinned host memory
@@ -313,10 +450,9 @@ def bench_serve(args):
         qs.append(hq)
         outs.append(ho)
     total_keys = sum(rsize)
-    print(f"# {R} requests, {total_keys} keys", file=sys.stderr, flush=True)
+    log(f"{R} requests, {total_keys} keys")
 
     # plain: one lookup per request, each copied in, labelled, copied out and waited for
-    s = torch.cuda.current_stream()
     dq = torch.empty(max(rsize) + 1, dtype=torch.int64, device=dev)
     do = torch.empty_like(dq)
     plain_lab = []
@@ -333,7 +469,7 @@ def bench_serve(args):
     plain_rps = R / plain_s
     for i in range(R):
         plain_lab.append(outs[i].a.copy())
-    print(f"# plain: {plain_rps:.0f} requests/s, {total_keys / plain_s:.3e} keys/s", file=sys.stderr, flush=True)
+    log(f"plain: {plain_rps:.0f} requests/s, {total_keys / plain_s:.3e} keys/s")
 
     server = mphf.Server(hbm_budget=int(args.hbm_budget), max_inflight=int(args.inflight))
     ids = [server.register(h) for h in fns]
@@ -360,21 +496,25 @@ def bench_serve(args):
                 "equal_to_plain": ok}
 
     sat = run(0)
-    print(f"# served at saturation: {sat['requests_per_s']:.0f} requests/s, p50 {sat['p50_us']:.0f} us",
-          file=sys.stderr, flush=True)
-    loads = {}
+    sat_rps = sat["requests_per_s"]
+    log(f"served at saturation: {sat_rps:.0f} requests/s, p50 {sat['p50_us']:.0f} us")
+    # the latency-throughput curve: Poisson arrivals at fractions of the served saturation rate,
+    # and at the rates plain per-request lookups could sustain
+    of_served, of_plain = {}, {}
+    for f in (0.25, 0.5, 0.8, 0.95):
+        of_served[str(f)] = run(f * sat_rps)
+        log(f"load {f} of served: p50 {of_served[str(f)]['p50_us']:.0f} us p99 {of_served[str(f)]['p99_us']:.0f} us")
     for f in (0.5, 0.8, 0.95):
-        loads[str(f)] = run(f * plain_rps)
-        print(f"# load {f}: p50 {loads[str(f)]['p50_us']:.0f} us p99 {loads[str(f)]['p99_us']:.0f} us",
-              file=sys.stderr, flush=True)
+        of_plain[str(f)] = run(f * plain_rps)
+        log(f"load {f} of plain: p50 {of_plain[str(f)]['p50_us']:.0f} us p99 {of_plain[str(f)]['p99_us']:.0f} us")
     st = server.stats()
     server.close()
-    res = {
-        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
-        "value": sat["keys_per_s"], "unit": "keys/s",
-        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * total_keys / sat["keys_per_s"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
+    for o in qs + outs:
+        o.close()
+    for h in fns:
+        h.close()
+    return {
+        "value": sat["keys_per_s"], "unit": "keys/s", "ms_per_step": 1e3 * total_keys / sat["keys_per_s"],
         "config": {"workload": f"serving: {nfn} resident functions, sizes floor(1e6*1000^u*{args.serve_scale}) "
                                f"(seed 6), gamma=2; {R} requests of floor(1e6^u) keys (seed 8), 90% present, "
                                f"10% absent, from pinned host memory",
@@ -384,11 +524,18 @@ def bench_serve(args):
         "plain": {"requests_per_s": plain_rps, "keys_per_s": total_keys / plain_s,
                   "what": "per request: copy in, lookup, copy out, wait"},
         "served_saturation": sat, "served_over_plain": sat["keys_per_s"] / (total_keys / plain_s),
-        "poisson_loads_of_plain_capacity": loads,
+        "poisson_loads_of_served_capacity": of_served,
+        "poisson_loads_of_plain_capacity": of_plain,
         "server_stats": st,
     }
-    for o in qs + outs:
-        o.close()
+
+
+def bench_serve(args):
+    r = run_serve(args)
+    res = {"metric": METRIC, "value": r["value"], "unit": "keys/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64", "data": "synthetic", "config": r["config"]}
+    res.update({k: v for k, v in r.items() if k not in res})
     print(json.dumps(res))
 
 
@@ -485,7 +632,7 @@ def bench_kmer(args):
     tb, tl = statistics.median(build_ms), statistics.median(lookup_ms)
     bb, bl = statistics.median(bb_ms), statistics.median(bl_ms)
     res = {
-        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "metric": METRIC,
         "value": n / ((tb + tl) / 1e3), "unit": "keys/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb + tl,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -558,7 +705,7 @@ def bench_stream(args):
     streamed = sum(1 for x in st["level_n"][:st["num_levels"]] if x > resident)
     tb = statistics.median(build_ms)
     res = {
-        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "metric": METRIC,
         "value": n / ((tb + lookup_ms) / 1e3), "unit": "keys/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb + lookup_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -625,7 +772,7 @@ def bench_gamma(args):
               file=sys.stderr, flush=True)
     base = next(r for r in rows if r["gamma"] == 2.0 and r["rank_sample"] == 512)
     res = {
-        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "metric": METRIC,
         "value": n / ((base["build_ms"] + base["lookup_ms"]) / 1e3), "unit": "keys/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": base["build_ms"] + base["lookup_ms"],
@@ -637,9 +784,38 @@ def bench_gamma(args):
     print(json.dumps(res))
 
 
+
+
+def plain_steps(mphf, keys, queries, out, gamma, steps, warmup, tag=""):
+    """`warmup` + `steps` build + lookup steps; per-step event times on the current stream."""
+    import torch
+    s = torch.cuda.current_stream()
+    build_ms, lookup_ms, step_ms = [], [], []
+    stats = None
+    for it in range(warmup + steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(s)
+        h = mphf.build(keys, gamma, 0)
+        e1.record(s)
+        h.lookup(queries, out=out)
+        e2.record(s)
+        torch.cuda.synchronize()
+        if it >= warmup:
+            build_ms.append(e0.elapsed_time(e1))
+            lookup_ms.append(e1.elapsed_time(e2))
+            step_ms.append(e0.elapsed_time(e2))
+        if stats is None:
+            stats = h.stats()
+        h.close()
+        log(f"{tag}step {it}: build {e0.elapsed_time(e1):.3f} ms lookup {e1.elapsed_time(e2):.3f} ms")
+    return build_ms, lookup_ms, step_ms, stats
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer", "stream", "gamma"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer", "stream", "gamma", "roofline"],
+                    default="plain")
     ap.add_argument("--resident-keys", type=float, default=2 ** 31, help="stream: survivors kept in memory")
     ap.add_argument("--kmer-bases", type=float, default=4.2e9, help="kmer: sequence length")
     ap.add_argument("--kmer-keys", type=float, default=4e9, help="kmer: distinct k-mers kept")
@@ -659,6 +835,8 @@ def main():
     ap.add_argument("--gamma", type=float, default=2.0)
     ap.add_argument("--cpu-sample", type=float, default=1e8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="plain: only the timed steps and the roofline (no gamma1, batched, served parts)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a known-size kernel for counter scaling)")
     args = ap.parse_args()
@@ -668,23 +846,18 @@ def main():
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
-    if args.workload == "batch":
-        bench_batch(args)
-        return
-    if args.workload == "serve":
-        bench_serve(args)
-        return
-    if args.workload == "kmer":
-        bench_kmer(args)
-        return
-    if args.workload == "gamma":
-        bench_gamma(args)
+    workloads = {"batch": bench_batch, "serve": bench_serve, "kmer": bench_kmer, "gamma": bench_gamma,
+                 "roofline": bench_roofline}
+    if args.workload in workloads:
+        workloads[args.workload](args)
         return
     if args.workload == "stream":
         if args.n == 1e9:
             args.n = 1e10
         bench_stream(args)
         return
+
+    import statistics
 
     import torch
 
@@ -697,44 +870,68 @@ def main():
     queries = inputs.shuffled_queries(keys, seed=2)
     out = torch.empty(n, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-    print(f"# inputs ready: {n} keys", file=sys.stderr, flush=True)
+    log(f"inputs ready: {n} keys")
 
-    s = torch.cuda.current_stream()
-    build_ms, lookup_ms, step_ms = [], [], []
-    stats = None
-    for it in range(args.warmup + args.steps):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        torch.cuda.synchronize()
-        e0.record(s)
-        h = mphf.build(keys, args.gamma, 0)
-        e1.record(s)
-        h.lookup(queries, out=out)
-        e2.record(s)
-        torch.cuda.synchronize()
-        if it >= args.warmup:
-            build_ms.append(e0.elapsed_time(e1))
-            lookup_ms.append(e1.elapsed_time(e2))
-            step_ms.append(e0.elapsed_time(e2))
-        if stats is None:
-            stats = h.stats()
-        h.close()
-        print(f"# step {it}: build {e0.elapsed_time(e1):.3f} ms lookup {e1.elapsed_time(e2):.3f} ms",
-              file=sys.stderr, flush=True)
+    build_ms, lookup_ms, step_ms, stats = plain_steps(mphf, keys, queries, out, args.gamma, args.steps,
+                                                      args.warmup)
     ok = bool(torch.equal(torch.sort(out).values, torch.arange(1, n + 1, device=dev)))
-
-    import statistics
-    tb, tl, ts = (statistics.median(x) for x in (build_ms, lookup_ms, step_ms))
+    tb, tl = (statistics.median(x) for x in (build_ms, lookup_ms))
     total_ms = sum(step_ms)
-    # Dominant kernel: the lookup (one launch, timed with events on its stream).  Algorithmic
-    # bytes per query: the key read, the label written, and one 128-byte HBM line per probe.
+
+    # ---- roofline of the lookup (the dominant kernel: one launch, timed with events on its stream)
     probes = mean_probes(stats)
-    lookup_bytes = n * (16.0 + LINE_BYTES * probes)
-    achieved = lookup_bytes / (tl / 1e3) / 1e9
-    traffic = measured_traffic(n)
-    build_bytes = build_algorithmic_bytes(stats)
-    build_traffic = measured_build_traffic(n)
+    foot = int(stats["lookup_bytes"])
+    sec_rate = probe_rate("random_sector64", foot, ops=1 << 29)
+    line_rate = probe_rate("random_read8", foot, ops=1 << 29)
+    copy_rate = probe_rate("stream_copy", 4 << 30)
+    lk_bytes = n * LOOKUP_BYTES_PER_QUERY
+    lk_ops = n * probes
+    t_stream = lk_bytes / (HBM_PEAK_GBS * 1e9)
+    t_rand = lk_ops / sec_rate["ops_per_s"]
+    t_lb = max(t_stream, t_rand)
+    achieved = lk_bytes / (tl / 1e3) / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(n), "kernel": "k_lookup",
+        "algorithmic_bytes_per_query": LOOKUP_BYTES_PER_QUERY,
+        "random": {"ops_per_query": probes, "ops_per_s": lk_ops / (tl / 1e3),
+                   "peak_ops_per_s": sec_rate["ops_per_s"], "frac": lk_ops / (tl / 1e3) / sec_rate["ops_per_s"],
+                   "footprint_bytes": foot,
+                   "what": "level probes (one 64-byte sector each, e^(1/gamma) per member query) against "
+                           "random 64-byte sector reads over the same footprint, measured in this run"},
+        "line_traffic_bytes_per_query": LOOKUP_BYTES_PER_QUERY + LINE_BYTES * probes,
+        "random_read8_ops_per_s": line_rate["ops_per_s"],
+        "stream_copy_gbs": copy_rate["bytes_per_s"] / 1e9,
+        "t_lb_ms": t_lb * 1e3, "t_meas_ms": tl, "t_lb_over_t_meas": t_lb / (tl / 1e3),
+    }
+    log(f"lookup: {achieved:.0f} GB/s algorithmic, probes {lk_ops / (tl / 1e3):.3e}/s of "
+        f"{sec_rate['ops_per_s']:.3e}/s at {foot / 2**20:.0f} MiB; T_lb/T = {t_lb / (tl / 1e3):.3f}")
+
+    # ---- roofline of the build: its streaming bytes, and its random test-and-sets and bit reads,
+    # which the partitioned levels make in LDS (a global test-and-set model is given for context)
+    bb = build_algorithmic_bytes(stats)
+    bops = build_random_ops(stats)
+    lds_rate = probe_rate("lds_atomic_or", 8192, ops=1 << 32)
+    m0 = stats["level_m"][0] if stats["num_levels"] else 1
+    glob_rate = probe_rate("random_atomic_or", 2 * ((m0 + 63) // 64) * 8, ops=1 << 28)
+    tb_stream = bb / (HBM_PEAK_GBS * 1e9)
+    tb_lb = max(tb_stream, bops / lds_rate["ops_per_s"])
+    build_roofline = {
+        "bound": "hbm", "achieved": bb / (tb / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": bb / (tb / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": measured_build_traffic(n),
+        "algorithmic_bytes_per_key": bb / n,
+        "random": {"ops_per_key": bops / n, "lds_peak_ops_per_s": lds_rate["ops_per_s"],
+                   "global_atomic_peak_ops_per_s": glob_rate["ops_per_s"],
+                   "global_atomic_model_ms": 1e3 * bops / glob_rate["ops_per_s"],
+                   "what": "a test-and-set and a filter read per key and level; here made in LDS by the "
+                           "position-partitioned levels; the global-atomic model is the same ops at the "
+                           "measured random atomicOr rate over level 0's A and C"},
+        "t_lb_ms": tb_lb * 1e3, "t_meas_ms": tb, "t_lb_over_t_meas": tb_lb / (tb / 1e3),
+        "stream_copy_frac": bb / (tb / 1e3) / copy_rate["bytes_per_s"],
+    }
+
     res = {
-        "metric": "build keys/s + lookup queries/s (1e9 u64, gamma=2); batched/served vs plain",
+        "metric": METRIC,
         "value": n * args.steps / (total_ms / 1e3),
         "unit": "keys/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -749,22 +946,49 @@ def main():
         "labels_bijective": ok,
         "levels": stats["num_levels"], "bits_per_key": stats["bits_per_key"],
         "n_fallback": stats["n_fallback"], "mean_probes": probes,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "kernel": "k_lookup",
-                     "algorithmic_bytes_per_query": 16.0 + LINE_BYTES * probes},
-        # The build beside the same roofline: the method's own bytes (one pass per level) over
-        # the build time, and the bytes the build's kernels move (two radix passes and the
-        # bucket pass per level instead of global atomics).
-        "build_roofline": {"bound": "hbm", "achieved": build_bytes / (tb / 1e3) / 1e9,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": build_bytes / (tb / 1e3) / 1e9 / HBM_PEAK_GBS,
-                           "traffic": build_traffic,
-                           "algorithmic_bytes_per_key": build_bytes / n},
+        "roofline": roofline,
+        "build_roofline": build_roofline,
     }
+
+    if not args.no_extras:
+        # gamma = 1 on the same keys and queries (the second gamma of the large plain workload)
+        b1, l1, _, st1 = plain_steps(mphf, keys, queries, out, 1.0, 3, 1, tag="gamma 1 ")
+        ok1 = bool(torch.equal(torch.sort(out).values, torch.arange(1, n + 1, device=dev)))
+        t1b, t1l = statistics.median(b1), statistics.median(l1)
+        res["gamma1"] = {"build_keys_per_s": n / (t1b / 1e3), "lookup_queries_per_s": n / (t1l / 1e3),
+                         "build_ms": t1b, "lookup_ms": t1l, "labels_bijective": ok1,
+                         "levels": st1["num_levels"], "bits_per_key": st1["bits_per_key"],
+                         "n_fallback": st1["n_fallback"], "mean_probes": mean_probes(st1), "steps": 3}
+    keys_host = queries_host = None
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(int(args.cpu_sample), args.gamma)
+        import numpy as np
+        keys_host = keys.cpu().numpy().view(np.uint64)
+        queries_host = queries.cpu().numpy().view(np.uint64)
+    del keys, queries, out
+    torch.cuda.empty_cache()
+    mphf.trim()
+
+    if not args.no_extras:
+        rb = run_batch(args, 3, 1, graph=True)
+        res["batched"] = {k: rb[k] for k in ("value", "unit", "config", "build_keys_per_s", "lookup_queries_per_s",
+                                            "build_ms", "lookup_ms", "labels_bijective_per_set", "bits_per_key",
+                                            "graph_replay", "plain_loop", "batched_over_plain")}
+        res["batched_over_plain"] = rb["batched_over_plain"]
+        mphf.trim()
+        torch.cuda.empty_cache()
+        rs = run_serve(args)
+        res["served"] = {k: rs[k] for k in ("value", "unit", "config", "plain", "served_saturation",
+                                            "served_over_plain", "poisson_loads_of_served_capacity",
+                                            "poisson_loads_of_plain_capacity")}
+        res["served_over_plain"] = rs["served_over_plain"]
+
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(int(args.cpu_sample), args.gamma)
+        log(f"cpu oracle: {cb['value']:.3e} keys/s")
+        cb["threaded"] = threaded_baseline(keys_host, queries_host, args.gamma)
+        log(f"cpu threaded: {cb['threaded']['value']:.3e} keys/s on {cb['threaded']['cores']} threads")
+        cb["host"] = host_info()
+        res["cpu_baseline"] = cb
     print(json.dumps(res))
 
 

@@ -379,6 +379,34 @@ mphf_status mphf_set_ids(const uint64_t* keys, uint64_t n, uint32_t bits, uint64
 mphf_status mphf_partition_sets_noalloc(const uint64_t* keys, uint64_t n, uint32_t bits, uint64_t seed,
                                         uint64_t* out, uint64_t* offsets, void* stream);
 
+/* ---- Roofline microbenchmarks ----------------------------------------------------------------
+ * The memory-system ceilings the build and lookup are measured against: the method streams keys and
+ * makes random accesses into bit arrays (a test-and-set per key and level while building,
+ * Algorithm 2; a probe per visited level while querying, Algorithm 3), and random accesses are what
+ * limits it (Section 3.2, "Parallelization"; Section 4.2).  mphf_probe enqueues one probe kernel on
+ * `stream` (asynchronous; time it with events on that stream):
+ *   MPHF_PROBE_STREAM_READ       read `bytes` of buf once (16-byte loads);
+ *   MPHF_PROBE_STREAM_COPY       copy `bytes` from buf to dst;
+ *   MPHF_PROBE_RANDOM_READ8      about `ops` 8-byte reads at random words of the `bytes` of buf;
+ *   MPHF_PROBE_RANDOM_SECTOR64   about `ops` reads of a random aligned 64-byte sector of buf (four
+ *                                16-byte loads, as a lookup probe issues them);
+ *   MPHF_PROBE_RANDOM_ATOMIC_OR  about `ops` atomicOr with the old value returned at random words of
+ *                                buf (the global test-and-set); buf's contents change;
+ *   MPHF_PROBE_LDS_ATOMIC_OR     about `ops` atomicOr with return at random words of `bytes`
+ *                                (4..49152) of each workgroup's LDS; buf and dst are unused.
+ * buf (and dst) are caller-owned device memory, buf 64-byte aligned.  `seed` seeds the random
+ * indices.  mphf_probe_ops(ops) is the exact number of random operations a probe of `ops` performs
+ * (rounded up to whole rounds of the launch). */
+#define MPHF_PROBE_STREAM_READ 0
+#define MPHF_PROBE_STREAM_COPY 1
+#define MPHF_PROBE_RANDOM_READ8 2
+#define MPHF_PROBE_RANDOM_SECTOR64 3
+#define MPHF_PROBE_RANDOM_ATOMIC_OR 4
+#define MPHF_PROBE_LDS_ATOMIC_OR 5
+mphf_status mphf_probe(uint32_t kind, void* buf, uint64_t bytes, void* dst, uint64_t ops, uint64_t seed,
+                       void* stream);
+uint64_t mphf_probe_ops(uint64_t ops);
+
 /* Free the build temporaries the library keeps per device between builds (a few times the
  * largest key set built so far).  Must not overlap a build. */
 mphf_status mphf_trim(void);

@@ -8,7 +8,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = ["kernels.hip", "partition.hip", "batch.hip", "kmer.hip", "stream.hip", "server.hip", "noalloc.hip", "api.hip"]
+SOURCES = ["kernels.hip", "partition.hip", "batch.hip", "kmer.hip", "stream.hip", "server.hip", "noalloc.hip", "probes.hip", "api.hip"]
 LIB = os.path.join(PKG, "libmphf.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 

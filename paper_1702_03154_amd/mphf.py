@@ -129,6 +129,8 @@ def lib() -> C.CDLL:
             "mphf_partition_sets": (st, [vp, u64, u32, u64, vp, vp, vp]),
             "mphf_set_ids": (st, [vp, u64, u32, u64, vp, vp]),
             "mphf_partition_sets_noalloc": (st, [vp, u64, u32, u64, vp, vp, vp]),
+            "mphf_probe": (st, [u32, vp, u64, vp, u64, u64, vp]),
+            "mphf_probe_ops": (u64, [u64]),
             "mphf_server_default_opts": (st, [C.POINTER(ServerOpts)]),
             "mphf_server_create": (st, [C.POINTER(ServerOpts), C.POINTER(vp)]),
             "mphf_server_register": (st, [vp, vp, C.POINTER(C.c_uint32)]),
@@ -461,6 +463,27 @@ def set_ids(keys: torch.Tensor, bits: int, seed: int = 0, stream=None) -> torch.
         _check(lib().mphf_set_ids(_dev(keys, "keys"), keys.numel(), bits, seed & (2**64 - 1), _dev(out, "out"),
                                   _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------- roofline probes
+
+PROBE_KINDS = {"stream_read": 0, "stream_copy": 1, "random_read8": 2, "random_sector64": 3,
+               "random_atomic_or": 4, "lds_atomic_or": 5}
+
+
+def probe(kind: str, buf: torch.Tensor | None = None, nbytes: int = 0, dst: torch.Tensor | None = None,
+          ops: int = 0, seed: int = 1, stream=None) -> int:
+    """Enqueue one roofline microbenchmark (mphf_probe) on the stream; returns the number of random
+    operations it performs (0 for the streaming kinds)."""
+    k = PROBE_KINDS[kind]
+    bp = buf.data_ptr() if buf is not None else 0
+    if buf is not None and (not buf.is_cuda or nbytes > buf.numel() * buf.element_size()):
+        raise ValueError("buf must be a GPU tensor of at least nbytes")
+    dp = dst.data_ptr() if dst is not None else 0
+    if dst is not None and (not dst.is_cuda or nbytes > dst.numel() * dst.element_size()):
+        raise ValueError("dst must be a GPU tensor of at least nbytes")
+    _check(lib().mphf_probe(k, bp, nbytes, dp, ops, seed, _stream(stream)))
+    return int(lib().mphf_probe_ops(ops)) if k >= 2 else 0
 
 
 # ---------------------------------------------------------------- serving
