@@ -19,6 +19,63 @@
 
 using namespace mphfk;
 
+// The streams a handle's device work was enqueued on after its build (lookups, rebuilds), each with
+// an event recorded after its latest use there, so that destroying the handle waits for exactly that
+// work rather than for the whole device (a serving loop's other batches keep running).  Work
+// recorded into a HIP graph under capture is not tracked: the caller finishes its replays first.
+class UseTracker {
+  public:
+    hipError_t note(hipStream_t s) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess) return hipGetLastError();
+        if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+        std::lock_guard<std::mutex> g(mu_);
+        for (auto& u : uses_)
+            if (u.first == s) return hipEventRecord(u.second, s);
+        hipEvent_t e = nullptr;
+        hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r != hipSuccess) return r;
+        uses_.push_back({s, e});
+        return hipEventRecord(e, s);
+    }
+    void wait_all() {
+        std::lock_guard<std::mutex> g(mu_);
+        for (auto& u : uses_) {
+            (void)hipEventSynchronize(u.second);
+            (void)hipEventDestroy(u.second);
+        }
+        uses_.clear();
+        (void)hipGetLastError();
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses_;
+};
+
+// Frees device memory of a destroyed handle in stream order on a library-owned stream of the
+// device (non-blocking, default priority), so that no other stream is waited for.
+void free_on_device(int dev, const std::vector<void*>& ptrs) {
+    static std::mutex mu;
+    static hipStream_t fs[64] = {};
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (dev != cur) (void)hipSetDevice(dev);
+    hipStream_t s = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (dev >= 0 && dev < 64) {
+            if (!fs[dev] && hipStreamCreateWithFlags(&fs[dev], hipStreamNonBlocking) != hipSuccess) fs[dev] = nullptr;
+            s = fs[dev];
+        }
+    }
+    for (void* p : ptrs)
+        if (p) (void)(s ? hipFreeAsync(p, s) : hipFree(p));
+    if (s) (void)hipStreamSynchronize(s);
+    (void)hipGetLastError();
+    if (dev != cur) (void)hipSetDevice(cur);
+}
+
 struct mphf {
     int device = 0;
     uint64_t n = 0;
@@ -47,6 +104,7 @@ struct mphf {
     DevLevel* dlev = nullptr;
     uint64_t* coll_all = nullptr;   // C of every level, laid out like A (keep_collisions)
     uint64_t peak_bytes = 0;
+    mutable UseTracker uses;
 };
 
 namespace {
@@ -228,12 +286,9 @@ class Arena {
 
 void free_handle(mphf* h) {
     if (!h) return;
-    // lookups may still be in flight on any stream: wait for the device before freeing
-    (void)hipDeviceSynchronize();
-    void* bufs[] = {h->words, h->rank, h->fb_keys, h->dlev, h->coll_all, h->sec, h->super};
-    for (void* p : bufs)
-        if (p) (void)hipFreeAsync(p, nullptr);
-    (void)hipStreamSynchronize(nullptr);
+    // lookups may still be in flight on the streams that used h: wait for those, then free
+    h->uses.wait_all();
+    free_on_device(h->device, {h->words, h->rank, h->fb_keys, h->dlev, h->coll_all, h->sec, h->super});
     delete h;
 }
 
@@ -1122,6 +1177,7 @@ mphf_status mphf_lookup_ex(const mphf_t* h, const uint64_t* keys, uint64_t n, ui
     HIP_TRY(launch_lookup(keys, n, out, h->dlev, h->num_levels, h->sec, h->super, h->fb_keys, h->nfb,
                           h->n, (hipStream_t)stream),
             "lookup");
+    HIP_TRY(h->uses.note((hipStream_t)stream), "lookup event");
     return MPHF_OK;
 }
 
@@ -1496,16 +1552,15 @@ struct mphf_batch {
     uint32_t grid = 0;
     BatchLaunch cfg;
     bool retried = false;   // the one-shot build was redone with worst-case regions
+    mutable UseTracker uses;
 };
 
 namespace {
 
 void free_batch(mphf_batch* b) {
     if (!b) return;
-    (void)hipDeviceSynchronize();
-    for (void* p : b->mem)
-        if (p) (void)hipFreeAsync(p, nullptr);
-    (void)hipStreamSynchronize(nullptr);
+    b->uses.wait_all();
+    free_on_device(b->device, b->mem);
     delete b;
 }
 
@@ -1875,6 +1930,7 @@ mphf_status mphf_batch_rebuild(mphf_batch_t* b, const uint64_t* keys, void* stre
     const hipStream_t s = (hipStream_t)stream;
     HIP_TRY(batch_levels(b, keys, s), "batch levels");
     HIP_TRY(launch_batch_heads(b->sets, b->levels, b->D, b->nsets, b->heads, b->lev, b->aux, s), "heads");
+    HIP_TRY(b->uses.note(s), "rebuild event");
     return MPHF_OK;
 }
 
@@ -1899,6 +1955,7 @@ mphf_status mphf_batch_lookup(const mphf_batch_t* b, const uint64_t* set_ids, co
     HIP_TRY(launch_batch_lookup(set_ids, keys, n, out, b->heads, b->lev, b->aux, b->D, b->nsets, b->sec, b->left,
                                 b->seeds, (hipStream_t)stream),
             "batch lookup");
+    HIP_TRY(b->uses.note((hipStream_t)stream), "batch lookup event");
     return MPHF_OK;
 }
 

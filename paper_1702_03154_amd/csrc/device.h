@@ -59,8 +59,10 @@ __device__ __forceinline__ uint64_t level_pos(uint64_t key, const LevelHash& L) 
     return mod_invariant(fmix64(key ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
 }
 
-// Exact floor(a * 2^64 / m) for a < m < 2^63 by binary long division (one thread).
-__device__ inline uint64_t div_shift64(uint64_t a, uint64_t m) {
+// Exact floor(a * 2^64 / m) for a < m (any m >= 1) by binary long division (one thread).  The
+// remainder stays below m; when m > 2^63 a doubled remainder can pass 2^64, which the carry out of
+// the shift records (the true remainder is then >= m, and the wrapped subtraction is exact).
+__host__ __device__ inline uint64_t div_shift64(uint64_t a, uint64_t m) {
     if ((m >> 32) == 0) {   // two base-2^32 digits of the long division, each a 64-bit quotient
         const uint64_t t1 = a << 32;
         const uint64_t q1 = t1 / m;
@@ -69,9 +71,10 @@ __device__ inline uint64_t div_shift64(uint64_t a, uint64_t m) {
     }
     uint64_t q = 0, r = a;
     for (int i = 0; i < 64; ++i) {
+        const uint64_t carry = r >> 63;
         r <<= 1;
         q <<= 1;
-        if (r >= m) {
+        if (carry || r >= m) {
             r -= m;
             q |= 1;
         }
@@ -79,16 +82,18 @@ __device__ inline uint64_t div_shift64(uint64_t a, uint64_t m) {
     return q;
 }
 
-// Device-side twin of make_level_hash (Granlund-Montgomery Figure 4.1 constants).
-__device__ inline LevelHash device_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
+// Device-side twin of make_level_hash (Granlund-Montgomery Figure 4.1 constants) for any m >= 1:
+// l = ceil(log2 m), magic = floor(2^64 (2^l - m) / m) + 1, sh1 = min(l, 1), sh2 = max(l - 1, 0),
+// with 2^l - m taken modulo 2^64 when l = 64 (m > 2^63).
+__host__ __device__ inline LevelHash device_level_hash(uint64_t seed, uint64_t m, uint64_t bit_off) {
     LevelHash L;
     L.seed = seed;
     L.m = m;
     L.bit_off = bit_off;
     uint32_t l = 0;
-    while (l < 63 && (1ull << l) < m) ++l;
-    if ((1ull << l) < m) l = 64;
-    L.magic = (l < 64 ? div_shift64((1ull << l) - m, m) : 0) + 1;
+    while (l < 64 && (1ull << l) < m) ++l;   // l = 64 only when m > 2^63
+    const uint64_t pow_l = l < 64 ? (1ull << l) : 0;   // 2^l mod 2^64
+    L.magic = div_shift64(pow_l - m, m) + 1;
     L.sh1 = l < 1 ? l : 1;
     L.sh2 = l > 1 ? l - 1 : 0;
     return L;
