@@ -363,8 +363,11 @@ class Builder {
         return levels_and_finish(keys, n, 0, 0);
     }
 
-    // Streamed levels over a generated key stream while the survivors exceed `budget` keys (no key
-    // is stored), then the survivors are collected and the in-memory levels continue.
+    // Streamed levels over a generated key stream, or over a key set in host memory (host_keys set),
+    // while the survivors exceed `budget` keys (no F_d is stored), then the survivors are collected
+    // and the in-memory levels continue.
+    void use_host_keys(const uint64_t* keys) { host_keys_ = keys; }
+
     mphf_status run_stream(uint64_t kseed, uint64_t kstart, uint64_t n, double gamma, uint64_t budget) {
         mphf_status st;
         if ((st = setup(n, gamma)) != MPHF_OK) return st;
@@ -399,7 +402,17 @@ class Builder {
             if (!accumulated) {
                 walkable = false;   // the later scans walk by random reads too
                 HIP_TRY(launch_zero(W, 2 * wd, s_), "zero W");
-                HIP_TRY(launch_stream_fill(kseed, kstart, n, lev, d, words_, W, L, s_), "stream fill");
+                if (!host_keys_) {
+                    HIP_TRY(launch_stream_fill(kseed, kstart, nullptr, n, lev, d, words_, W, L, s_), "stream fill");
+                } else {   // the stored keys, chunk by chunk
+                    const uint64_t ch = chunk_keys(n, budget);
+                    if (!chunk && (st = ar_.alloc(&chunk, ch, "stream chunk")) != MPHF_OK) return st;
+                    for (uint64_t c0 = 0; c0 < n; c0 += ch) {
+                        const uint64_t c = std::min<uint64_t>(ch, n - c0);
+                        if ((st = load_chunk(kseed, kstart, c0, c, chunk)) != MPHF_OK) return st;
+                        HIP_TRY(launch_stream_fill(0, 0, chunk, c, lev, d, words_, W, L, s_), "stream fill");
+                    }
+                }
             }
             HIP_TRY(launch_finalize(W, wd, words_ + off / 64, coll_ ? coll_ + off / 64 : nullptr, counters + d, s_),
                     "finalize");
@@ -432,7 +445,7 @@ class Builder {
             // chunk by chunk, the levels walked by bucket
             unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
             HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
-            const uint64_t ch = std::min<uint64_t>(n, std::max<uint64_t>(budget, 1ull << 20));
+            const uint64_t ch = chunk_keys(n, budget);
             uint64_t got = 0;
             bool fits = true;
             for (uint64_t c0 = 0; c0 < n && fits; c0 += ch) {
@@ -451,14 +464,41 @@ class Builder {
         }
         if (!collected) {
             HIP_TRY(launch_zero(dev_ + 200, 1, s_), "zero count");
-            HIP_TRY(launch_stream_collect(kseed, kstart, n, lev, d, words_, dense, nd, counters + 200, s_),
-                    "collect");
+            if (!host_keys_) {
+                HIP_TRY(launch_stream_collect(kseed, kstart, nullptr, n, lev, d, words_, dense, nd, counters + 200, s_),
+                        "collect");
+            } else {   // the stored keys, chunk by chunk, appended at the running count
+                const uint64_t ch = chunk_keys(n, budget);
+                if (!chunk && (st = ar_.alloc(&chunk, ch, "stream chunk")) != MPHF_OK) return st;
+                for (uint64_t c0 = 0; c0 < n; c0 += ch) {
+                    const uint64_t c = std::min<uint64_t>(ch, n - c0);
+                    if ((st = load_chunk(kseed, kstart, c0, c, chunk)) != MPHF_OK) return st;
+                    HIP_TRY(launch_stream_collect(0, 0, chunk, c, lev, d, words_, dense, nd, counters + 200, s_),
+                            "collect");
+                }
+            }
             if ((st = read_back(counters + 200, 8)) != MPHF_OK) return st;
             if (host_[0] != nd) return fail(MPHF_E_DEVICE, "collected survivors differ from the level counts");
         }
         if (chunk) ar_.release(chunk);
         tr_.mark("collect", (long)nd);
         return levels_and_finish(dense, nd, d, off);
+    }
+
+    // Keys per chunk of a streamed scan: the survivor budget, at least 2^20, at most the set.
+    static uint64_t chunk_keys(uint64_t n, uint64_t budget) {
+        return std::min<uint64_t>(n, std::max<uint64_t>(budget, 1ull << 20));
+    }
+
+    // Keys c0 .. c0 + c - 1 of the key source into the device array chunk: generated, or copied from
+    // the host array (over PCIe, in stream order).
+    mphf_status load_chunk(uint64_t kseed, uint64_t kstart, uint64_t c0, uint64_t c, uint64_t* chunk) {
+        if (host_keys_) {
+            HIP_TRY(hipMemcpyAsync(chunk, host_keys_ + c0, 8 * c, hipMemcpyHostToDevice, s_), "chunk copy");
+        } else {
+            HIP_TRY(launch_stream_keys(kseed, kstart + c0, c, chunk, s_), "chunk keys");
+        }
+        return MPHF_OK;
     }
 
     // Bucket bits for a level of m positions: the bucket geometry's, raised until two radix passes
@@ -477,7 +517,7 @@ class Builder {
     mphf_status stream_unplaced(uint64_t kseed, uint64_t kstart, uint64_t c0, uint64_t c, uint32_t d,
                                 uint64_t* chunk, uint64_t* pre0, KeySet* out, unsigned long long* ovf) {
         mphf_status st;
-        HIP_TRY(launch_stream_keys(kseed, kstart + c0, c, chunk, s_), "chunk keys");
+        if ((st = load_chunk(kseed, kstart, c0, c, chunk)) != MPHF_OK) return st;
         HIP_TRY(launch_pair(pre0, 0, c, s_), "chunk prefix");
         KeySet cur;
         cur.base = chunk;
@@ -525,7 +565,7 @@ class Builder {
                                         uint64_t wd, uint64_t** chunk, uint64_t** pre0, bool* done) {
         mphf_status st;
         *done = false;
-        const uint64_t ch = std::min<uint64_t>(n, std::max<uint64_t>(budget, 1ull << 20));
+        const uint64_t ch = chunk_keys(n, budget);
         if (!*chunk && (st = ar_.alloc(chunk, ch, "stream chunk")) != MPHF_OK) return st;
         if (!*pre0 && (st = ar_.alloc(pre0, 2, "chunk prefix")) != MPHF_OK) return st;
         HIP_TRY(accumulate_setup(), "accumulate setup");
@@ -653,10 +693,8 @@ class Builder {
         mphf_status st;
         if ((st = fallback_table()) != MPHF_OK) return st;
         tr_.mark("fallback table", (long)nleft_);
-        if ((st = rank_table()) != MPHF_OK) return st;
-        tr_.mark("rank table");
-        if ((st = lookup_layout()) != MPHF_OK) return st;
-        tr_.mark("lookup layout");
+        if ((st = rank_and_lookup_layout()) != MPHF_OK) return st;
+        tr_.mark("rank table and lookup layout");
         if ((st = level_table()) != MPHF_OK) return st;
         tr_.mark("level table");
         h_->words = words_;
@@ -694,6 +732,7 @@ class Builder {
     WsBufs priv_;
     WsBufs* ws_ = &priv_;
     bool cached_ = false;
+    const uint64_t* host_keys_ = nullptr;   // streaming build over a stored key set in host memory
     std::unique_lock<std::mutex> lock_;
     int ypar_ = 0;
 
@@ -723,7 +762,7 @@ class Builder {
             HIP_TRY(launch_zero(nc, ncap, s_), "zero C");
             if (coll_) HIP_TRY(hipMemcpyAsync(nc, coll_, cap_words_ * 8, hipMemcpyDeviceToDevice, s_), "grow C");
         }
-        HIP_TRY(hipStreamSynchronize(s_), "grow sync");
+        // the old arrays are freed in stream order, after the copies
         ar_.release(words_);
         ar_.release(coll_);
         words_ = nw;
@@ -886,8 +925,10 @@ class Builder {
                 "bucket");
         HIP_TRY(launch_zero32(ws_->surv[yp] + B, 1, s_), "zero count tail");
         if ((st = prefix(ws_->surv[yp], B, ws_->preY[yp])) != MPHF_OK) return st;
-        HIP_TRY(hipMemcpyAsync(dev_ + 130, ws_->preY[yp] + B, 8, hipMemcpyDeviceToDevice, s_), "copy total");
-        if ((st = read_back(dev_ + 129, 16)) != MPHF_OK) return st;
+        // the overflow flag and the survivor total, read back together
+        HIP_TRY(hipMemcpyAsync(host_, dev_ + 129, 8, hipMemcpyDeviceToHost, s_), "read back");
+        HIP_TRY(hipMemcpyAsync(host_ + 1, ws_->preY[yp] + B, 8, hipMemcpyDeviceToHost, s_), "read back");
+        HIP_TRY(hipStreamSynchronize(s_), "level sync");
         if (host_[0]) return MPHF_OK;   // overflow: redo with atomics
         const uint64_t nnext = host_[1];
         if (nnext > n) return fail(MPHF_E_DEVICE, "survivors exceed the level's keys");
@@ -913,11 +954,14 @@ class Builder {
         HIP_TRY(launch_tail(in.base, in.stride, in.pre, in.nseg, tk, gamma_, seeds_, d0, D, off, words_,
                             coll_, tail_rec_, left, (TailSummary*)(dev_ + 130), s_),
                 "tail");
-        if ((st = read_back(dev_ + 130, 24)) != MPHF_OK) return st;
-        const uint64_t end = host_[0], nleft = host_[1], bit_end = host_[2];
-        std::vector<TailLevel> rec(MPHF_MAX_LEVELS);
-        HIP_TRY(hipMemcpy(rec.data(), tail_rec_, sizeof(TailLevel) * MPHF_MAX_LEVELS, hipMemcpyDeviceToHost),
+        // the summary and the per-level records in one read-back into the pinned buffer
+        static_assert(8 * 8 + sizeof(TailLevel) * MPHF_MAX_LEVELS <= 4096, "pinned read-back buffer");
+        HIP_TRY(hipMemcpyAsync(host_, dev_ + 130, 24, hipMemcpyDeviceToHost, s_), "read back");
+        HIP_TRY(hipMemcpyAsync(host_ + 8, tail_rec_, sizeof(TailLevel) * MPHF_MAX_LEVELS, hipMemcpyDeviceToHost, s_),
                 "read tail records");
+        HIP_TRY(hipStreamSynchronize(s_), "tail sync");
+        const uint64_t end = host_[0], nleft = host_[1], bit_end = host_[2];
+        const TailLevel* rec = (const TailLevel*)(host_ + 8);
         for (uint64_t d = d0; d < end; ++d)
             record((uint32_t)d, rec[d].n, rec[d].m, rec[d].weight, rec[d].offset, MPHF_PATH_TAIL);
         h_->total_bits = bit_end;
@@ -1010,35 +1054,27 @@ class Builder {
         return MPHF_OK;
     }
 
-    // Rank table (Section 3.1).
-    mphf_status rank_table() {
+    // Rank table (Section 3.1) and the lookup's copy of A in 64-byte sectors with embedded rank
+    // counters, both from one counting read of A.
+    mphf_status rank_and_lookup_layout() {
         h_->nrank = (h_->total_bits + o_.rank_sample - 1) / o_.rank_sample;
-        if (!h_->nrank) return MPHF_OK;
-        mphf_status st;
-        uint32_t* rc = nullptr;
-        uint64_t* rt = nullptr;
-        if ((st = ar_.alloc(&h_->rank, h_->nrank, "rank")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&rc, h_->nrank, "rank counts")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&rt, scan_tmp_tiles(h_->nrank), "rank tiles")) != MPHF_OK) return st;
-        HIP_TRY(launch_rank(words_, h_->total_words, o_.rank_sample, h_->rank, h_->nrank, rc, rt, s_),
-                "rank");
-        ar_.keep(h_->rank);
-        return MPHF_OK;
-    }
-
-    // The lookup's copy of A in 64-byte sectors with embedded rank counters.
-    mphf_status lookup_layout() {
         h_->nsec = sector_count(h_->total_bits);
-        if (!h_->nsec) return MPHF_OK;
+        if (!h_->nsec) return MPHF_OK;   // no bits: no rank entries either
         mphf_status st;
-        uint32_t* cnt = nullptr;
+        uint32_t *cnt = nullptr, *rc = nullptr;
         uint64_t *pre = nullptr, *tiles = nullptr;
+        if ((st = ar_.alloc(&h_->rank, h_->nrank, "rank")) != MPHF_OK) return st;
         if ((st = ar_.alloc(&h_->sec, h_->nsec * 16, "lookup sectors")) != MPHF_OK) return st;
         if ((st = ar_.alloc(&h_->super, super_count(h_->nsec), "lookup superblocks")) != MPHF_OK) return st;
         if ((st = ar_.alloc(&cnt, h_->nsec, "sector counts")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&rc, h_->nrank, "rank counts")) != MPHF_OK) return st;
         if ((st = ar_.alloc(&pre, h_->nsec, "sector prefix")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&tiles, scan_tmp_tiles(h_->nsec), "sector tiles")) != MPHF_OK) return st;
-        HIP_TRY(launch_sectors(words_, h_->total_bits, h_->sec, h_->super, cnt, pre, tiles, s_), "sectors");
+        if ((st = ar_.alloc(&tiles, scan_tmp_tiles(std::max(h_->nsec, h_->nrank)), "scan tiles")) != MPHF_OK)
+            return st;
+        HIP_TRY(launch_rank_sectors(words_, h_->total_bits, o_.rank_sample, h_->rank, h_->nrank, h_->sec, h_->super,
+                                    cnt, rc, pre, tiles, s_),
+                "rank and sectors");
+        ar_.keep(h_->rank);
         ar_.keep(h_->sec);
         ar_.keep(h_->super);
         return MPHF_OK;
@@ -1091,8 +1127,8 @@ mphf_status build_impl(const uint64_t* keys, uint64_t n, double gamma, uint64_t 
     return MPHF_OK;
 }
 
-mphf_status build_stream_impl(uint64_t kseed, uint64_t kstart, uint64_t n, double gamma, uint64_t seed,
-                              const mphf_opts& opts, uint64_t budget, hipStream_t s, mphf** out) {
+mphf_status build_stream_impl(uint64_t kseed, uint64_t kstart, const uint64_t* host_keys, uint64_t n, double gamma,
+                              uint64_t seed, const mphf_opts& opts, uint64_t budget, hipStream_t s, mphf** out) {
     if (!(gamma >= 1.0) || !std::isfinite(gamma))
         return fail(MPHF_E_INVALID, "gamma must be a finite number >= 1");
     if (gamma * (double)n >= 9.2e18) return fail(MPHF_E_INVALID, "gamma * n too large");
@@ -1108,6 +1144,7 @@ mphf_status build_stream_impl(uint64_t kseed, uint64_t kstart, uint64_t n, doubl
     h->rank_shift = opts.rank_sample == 1024 ? 10 : 9;
     {
         Builder b(h, opts, s);
+        b.use_host_keys(host_keys);
         st = b.run_stream(kseed, kstart, n, gamma, budget);
     }
     if (st != MPHF_OK) {
@@ -1130,7 +1167,21 @@ mphf_status mphf_build_stream(const mphf_key_stream* src, uint64_t n, double gam
     if (opts) o = *opts;
     else mphf_default_opts(&o);
     if (o.flags & ~MPHF_FLAG_ATOMIC_LEVELS) return fail(MPHF_E_INVALID, "unknown flags");
-    return build_stream_impl(src->seed, src->start, n, gamma, seed, o, resident_keys, (hipStream_t)stream, out);
+    return build_stream_impl(src->seed, src->start, nullptr, n, gamma, seed, o, resident_keys, (hipStream_t)stream,
+                             out);
+}
+
+mphf_status mphf_build_host(const uint64_t* keys, uint64_t n, double gamma, uint64_t seed, const mphf_opts* opts,
+                            uint64_t resident_keys, void* stream, mphf_t** out) {
+    if (!out) return fail(MPHF_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (n && !keys) return fail(MPHF_E_INVALID, "keys is NULL");
+    if (n && is_device_ptr(keys)) return fail(MPHF_E_INVALID, "keys must be host memory (mphf_build_ex takes device keys)");
+    mphf_opts o;
+    if (opts) o = *opts;
+    else mphf_default_opts(&o);
+    if (o.flags & ~MPHF_FLAG_ATOMIC_LEVELS) return fail(MPHF_E_INVALID, "unknown flags");
+    return build_stream_impl(0, 0, keys, n, gamma, seed, o, resident_keys, (hipStream_t)stream, out);
 }
 
 mphf_status mphf_stream_keys(const mphf_key_stream* src, uint64_t first, uint64_t count, uint64_t* out,

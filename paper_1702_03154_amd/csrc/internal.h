@@ -216,18 +216,17 @@ hipError_t launch_filter_fill(const uint64_t* Fin, uint64_t n, const uint64_t* w
                               const LevelHash& Ld, uint64_t* Fout, uint64_t cap,
                               unsigned long long* count, uint64_t* W, const LevelHash& Lnext,
                               bool do_fill, hipStream_t s);
-hipError_t launch_rank(const uint64_t* words, uint64_t total_words, uint32_t rank_sample,
-                       uint64_t* rank, uint64_t nrank, uint32_t* tmp_counts, uint64_t* tmp_tiles,
-                       hipStream_t s);
 uint64_t scan_tmp_tiles(uint64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
                                  hipStream_t s);
 // streaming build (stream.hip)
-hipError_t launch_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
-                              const uint64_t* words, uint64_t* W, const LevelHash& L, hipStream_t s);
-hipError_t launch_stream_collect(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
-                                 const uint64_t* words, uint64_t* out, uint64_t cap, unsigned long long* count,
-                                 hipStream_t s);
+// keys = NULL: key i of the range is output kstart + i of the generated stream; else keys[i] (a chunk of a
+// stored key set on the device).
+hipError_t launch_stream_fill(uint64_t kseed, uint64_t kstart, const uint64_t* keys, uint64_t n, const DevLevel* lev,
+                              uint32_t d, const uint64_t* words, uint64_t* W, const LevelHash& L, hipStream_t s);
+hipError_t launch_stream_collect(uint64_t kseed, uint64_t kstart, const uint64_t* keys, uint64_t n,
+                                 const DevLevel* lev, uint32_t d, const uint64_t* words, uint64_t* out, uint64_t cap,
+                                 unsigned long long* count, hipStream_t s);
 hipError_t launch_stream_keys(uint64_t kseed, uint64_t kstart, uint64_t n, uint64_t* out, hipStream_t s);
 
 // k-mer workload (kmer.hip)
@@ -255,8 +254,12 @@ hipError_t launch_find_duplicates(const uint64_t* sorted, uint64_t n, unsigned l
                                   hipStream_t s);
 uint64_t sector_count(uint64_t total_bits);
 uint64_t super_count(uint64_t nsec);
-hipError_t launch_sectors(const uint64_t* words, uint64_t total_bits, uint32_t* sec, uint64_t* super,
-                          uint32_t* tmp_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s);
+// The rank table (counters every rank_sample positions) and the lookup sectors from one counting
+// read of A: tmp_counts holds a u32 per sector, tmp_rank_counts a u32 per rank entry, tmp_pre a u64
+// per sector, tmp_tiles scan_tmp_tiles(max(sectors, rank entries)).
+hipError_t launch_rank_sectors(const uint64_t* words, uint64_t total_bits, uint32_t rank_sample, uint64_t* rank,
+                               uint64_t nrank, uint32_t* sec, uint64_t* super, uint32_t* tmp_counts,
+                               uint32_t* tmp_rank_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s);
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
                          uint32_t nlev, const uint32_t* sec, const uint64_t* super,
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);

@@ -127,21 +127,7 @@ __global__ void k_filter_fill(const uint64_t* __restrict__ Fin, uint64_t n,
     }
 }
 
-// ---------------------------------------------------------------- rank table
-
-// Ones in each rank block of wpb words.
-__global__ void k_rank_counts(const uint64_t* __restrict__ words, uint64_t total_words,
-                              uint32_t wpb, uint32_t* __restrict__ counts, uint64_t nb) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
-        const uint64_t w0 = b * wpb;
-        uint64_t w1 = w0 + wpb;
-        if (w1 > total_words) w1 = total_words;
-        uint32_t c = 0;
-        for (uint64_t w = w0; w < w1; ++w) c += __popcll(words[w]);
-        counts[b] = c;
-    }
-}
+// ---------------------------------------------------------------- scans
 
 // Three-phase exclusive scan of u32 counts into u64 prefixes.
 constexpr int SCAN_ITEMS = 16;
@@ -273,14 +259,44 @@ __global__ void k_find_duplicates(const uint64_t* __restrict__ s, uint64_t n,
 // request rate caps how many 16-byte pieces a lane may load per probe, so a probe should touch one
 // small aligned unit holding both the probed bit and what its rank needs: the 64-byte sectors of
 // device.h (Section 3.1's counters, here one 32-bit counter per 480 positions plus superblocks).
-__global__ void k_sector_counts(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec,
-                                uint32_t* __restrict__ counts) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nsec; j += stride) {
-        uint32_t c = 0;
-        for (uint64_t w = 15 * j; w < 15 * j + 15 && w < nwords32; ++w) c += __popc(A32[w]);
-        counts[j] = c;
+//
+// Sector counts and rank-block counts from one read of A: workgroup g covers the 256 sectors
+// 256 g .. 256 g + 255, i.e. bits [122880 g, 122880 (g+1)), which is exactly 240 rank blocks of 512
+// positions (120 of 1024), so its rank blocks are counted in LDS and written once.  A sector's 480
+// bits meet at most two rank blocks, split on a 32-bit word boundary.
+constexpr uint32_t SR_SECTORS = 256;
+constexpr uint64_t SR_BITS = SR_SECTORS * SEC_BITS;   // 122880
+
+__global__ void __launch_bounds__(SR_SECTORS)
+k_sector_rank_counts(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec, uint32_t rshift,
+                     uint64_t nrank, uint32_t* __restrict__ sec_counts, uint32_t* __restrict__ rank_counts) {
+    __shared__ uint32_t rc[SR_BITS / 512];
+    const uint32_t nrb = (uint32_t)(SR_BITS >> rshift);   // rank blocks of this workgroup
+    for (uint32_t i = threadIdx.x; i < nrb; i += SR_SECTORS) rc[i] = 0;
+    __syncthreads();
+    const uint64_t j = (uint64_t)blockIdx.x * SR_SECTORS + threadIdx.x;
+    if (j < nsec) {
+        const uint64_t bit0 = j * SEC_BITS;
+        const uint64_t b0 = bit0 >> rshift;
+        // words of this sector before the next rank block's first bit (15 if it starts later)
+        const uint64_t split = ((b0 + 1) << rshift) - bit0;
+        const uint32_t wsplit = split >= SEC_BITS ? 15u : (uint32_t)(split >> 5);
+        uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < 15; ++w) {
+            const uint64_t src = 15 * j + w;
+            const uint32_t c = src < nwords32 ? __popc(A32[src]) : 0u;
+            if (w < wsplit) c0 += c; else c1 += c;
+        }
+        sec_counts[j] = c0 + c1;
+        const uint32_t local = (uint32_t)(b0 - (((uint64_t)blockIdx.x * SR_BITS) >> rshift));
+        if (c0) atomicAdd(&rc[local], c0);
+        if (c1) atomicAdd(&rc[local + 1], c1);
     }
+    __syncthreads();
+    const uint64_t r0 = ((uint64_t)blockIdx.x * SR_BITS) >> rshift;
+    for (uint32_t i = threadIdx.x; i < nrb; i += SR_SECTORS)
+        if (r0 + i < nrank) rank_counts[r0 + i] = rc[i];
 }
 
 // One thread per u32 word of the sector layout.
@@ -406,17 +422,6 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const uint64_t* words, uint64_t total_words, uint32_t rank_sample,
-                       uint64_t* rank, uint64_t nrank, uint32_t* tmp_counts, uint64_t* tmp_tiles,
-                       hipStream_t s) {
-    if (!nrank) return hipSuccess;
-    hipLaunchKernelGGL(k_rank_counts, dim3(grid_for(nrank, NT)), dim3(NT), 0, s, words, total_words,
-                       rank_sample / 64, tmp_counts, nrank);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_exclusive_scan(tmp_counts, rank, nrank, tmp_tiles, s);
-}
-
 uint64_t radix_tmp_counts(uint64_t n) { return 256 * ((n + RADIX_TILE - 1) / RADIX_TILE); }
 
 hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t n, uint32_t* counts,
@@ -451,15 +456,19 @@ hipError_t launch_find_duplicates(const uint64_t* sorted, uint64_t n, unsigned l
 uint64_t sector_count(uint64_t total_bits) { return (total_bits + SEC_BITS - 1) / SEC_BITS; }
 uint64_t super_count(uint64_t nsec) { return (nsec >> SUPER_SHIFT) + 1; }
 
-hipError_t launch_sectors(const uint64_t* words, uint64_t total_bits, uint32_t* sec, uint64_t* super,
-                          uint32_t* tmp_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s) {
+hipError_t launch_rank_sectors(const uint64_t* words, uint64_t total_bits, uint32_t rank_sample, uint64_t* rank,
+                               uint64_t nrank, uint32_t* sec, uint64_t* super, uint32_t* tmp_counts,
+                               uint32_t* tmp_rank_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s) {
     const uint64_t ns = sector_count(total_bits);
     if (!ns) return hipSuccess;
+    if (rank_sample != 512 && rank_sample != 1024) return hipErrorInvalidValue;
     const uint64_t nw32 = total_bits / 32;
-    hipLaunchKernelGGL(k_sector_counts, dim3(grid_for(ns, NT)), dim3(NT), 0, s, (const uint32_t*)words,
-                       nw32, ns, tmp_counts);
+    hipLaunchKernelGGL(k_sector_rank_counts, dim3((unsigned)((ns + SR_SECTORS - 1) / SR_SECTORS)), dim3(SR_SECTORS),
+                       0, s, (const uint32_t*)words, nw32, ns, rank_sample == 512 ? 9u : 10u, nrank, tmp_counts,
+                       tmp_rank_counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(tmp_rank_counts, rank, nrank, tmp_tiles, s)) != hipSuccess) return e;
     if ((e = launch_exclusive_scan(tmp_counts, tmp_pre, ns, tmp_tiles, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sector_write, dim3(grid_for(ns * SEC_WORDS, NT * 4)), dim3(NT), 0, s,
                        (const uint32_t*)words, nw32, ns, tmp_pre, sec, super);

@@ -71,8 +71,8 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // unfinished lines go out at the end.  With 2^10 bins the per-bin lines would not fit in LDS and
 // the runs are written as they are.
 //
-// Tiles: with SPAN = false a tile is the rest of its segment, up to PTILE keys, one contiguous
-// read, and the next tile's keys are loaded while the current one is sorted and written.  With
+// Tiles: with SPAN = false a tile is up to PTILE keys from the segment holding its start and the
+// next segment, and the next tile's keys are loaded while the current one is sorted and written.  With
 // SPAN = true (inputs of small segments) a tile is a dense range across up to TSEG segments, each
 // key found in the segment boundaries staged in LDS.
 //
@@ -258,13 +258,15 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
     }
 }
 
-// Loads the tile [0, tn) of src (tn >= 1); items past the tile load the last key again.
-__device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t* __restrict__ src,
-                                          uint32_t tn) {
+// Loads a tile of tn >= 1 keys: its first n1 from src1, the rest from src2 (the start of the next
+// segment); items past the tile load the last key again.
+__device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t* __restrict__ src1, uint32_t n1,
+                                          const uint64_t* __restrict__ src2, uint32_t tn) {
 #pragma unroll
     for (int it = 0; it < PITEMS; ++it) {
-        const uint32_t j = it * PT + threadIdx.x;
-        k[it] = src[j < tn ? j : tn - 1];
+        const uint32_t j0 = it * PT + threadIdx.x;
+        const uint32_t j = j0 < tn ? j0 : tn - 1;
+        k[it] = j < n1 ? src1[j] : src2[j - n1];
     }
 }
 
@@ -319,21 +321,32 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
     uint32_t s = lo < hi ? find_segment(pre, s0, s1, lo) : s0;
     uint64_t sb = pre[s], se = pre[s + 1];
     if constexpr (!SPAN) {
-        // the tile starting at t (< hi): the rest of its segment, up to PTILE keys
+        // the tile starting at t (< hi): up to PTILE keys from the segment holding t and the next
+        // one (segments average at least half a tile here, so tiles stay nearly full)
         auto tile_end = [&](uint64_t t) {
             while (se <= t) {   // pre[s1] >= hi > t ends it
                 ++s;
                 sb = se;
                 se = pre[s + 1];
             }
-            const uint64_t e = t + PTILE < hi ? t + PTILE : hi;
-            return se < e ? se : e;
+            uint64_t e = t + PTILE < hi ? t + PTILE : hi;
+            if (e > se) {   // then s + 1 < s1, and pre[s + 2] ends the next segment
+                const uint64_t se2 = pre[s + 2];
+                if (e > se2) e = se2;
+            }
+            return e;
+        };
+        // the tile [t, e) from segment s and, past se, segment s + 1
+        auto load = [&](uint64_t (&k)[PITEMS], uint64_t t, uint64_t e) {
+            const uint64_t n1 = (se < e ? se : e) - t;
+            load_tile(k, in + (uint64_t)s * in_stride + (t - sb), (uint32_t)n1, in + (uint64_t)(s + 1) * in_stride,
+                      (uint32_t)(e - t));
         };
         uint64_t kn[PITEMS];
         uint64_t t0 = lo, te = lo;
         if (t0 < hi) {
             te = tile_end(t0);
-            load_tile(kn, in + (uint64_t)s * in_stride + (t0 - sb), (uint32_t)(te - t0));
+            load(kn, t0, te);
         }
         while (t0 < hi) {
             uint64_t k[PITEMS];
@@ -344,7 +357,7 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             uint64_t te1 = t1;
             if (t1 < hi) {   // the next tile's loads overlap this tile's sort and writes
                 te1 = tile_end(t1);
-                load_tile(kn, in + (uint64_t)s * in_stride + (t1 - sb), (uint32_t)(te1 - t1));
+                load(kn, t1, te1);
             }
             part_tile<NB, WC, HASHED, DIG>(S, k, tn, L, pbits, out_shift, pack_shift, bin_base, lim, obase,
                                       out_cap, overflow);
