@@ -204,6 +204,17 @@ typedef struct mphf_key_stream {
 mphf_status mphf_build_stream(const mphf_key_stream* src, uint64_t n, double gamma, uint64_t seed,
                               const mphf_opts* opts, uint64_t resident_keys, void* stream, mphf_t** out);
 
+/* The same streaming build over n keys stored in HOST memory (pinned memory from mphf_host_alloc is
+ * copied fastest; any host array works): the re-scan strategy of Section 3.4 for a stored key set
+ * larger than device memory.  Every streamed level copies the keys to the device chunk by chunk
+ * (max(resident_keys, 2^20) keys at a time, over PCIe) and treats them as mphf_build_stream treats its
+ * generated keys; no F_d is stored until the survivors fit resident_keys.  The keys must stay
+ * unchanged until the call returns; a device pointer is rejected with MPHF_E_INVALID (mphf_build_ex
+ * builds from device keys).  The function, its levels and labels equal those of mphf_build_ex on the
+ * same keys; duplicate keys give MPHF_E_DUPLICATE_KEYS.  Synchronous. */
+mphf_status mphf_build_host(const uint64_t* keys, uint64_t n, double gamma, uint64_t seed, const mphf_opts* opts,
+                            uint64_t resident_keys, void* stream, mphf_t** out);
+
 /* Keys first .. first+count-1 of the stream into the device array out (queries of a streamed build). */
 mphf_status mphf_stream_keys(const mphf_key_stream* src, uint64_t first, uint64_t count, uint64_t* out,
                              void* stream);

@@ -7,9 +7,11 @@
 // collected and the in-memory levels take over; the result equals a build from the stored keys
 // because the levels depend only on the key set.
 //
-// Key source: a deterministic stream of pseudo-random keys generated on the fly, as for the
+// Key sources: a deterministic stream of pseudo-random keys generated on the fly, as for the
 // trillion-key run of Section 4.5: key i is the SplitMix64 output (Steele, Lea and Flood, OOPSLA
-// 2014) of seed + (i + 1) * 0x9E3779B97F4A7C15, a bijective mix, so the n keys are distinct.
+// 2014) of seed + (i + 1) * 0x9E3779B97F4A7C15, a bijective mix, so the n keys are distinct; or a
+// stored key set in host memory, copied to the device chunk by chunk at every re-scan (the kernels
+// below then read the chunk's keys instead of generating them).
 #include "internal.h"
 
 namespace mphfk {
@@ -46,8 +48,9 @@ __device__ __forceinline__ void mark_pos(unsigned long long* W, uint64_t p) {
 constexpr int ZI = 8;   // keys per thread per iteration: independent walks in flight
 
 __global__ void __launch_bounds__(ZT)
-k_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __restrict__ lev, uint32_t d,
-              const uint64_t* __restrict__ words, unsigned long long* W, LevelHash L) {
+k_stream_fill(uint64_t kseed, uint64_t kstart, const uint64_t* __restrict__ keys, uint64_t n,
+              const DevLevel* __restrict__ lev, uint32_t d, const uint64_t* __restrict__ words, unsigned long long* W,
+              LevelHash L) {
     const uint64_t stride = (uint64_t)gridDim.x * ZT * ZI;
     for (uint64_t i0 = (uint64_t)blockIdx.x * ZT * ZI; i0 < n; i0 += stride) {
         uint64_t x[ZI];
@@ -56,7 +59,7 @@ k_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __res
         for (int it = 0; it < ZI; ++it) {
             const uint64_t i = i0 + (uint64_t)it * ZT + threadIdx.x;
             live[it] = i < n;
-            x[it] = live[it] ? stream_key(kseed, kstart + i) : 0;
+            x[it] = live[it] ? (keys ? keys[i] : stream_key(kseed, kstart + i)) : 0;
         }
 #pragma unroll
         for (int it = 0; it < ZI; ++it) live[it] = live[it] && !placed_before(x[it], lev, d, words);
@@ -70,9 +73,9 @@ k_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __res
 // counter updated by every wave would serialize on one address.  Order inside a block's chunk is
 // thread-major; the build does not depend on the order of F_d.
 __global__ void __launch_bounds__(ZT)
-k_stream_collect(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __restrict__ lev, uint32_t d,
-                 const uint64_t* __restrict__ words, uint64_t* __restrict__ out, uint64_t cap,
-                 unsigned long long* count) {
+k_stream_collect(uint64_t kseed, uint64_t kstart, const uint64_t* __restrict__ keys, uint64_t n,
+                 const DevLevel* __restrict__ lev, uint32_t d, const uint64_t* __restrict__ words,
+                 uint64_t* __restrict__ out, uint64_t cap, unsigned long long* count) {
     __shared__ uint32_t wsum[ZT / 64 + 1];
     __shared__ unsigned long long s_base;
     const uint64_t stride = (uint64_t)gridDim.x * ZT * ZI;
@@ -82,7 +85,7 @@ k_stream_collect(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* __
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
             const uint64_t i = i0 + (uint64_t)it * ZT + threadIdx.x;
-            x[it] = i < n ? stream_key(kseed, kstart + i) : 0;
+            x[it] = i < n ? (keys ? keys[i] : stream_key(kseed, kstart + i)) : 0;
         }
 #pragma unroll
         for (int it = 0; it < ZI; ++it) {
@@ -120,20 +123,20 @@ unsigned zgrid(uint64_t n) {
 
 }  // namespace
 
-hipError_t launch_stream_fill(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
-                              const uint64_t* words, uint64_t* W, const LevelHash& L, hipStream_t s) {
+hipError_t launch_stream_fill(uint64_t kseed, uint64_t kstart, const uint64_t* keys, uint64_t n, const DevLevel* lev,
+                              uint32_t d, const uint64_t* words, uint64_t* W, const LevelHash& L, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_stream_fill, dim3(zgrid(n)), dim3(ZT), 0, s, kseed, kstart, n, lev, d, words,
+    hipLaunchKernelGGL(k_stream_fill, dim3(zgrid(n)), dim3(ZT), 0, s, kseed, kstart, keys, n, lev, d, words,
                        (unsigned long long*)W, L);
     return hipGetLastError();
 }
 
-hipError_t launch_stream_collect(uint64_t kseed, uint64_t kstart, uint64_t n, const DevLevel* lev, uint32_t d,
-                                 const uint64_t* words, uint64_t* out, uint64_t cap, unsigned long long* count,
-                                 hipStream_t s) {
+hipError_t launch_stream_collect(uint64_t kseed, uint64_t kstart, const uint64_t* keys, uint64_t n,
+                                 const DevLevel* lev, uint32_t d, const uint64_t* words, uint64_t* out, uint64_t cap,
+                                 unsigned long long* count, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_stream_collect, dim3(zgrid(n)), dim3(ZT), 0, s, kseed, kstart, n, lev, d, words, out, cap,
-                       count);
+    hipLaunchKernelGGL(k_stream_collect, dim3(zgrid(n)), dim3(ZT), 0, s, kseed, kstart, keys, n, lev, d, words, out,
+                       cap, count);
     return hipGetLastError();
 }
 

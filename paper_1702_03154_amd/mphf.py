@@ -124,6 +124,7 @@ def lib() -> C.CDLL:
             "mphf_build_stream": (st, [C.POINTER(KeyStream), u64, C.c_double, u64, C.POINTER(Opts), u64, vp,
                                        C.POINTER(vp)]),
             "mphf_stream_keys": (st, [C.POINTER(KeyStream), u64, u64, vp, vp]),
+            "mphf_build_host": (st, [vp, u64, C.c_double, u64, C.POINTER(Opts), u64, vp, C.POINTER(vp)]),
             "mphf_kmers": (st, [vp, u64, u32, vp, vp]),
             "mphf_first_occurrences": (st, [vp, u64, u64, vp, C.POINTER(C.c_uint64), vp]),
             "mphf_partition_sets": (st, [vp, u64, u32, u64, vp, vp, vp]),
@@ -394,6 +395,23 @@ def build_stream(n: int, key_seed: int, gamma: float = 2.0, seed: int = 0, resid
     with torch.cuda.device(dev):
         _check(L.mphf_build_stream(C.byref(src), n, float(gamma), seed & (2**64 - 1), C.byref(o), resident_keys,
                                    _stream(stream), C.byref(h)))
+    return MPHF(h.value, dev)
+
+
+def build_host(keys, gamma: float = 2.0, seed: int = 0, resident_keys: int = 1 << 31, max_levels: int = 25,
+               rank_sample: int = 512, atomic_levels: bool = False, device=None, stream=None) -> "MPHF":
+    """Streaming build over keys stored in host memory (mphf_build_host): a numpy uint64/int64 array or
+    a HostArray; every streamed level copies the keys to the device in chunks."""
+    a = keys.a if isinstance(keys, HostArray) else keys
+    if not isinstance(a, np.ndarray) or a.dtype.itemsize != 8 or not a.flags.c_contiguous:
+        raise ValueError("keys must be a contiguous 64-bit host array")
+    L = lib()
+    o = Opts(max_levels, rank_sample, 0, 0, 1 if atomic_levels else 0)
+    h = C.c_void_p()
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    with torch.cuda.device(dev):
+        _check(L.mphf_build_host(a.ctypes.data if len(a) else 0, len(a), float(gamma), seed & (2**64 - 1),
+                                 C.byref(o), resident_keys, _stream(stream), C.byref(h)))
     return MPHF(h.value, dev)
 
 

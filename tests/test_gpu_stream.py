@@ -1,6 +1,6 @@
-"""GPU parity of the streaming build (keys generated on the fly, re-scanned at every streamed
-level, Section 3.4's second strategy): the function must equal the oracle's on the materialized
-keys bit for bit, whatever the number of streamed levels."""
+"""GPU parity of the streaming build (keys generated on the fly, or stored in host memory, re-scanned
+at every streamed level, Section 3.4's second strategy): the function must equal the oracle's on the
+same keys bit for bit, whatever the number of streamed levels."""
 import numpy as np
 import pytest
 import torch
@@ -87,3 +87,74 @@ def test_streamed_build_large(M):
     lab = h.lookup(keys)
     assert torch.equal(lab, ref.lookup(keys))
     assert torch.equal(torch.sort(lab).values, torch.arange(1, n + 1, device=lab.device))
+
+
+# ------------------------------------------------------------ stored keys in host memory
+
+def check_host(M, keys, gamma, resident, pinned=False, max_levels=25, atomic=False, queries=None):
+    """mphf_build_host over keys held in host memory (pinned or pageable), re-read at every streamed
+    level, against the oracle on the same keys."""
+    arr = keys
+    pin = None
+    if pinned:
+        pin = M.HostArray(len(keys))
+        pin.a[:] = keys
+        arr = pin
+    h = M.build_host(arr, gamma, 0, resident_keys=resident, max_levels=max_levels, atomic_levels=atomic)
+    st = O.build(keys, gamma, 0, max_levels=max_levels)
+    s = h.stats()
+    assert s["level_n"] == [l.n for l in st.levels]
+    assert s["level_m"] == [l.m for l in st.levels]
+    assert s["level_weight"] == [l.weight for l in st.levels]
+    ex = h.export()
+    assert np.array_equal(ex["words"], st.words)
+    assert np.array_equal(ex["rank"], st.rank)
+    assert np.array_equal(ex["fallback_keys"], st.fallback_keys)
+    if len(keys):
+        q = torch.from_numpy(keys.view(np.int64)).cuda()
+        assert np.array_equal(host(h.lookup(q)), O.lookup(st, keys))
+    if queries is not None:
+        q = torch.from_numpy(queries.view(np.int64)).cuda()
+        assert np.array_equal(host(h.lookup(q)), O.lookup(st, queries))
+    streamed = [p for p in s["level_path"] if p.startswith("streamed")]
+    h.close()
+    if pin is not None:
+        pin.close()
+    return streamed
+
+
+@pytest.mark.parametrize("n,resident", [(0, 0), (1, 0), (1000, 0), (300_000, 1000), (300_000, 10 ** 9)])
+def test_host_keys_equal_the_oracle(M, n, resident):
+    keys = I.keys(n, 41).numpy().view(np.uint64)
+    check_host(M, keys, 2.0, resident)
+
+
+def test_host_keys_in_several_chunks_pinned_and_pageable(M):
+    """3e6 stored keys in chunks of 2^20, every level streamed until 1000 survivors remain: pinned
+    and pageable host arrays, the LDS-accumulated and the global-atomic levels, gamma 1 and 2."""
+    keys = I.keys(3_000_000, 43).numpy().view(np.uint64)
+    absent = I.keys(20_000, 44).numpy().view(np.uint64)
+    streamed = check_host(M, keys, 2.0, 1000, pinned=True, queries=absent)
+    assert len(streamed) >= 5 and set(streamed) == {"streamed"}
+    assert set(check_host(M, keys, 2.0, 1000, atomic=True)) == {"streamed_atomic"}
+    check_host(M, keys[:1_500_000].copy(), 1.0, 100_000)
+
+
+def test_host_keys_structured_and_with_fallback(M):
+    """Keys that are not random (dense integers, a strided set) and a forced fallback table."""
+    k = np.unique(np.concatenate([np.arange(1, 400_001, dtype=np.uint64),
+                                  np.arange(200_001, dtype=np.uint64) * np.uint64(2**40) + np.uint64(2**63)]))
+    check_host(M, k, 2.0, 5000)
+    check_host(M, I.keys(100_000, 45).numpy().view(np.uint64), 2.0, 0, max_levels=3)
+
+
+def test_host_keys_duplicates_and_device_pointer_rejected(M):
+    keys = I.keys(200_000, 46).numpy().view(np.uint64).copy()
+    keys[150_000] = keys[7]
+    with pytest.raises(M.DuplicateKeysError):
+        M.build_host(keys, 2.0, 0, resident_keys=1000)
+    import ctypes
+    d = torch.from_numpy(keys.view(np.int64)).cuda()
+    h = ctypes.c_void_p()
+    st = M.lib().mphf_build_host(d.data_ptr(), 1000, 2.0, 0, None, 0, None, ctypes.byref(h))
+    assert st == M.E_INVALID and not h.value
