@@ -655,10 +655,12 @@ def bench_kmer(args):
 
 
 def bench_stream(args):
-    """Streaming build over n generated keys (never stored), then the lookup of every key,
-    regenerated chunk by chunk; bijection checked with one byte per label."""
+    """Streaming build over n generated keys (never stored), or with --stream-host over the same keys
+    stored in pinned host memory; then the lookup of every key, regenerated chunk by chunk; bijection
+    checked with one byte per label."""
     import statistics
 
+    import numpy as np
     import torch
 
     from paper_1702_03154_amd import mphf
@@ -668,7 +670,17 @@ def bench_stream(args):
     n = int(args.n)
     resident = int(args.resident_keys)
     s = torch.cuda.current_stream()
-    build_ms = []
+    host = None
+    if args.stream_host:
+        # the same keys stored in pinned host memory, filled from the device in chunks
+        t0 = time.perf_counter()
+        host = mphf.HostArray(n)
+        step = 1 << 28
+        for c0 in range(0, n, step):
+            c = min(step, n - c0)
+            host.a[c0:c0 + c] = mphf.stream_keys(1, c0, c).cpu().numpy().view(np.uint64)
+        log(f"{n} keys in pinned host memory ({8 * n / 2**30:.1f} GiB) in {time.perf_counter() - t0:.1f} s")
+    build_ms, builds = [], []
     h = None
     for it in range(args.warmup + args.steps):
         if h is not None:
@@ -676,12 +688,18 @@ def bench_stream(args):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(s)
-        h = mphf.build_stream(n, 1, args.gamma, 0, resident_keys=resident)
+        if host is not None:
+            h = mphf.build_host(host, args.gamma, 0, resident_keys=resident)
+        else:
+            h = mphf.build_stream(n, 1, args.gamma, 0, resident_keys=resident)
         e1.record(s)
         torch.cuda.synchronize()
+        paths = h.stats()["level_path"]
+        builds.append({"ms": e0.elapsed_time(e1), "streamed": sum(p.startswith("streamed") for p in paths),
+                       "paths": sorted(set(paths))})
         if it >= args.warmup:
             build_ms.append(e0.elapsed_time(e1))
-        print(f"# stream build {it}: {e0.elapsed_time(e1):.1f} ms", file=sys.stderr, flush=True)
+        log(f"stream build {it}: {e0.elapsed_time(e1):.1f} ms, level paths {sorted(set(paths))}")
     st = h.stats()
     chunk = 1 << 28
     seen = torch.zeros(n, dtype=torch.int8, device=dev)
@@ -710,10 +728,13 @@ def bench_stream(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb + lookup_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"streaming build over {n} SplitMix64 keys (seed 1) generated on the fly, "
+        "config": {"workload": f"streaming build over {n} SplitMix64 keys (seed 1) "
+                               f"{'stored in pinned host memory' if host is not None else 'generated on the fly'}, "
                                f"re-scanned while more than {resident} survive, gamma={args.gamma}; "
                                f"lookup of every key regenerated in chunks",
-                   "n": n, "gamma": args.gamma, "resident_keys": resident},
+                   "n": n, "gamma": args.gamma, "resident_keys": resident,
+                   "key_source": "host" if host is not None else "generated"},
+        "builds": builds,
         "build_keys_per_s": n / (tb / 1e3), "lookup_queries_per_s": n / (lookup_ms / 1e3),
         "build_ms": tb, "lookup_ms": lookup_ms, "labels_bijective": ok,
         "levels": st["num_levels"], "streamed_levels": streamed, "bits_per_key": st["bits_per_key"],
@@ -721,6 +742,8 @@ def bench_stream(args):
         "level_n": st["level_n"][:st["num_levels"]],
     }
     h.close()
+    if host is not None:
+        host.close()
     print(json.dumps(res))
 
 
@@ -817,6 +840,7 @@ def main():
     ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer", "stream", "gamma", "roofline"],
                     default="plain")
     ap.add_argument("--resident-keys", type=float, default=2 ** 31, help="stream: survivors kept in memory")
+    ap.add_argument("--stream-host", action="store_true", help="stream: keys stored in pinned host memory")
     ap.add_argument("--kmer-bases", type=float, default=4.2e9, help="kmer: sequence length")
     ap.add_argument("--kmer-keys", type=float, default=4e9, help="kmer: distinct k-mers kept")
     ap.add_argument("--kmer-set-bits", type=float, default=15, help="kmer: log2 of the batched sets")

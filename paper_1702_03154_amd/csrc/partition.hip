@@ -192,16 +192,37 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
         // whole lines: key g of bin d comes from the unfinished line (g < run before the tile)
         // or from the tile's sorted run
         const uint32_t nf = S.nf;
-        for (uint32_t f = threadIdx.x; f < nf; f += PT) {
-            const uint32_t d = S.lbin[f / LW];
-            const uint32_t r = S.rold[d];
-            const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - S.fpre[d]);
-            // the key's index in the unfinished line (g < r) or in the sorted tile, blended with a
-            // mask rather than a branch (the lanes of a line take both sides)
-            const uint32_t ic = PTILE + d * LW + (g & (LW - 1));
-            const uint32_t it = S.hoff[d] + (g - r);
-            const uint64_t v = S.kbuf[ic + ((it - ic) & (0u - (uint32_t)(g >= r)))];
-            if (DIG == 2 ? g >= S.a0[d] : g < out_cap) obase[S.dst[d] + g] = v;
+        if constexpr (DIG == 2) {
+            for (uint32_t f = threadIdx.x; f < nf; f += PT) {
+                const uint32_t d = S.lbin[f / LW];
+                const uint32_t r = S.rold[d];
+                const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - S.fpre[d]);
+                // the key's index in the unfinished line (g < r) or in the sorted tile, blended with a
+                // mask rather than a branch (the lanes of a line take both sides)
+                const uint32_t ic = PTILE + d * LW + (g & (LW - 1));
+                const uint32_t it = S.hoff[d] + (g - r);
+                const uint64_t v = S.kbuf[ic + ((it - ic) & (0u - (uint32_t)(g >= r)))];
+                if (g >= S.a0[d]) obase[S.dst[d] + g] = v;
+            }
+        } else {
+            // four consecutive keys of a line per lane (two 16-byte stores; four lanes per line): the
+            // line's bookkeeping is read and computed once per four keys
+            for (uint32_t f = 4 * threadIdx.x; f < nf; f += 4 * PT) {
+                const uint32_t d = S.lbin[f / LW];
+                const uint32_t r = S.rold[d];
+                const uint32_t g = (r & ~(uint32_t)(LW - 1)) + (f - S.fpre[d]);   // a multiple of 4
+                const uint32_t ic = PTILE + d * LW + (g & (LW - 1));
+                const uint32_t it = S.hoff[d] + (g - r);
+                uint64_t v[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+                    v[u] = S.kbuf[(g + u >= r) ? it + u : ic + u];
+                if (g < out_cap) {   // out_cap is a multiple of 16: the four keys are in or out together
+                    ulonglong2* o = (ulonglong2*)(obase + S.dst[d] + g);
+                    o[0] = make_ulonglong2(v[0], v[1]);
+                    o[1] = make_ulonglong2(v[2], v[3]);
+                }
+            }
         }
         __syncthreads();
         // keys past the last whole line start the bin's next unfinished line (run[] already

@@ -298,3 +298,49 @@ def test_tail_only_sizes(M):
     # every size up to one workgroup's LDS is built by the single-workgroup kernel
     for n in (7, 1000, 16_000, 16_384, 16_385, 20_000):
         check_against_oracle(M, keys_np(n, seed=n), 2.0)
+
+
+def test_level1_bucket_overflow_falls_back_with_hashed_survivors(M):
+    """Keys crafted so that level 0 builds by partition but one bucket of level 1 (2^8 positions,
+    room for 347 keys) receives more than 400: level 1 and the levels after it are redone with global
+    atomics from level 0's partitioned survivors, and every bit, counter and label must still equal the
+    oracle's."""
+    gamma, bits = 2.0, 8
+    rest = keys_np(100_000, seed=57)
+    n_adv_groups, per_group = 20, 20
+    N = len(rest) + n_adv_groups * per_group
+    m0 = math.ceil(gamma * N)
+    s0, s1 = O.level_seeds(0, 2)
+    rng = np.random.default_rng(11)
+    # level-0 positions of the groups: one per distinct bucket of 2^8 positions
+    p0s = (rng.choice(m0 >> bits, size=n_adv_groups, replace=False).astype(np.int64) << bits) + 7
+    # |F_1| does not depend on which keys of a group are chosen (each group collides at its p0), so
+    # m1 follows from the random keys and the groups' positions alone
+    pos_rest = O.level_positions(rest, s0, m0).astype(np.int64)
+    cnt = np.bincount(np.concatenate([pos_rest, np.repeat(p0s, per_group)]), minlength=m0)
+    n1 = int((cnt[pos_rest] >= 2).sum()) + n_adv_groups * per_group
+    m1 = math.ceil(gamma * n1)
+    inv1 = pow(0xFF51AFD7ED558CCD, -1, 1 << 64)
+    inv2 = pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)
+    adv = []
+    for p0 in p0s.tolist():
+        found = 0
+        while found < per_group:
+            js = rng.integers(1, 2**40, size=4096).astype(object)
+            hs = [p0 + int(j) * m0 for j in js]
+            xs = np.array([unfmix64(h) ^ s0 for h in hs], dtype=np.uint64)
+            ok = O.level_positions(xs, s1, m1) < (1 << bits)
+            for x in xs[ok].tolist():
+                if found < per_group:
+                    adv.append(x)
+                    found += 1
+    k = np.concatenate([rest, np.array(adv, dtype=np.uint64)])
+    assert len(np.unique(k)) == len(k) == N
+    st = O.build(k, gamma, 0)
+    assert st.levels[1].n == n1 and st.levels[1].m == m1
+    # every crafted key survives level 0 and lands in level 1's first bucket: 400 > 347 keys
+    assert np.all(O.level_positions(np.array(adv, dtype=np.uint64), s1, m1) < (1 << bits))
+
+    def want(p):
+        assert p[0] == "one_pass" and set(p[1:]) == {"atomic"}, p
+    check_against_oracle(M, k, gamma, bucket_bits=bits, paths=want, queries_np=keys_np(5000, seed=58))
