@@ -100,6 +100,7 @@ struct mphf {
     uint64_t nfb = 0;
     uint32_t* sec = nullptr;        // lookup layout: 64-byte sectors of (rank counter, 480 bits of A)
     uint64_t* super = nullptr;
+    void* layout = nullptr;         // the one allocation holding sec, super and rank
     uint64_t nsec = 0;
     DevLevel* dlev = nullptr;
     uint64_t* coll_all = nullptr;   // C of every level, laid out like A (keep_collisions)
@@ -288,7 +289,7 @@ void free_handle(mphf* h) {
     if (!h) return;
     // lookups may still be in flight on the streams that used h: wait for those, then free
     h->uses.wait_all();
-    free_on_device(h->device, {h->words, h->rank, h->fb_keys, h->dlev, h->coll_all, h->sec, h->super});
+    free_on_device(h->device, {h->words, h->fb_keys, h->dlev, h->coll_all, h->layout});
     delete h;
 }
 
@@ -608,9 +609,12 @@ class Builder {
             HIP_TRY(hipHostMalloc((void**)&host_, 4096, hipHostMallocDefault), "hipHostMalloc");
             if (cached_) ws_->host = host_;
         }
-        if ((st = ar_.alloc(&dev_, 512, "counters")) != MPHF_OK) return st;
-        HIP_TRY(launch_zero(dev_, 512, s_), "zero counters");
-        if ((st = ar_.alloc(&tail_rec_, MPHF_MAX_LEVELS, "tail records")) != MPHF_OK) return st;
+        HIP_TRY(hipHostGetDevicePointer((void**)&host_dev_, host_, 0), "hipHostGetDevicePointer");
+        // counters, flags and the tail's level records in one small allocation
+        static_assert(sizeof(TailLevel) * MPHF_MAX_LEVELS <= 8 * 256, "tail records after the counters");
+        if ((st = ar_.alloc(&dev_, 512 + 256, "counters")) != MPHF_OK) return st;
+        HIP_TRY(launch_zero(dev_, 512 + 256, s_), "zero counters");
+        tail_rec_ = (TailLevel*)(dev_ + 512);
         // The concatenated A: reserve the expected gamma e^{1/gamma} N bits (Section 2.3) plus
         // slack; grown by copying in the rare case the levels need more.
         {
@@ -630,11 +634,9 @@ class Builder {
         mphf_status st;
         const bool atomic_only = o_.flags & MPHF_FLAG_ATOMIC_LEVELS;
         KeySet cur;
-        uint64_t* pre0 = nullptr;
-        if ((st = ar_.alloc(&pre0, 2, "prefix")) != MPHF_OK) return st;
-        host_[0] = 0;
-        host_[1] = n;
-        HIP_TRY(hipMemcpyAsync(pre0, host_, 16, hipMemcpyHostToDevice, s_), "copy prefix");
+        uint64_t* pre0 = dev_ + 400;   // the one-segment prefix {0, n} of the input
+        HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");   // the partitioned levels' flag
+        HIP_TRY(launch_pair(pre0, 0, n, s_), "prefix");
         cur.base = keys;
         cur.pre = pre0;
         cur.nseg = 1;
@@ -719,9 +721,11 @@ class Builder {
     BucketGeometry geo_{};
     SeedTable seeds_{};
     uint64_t* host_ = nullptr;
+    uint64_t* host_dev_ = nullptr;   // host_ as the device sees it (pinned, device-writable)
     uint64_t* dev_ = nullptr;        // [0..63] weights, [64..127] survivor counts, [128] dup flag,
                                      // [129] overflow flag, [130..132] tail summary, [200] streamed
-                                     // survivors, [300] keys collected from a stream chunk
+                                     // survivors, [300] keys collected from a stream chunk, [400..401]
+                                     // the input's prefix, [512..767] the tail's level records
     TailLevel* tail_rec_ = nullptr;
     uint64_t* words_ = nullptr;
     uint64_t* coll_ = nullptr;
@@ -868,7 +872,7 @@ class Builder {
                                      fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, n, in.nseg, s_,
                                      3, nullptr, pb + fb),
                     "partition 1");
-            HIP_TRY(launch_zero32(ws_->cntZ + C * W, 1, s_), "zero count tail");
+            // (the pass writes the count after the last region as 0, for the scan's total)
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
             if ((st = prefix(ws_->cntZ, C * W, ws_->preZ)) != MPHF_OK) return st;
             const uint64_t K = slots_per_group(C, n);
@@ -906,8 +910,7 @@ class Builder {
         const uint64_t B = (m + P - 1) / P;
         const uint32_t lb = ceil_log2(B);
         if (lb > 18) return MPHF_OK;   // beyond two passes: use the atomic levels
-        unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
-        HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
+        unsigned long long* ovf = (unsigned long long*)(dev_ + 129);   // zero here (cleared by each report)
         uint64_t xcap;
         uint32_t S;
         uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
@@ -923,11 +926,11 @@ class Builder {
         HIP_TRY(launch_bucket(X, xcap, ws_->cntX, S, B, L, pb, packed, g.kcap, words_ + off / 64, C_level, wd,
                               ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_),
                 "bucket");
-        HIP_TRY(launch_zero32(ws_->surv[yp] + B, 1, s_), "zero count tail");
+        // (the bucket pass writes the count after the last bucket as 0, for the scan's total)
         if ((st = prefix(ws_->surv[yp], B, ws_->preY[yp])) != MPHF_OK) return st;
-        // the overflow flag and the survivor total, read back together
-        HIP_TRY(hipMemcpyAsync(host_, dev_ + 129, 8, hipMemcpyDeviceToHost, s_), "read back");
-        HIP_TRY(hipMemcpyAsync(host_ + 1, ws_->preY[yp] + B, 8, hipMemcpyDeviceToHost, s_), "read back");
+        // the overflow flag and the survivor total, written to pinned host memory by one small kernel
+        // (which also clears the flag for the next level)
+        HIP_TRY(launch_report(ovf, ws_->preY[yp] + B, host_dev_, s_), "report");
         HIP_TRY(hipStreamSynchronize(s_), "level sync");
         if (host_[0]) return MPHF_OK;   // overflow: redo with atomics
         const uint64_t nnext = host_[1];
@@ -1061,22 +1064,27 @@ class Builder {
         h_->nsec = sector_count(h_->total_bits);
         if (!h_->nsec) return MPHF_OK;   // no bits: no rank entries either
         mphf_status st;
-        uint32_t *cnt = nullptr, *rc = nullptr;
-        uint64_t *pre = nullptr, *tiles = nullptr;
-        if ((st = ar_.alloc(&h_->rank, h_->nrank, "rank")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&h_->sec, h_->nsec * 16, "lookup sectors")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&h_->super, super_count(h_->nsec), "lookup superblocks")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&cnt, h_->nsec, "sector counts")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&rc, h_->nrank, "rank counts")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&pre, h_->nsec, "sector prefix")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&tiles, scan_tmp_tiles(std::max(h_->nsec, h_->nrank)), "scan tiles")) != MPHF_OK)
-            return st;
+        // one allocation for what the function keeps (sectors, superblocks, rank table) and one for
+        // the temporaries, each part on a 256-byte boundary
+        auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+        const uint64_t sec_b = up(h_->nsec * 64), sup_b = up(super_count(h_->nsec) * 8), rank_b = up(h_->nrank * 8);
+        const uint64_t cnt_b = up(h_->nsec * 4), rc_b = up(h_->nrank * 4), pre_b = up(h_->nsec * 8);
+        const uint64_t tiles_b = up(scan_tmp_tiles(std::max(h_->nsec, h_->nrank)) * 8);
+        uint8_t *keep = nullptr, *tmp = nullptr;
+        if ((st = ar_.alloc(&keep, sec_b + sup_b + rank_b, "lookup sectors and rank table")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&tmp, cnt_b + rc_b + pre_b + tiles_b, "rank and sector temporaries")) != MPHF_OK) return st;
+        h_->sec = (uint32_t*)keep;
+        h_->super = (uint64_t*)(keep + sec_b);
+        h_->rank = (uint64_t*)(keep + sec_b + sup_b);
+        h_->layout = keep;
+        uint32_t* cnt = (uint32_t*)tmp;
+        uint32_t* rc = (uint32_t*)(tmp + cnt_b);
+        uint64_t* pre = (uint64_t*)(tmp + cnt_b + rc_b);
+        uint64_t* tiles = (uint64_t*)(tmp + cnt_b + rc_b + pre_b);
         HIP_TRY(launch_rank_sectors(words_, h_->total_bits, o_.rank_sample, h_->rank, h_->nrank, h_->sec, h_->super,
                                     cnt, rc, pre, tiles, s_),
                 "rank and sectors");
-        ar_.keep(h_->rank);
-        ar_.keep(h_->sec);
-        ar_.keep(h_->super);
+        ar_.keep(keep);
         return MPHF_OK;
     }
 

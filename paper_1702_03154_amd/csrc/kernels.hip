@@ -342,6 +342,16 @@ __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* _
     }
 }
 
+// A level's overflow flag and survivor total written to host memory the device can write (one small
+// kernel rather than two copies), and the flag cleared for the next level.
+__global__ void k_report(unsigned long long* flag, const uint64_t* __restrict__ total, uint64_t* out) {
+    if (threadIdx.x == 0) {
+        out[0] = *flag;
+        out[1] = *total;
+        *flag = 0;
+    }
+}
+
 __global__ void k_positions(const uint64_t* __restrict__ keys, uint64_t n, LevelHash L,
                             uint64_t* __restrict__ out) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -481,6 +491,11 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_lookup, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, q, n, out, lev, nlev,
                        sec, super, fb_keys, nfb, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, flag, total, out);
     return hipGetLastError();
 }
 

@@ -434,6 +434,8 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
         }
     }
     if constexpr (!DENSE) {
+        // the entry after the last region is 0, so an exclusive scan of the counts ends in the total
+        if (blockIdx.x == 0 && threadIdx.x == 0) out_cnt[nbins * S_out] = 0;
         for (uint64_t d = threadIdx.x; d < lim; d += PT) {
             out_cnt[(bin_base + d) * S_out + slot] = S.run[d] < out_cap ? S.run[d] : (uint32_t)out_cap;
             if (S.run[d] > out_cap) atomicOr(overflow, 1ull);
@@ -535,6 +537,7 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
         if (threadIdx.x == 0) {
             atomicOr(overflow, 2ull);
             surv[b] = 0;
+            if (b == 0) surv[gridDim.x] = 0;
         }
         return;
     }
@@ -615,7 +618,10 @@ k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __res
         if (keep) dst[wo + __popcll(bal & below)] = unfmix64(h[it]) ^ L.seed;
         wo += (uint32_t)__popcll(bal);
     }
-    if (threadIdx.x == 0) surv[b] = tot;
+    if (threadIdx.x == 0) {
+        surv[b] = tot;
+        if (b == 0) surv[gridDim.x] = 0;   // the entry after the last bucket, for the scan's total
+    }
 }
 
 // ---------------------------------------------------------------- accumulating a level by chunks
