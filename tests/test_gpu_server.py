@@ -1,6 +1,6 @@
 """GPU tests of the serving loop: resident functions, requests admitted by HBM budget and batched as
-they arrive.  A request's labels must be exactly those of a plain lookup on its function (and of
-the oracle on small functions), whether it runs alone or in a mix with other requests."""
+they arrive.  A request's labels must be exactly those of a plain lookup on its function and of the
+oracle built on that function's keys, whether it runs alone or in a mix with other requests."""
 import threading
 
 import numpy as np
@@ -32,6 +32,12 @@ def fns(M):
         k = I.keys(n, 100 + j)
         out.append((M.build(k.cuda(), 2.0, 0), k.numpy().view(np.uint64)))
     return out
+
+
+@pytest.fixture(scope="module")
+def oracles(fns):
+    """The oracle's build of every resident function (2.5e6 keys in all)."""
+    return [O.build(keys, 2.0, 0) for _, keys in fns]
 
 
 def make_requests(fns, count, seed, max_n=40_000):
@@ -66,7 +72,9 @@ def run(server, ids, reqs, pinned=None):
     return outs, infos
 
 
-def test_results_alone_and_in_the_mix(M, fns):
+def test_results_alone_and_in_the_mix(M, fns, oracles):
+    """Every request's labels, served alone and in a mix of 240, equal a plain lookup on its function
+    and the oracle's labels (members and the 10% non-members) for every function, up to 2e6 keys."""
     reqs = make_requests(fns, 240, seed=1)
     s = M.Server(hbm_budget=256 << 20, max_inflight=2)
     ids = [s.register(h) for h, _ in fns]
@@ -79,6 +87,7 @@ def test_results_alone_and_in_the_mix(M, fns):
     for i, (f, q) in enumerate(reqs):
         want = plain_labels(M, fns, f, q)
         assert np.array_equal(mixed[i], want), i
+        assert np.array_equal(mixed[i], O.lookup(oracles[f], q)), i
         if i < 40:
             assert np.array_equal(alone[i], want), i
     # continuous batching: requests shared batches, and batches overlapped on the device
