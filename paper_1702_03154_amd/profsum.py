@@ -7,6 +7,10 @@
         1 GiB calibration copy (bench.py --calibrate-copy) run in the same process
     python -m paper_1702_03154_amd.profsum build-traffic <fetch.db> <write.db> <keys> <out.json>
         the same for every library kernel of the one build before the first lookup
+    python -m paper_1702_03154_amd.profsum steps <results.db> <k>
+        the first k build + lookup steps of a kernel trace, one line each: the summed durations of
+        the library kernels from the step's first kernel to its k_lookup (the build's kernel time),
+        the span of those kernels on the device clock, and the k_lookup launch itself
 
 Kernel names are shortened (namespace and argument list dropped).
 """
@@ -18,7 +22,7 @@ import sys
 
 
 def short(name: str) -> str:
-    name = name.replace("mphfk::(anonymous namespace)::", "")
+    name = name.replace("mphfk::", "").replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*$", "", name)
     return name[:60]
 
@@ -123,6 +127,51 @@ def build_traffic(fetch_db: str, write_db: str, keys: int, out_json: str):
     print(json.dumps(res, indent=1))
 
 
+def _is_library(name: str) -> bool:
+    """A kernel of the build or lookup path (the roofline probes are left out)."""
+    sn = short(name)
+    return ("mphfk" in name or sn.startswith(("k_", "void k_"))) and "k_probe" not in sn
+
+
+def steps(db: str, k: int, out=sys.stdout):
+    """Splits a kernel trace of bench.py into its build + lookup steps: each step ends with a
+    k_lookup dispatch, and its build is every library kernel dispatched since the previous one."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, start, end, grid_x, workgroup_x from kernels order by start").fetchall()
+    print(f"{'step':>4s} {'build_kernels':>14s} {'build_kernel_ms':>16s} {'build_span_ms':>14s} "
+          f"{'lookup_ms':>10s} {'lookup_grid':>12s} {'lookup_wg':>10s}", file=out)
+    cur, done, lk, last = [], 0, [], []
+    for name, t0, t1, gx, wx in rows:
+        if not _is_library(name):
+            continue
+        if short(name) == "k_lookup":
+            busy = sum(b - a for _, a, b in cur)
+            span = (cur[-1][2] - cur[0][1]) if cur else 0
+            print(f"{done:4d} {len(cur):14d} {busy / 1e6:16.3f} {span / 1e6:14.3f} {(t1 - t0) / 1e6:10.3f} "
+                  f"{gx:12d} {wx:10d}", file=out)
+            lk.append((t1 - t0) / 1e6)
+            last = cur
+            cur = []
+            done += 1
+            if done == k:
+                break
+        else:
+            cur.append((short(name), t0, t1))
+    if len(lk) > 1:
+        print(f"mean k_lookup over steps 1..{len(lk) - 1} (after the first): "
+              f"{sum(lk[1:]) / (len(lk) - 1):.3f} ms", file=out)
+    if last:
+        # the build of the last step by kernel, in order of first dispatch
+        agg = {}
+        for n, a, b in last:
+            c, t, big = agg.get(n, (0, 0, 0))
+            agg[n] = (c + 1, t + (b - a), max(big, b - a))
+        print(f"\nbuild of step {done - 1} by kernel:", file=out)
+        print(f"{'kernel':48s} {'calls':>6s} {'total_ms':>9s} {'longest_ms':>11s}", file=out)
+        for n, (c, t, big) in agg.items():
+            print(f"{n:48s} {c:6d} {t / 1e6:9.3f} {big / 1e6:11.3f}", file=out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
@@ -130,6 +179,8 @@ if __name__ == "__main__":
         pmc(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(float(sys.argv[5])), sys.argv[6])
+    elif sys.argv[1] == "steps":
+        steps(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "build-traffic":
         build_traffic(sys.argv[2], sys.argv[3], int(float(sys.argv[4])), sys.argv[5])
     else:

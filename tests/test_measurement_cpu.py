@@ -71,3 +71,33 @@ def test_build_traffic_counts_library_kernels_before_the_first_lookup(tmp_path):
 def test_short_names_drop_namespace_and_arguments():
     assert profsum.short("mphfk::(anonymous namespace)::k_lookup(unsigned long const*, int)") == "k_lookup"
     assert profsum.short("void mphfk::(anonymous namespace)::k_bucket<true>(int)") == "void k_bucket<true>"
+
+
+def test_steps_split_a_trace_into_build_and_lookup(tmp_path):
+    """profsum steps: each step ends with a k_lookup dispatch; its build is every library kernel since
+    the previous one (torch kernels and the roofline probes left out)."""
+    import io
+    import sqlite3
+
+    db = str(tmp_path / "k.db")
+    c = sqlite3.connect(db)
+    c.execute("create table kernels(name text, start int, end int, grid_x int, workgroup_x int)")
+    rows = [("void at::native::fill_kernel(int)", 0, 10, 1, 1),
+            ("void mphfk::(anonymous namespace)::k_partition<8, false, false, 3>(x)", 100, 1100, 10, 768),
+            ("mphfk::(anonymous namespace)::k_bucket<true>(x)", 1200, 1700, 10, 1024),
+            ("mphfk::(anonymous namespace)::k_lookup(x)", 2000, 3000, 4096, 256),
+            ("(anonymous namespace)::k_probe_copy(x)", 3100, 3200, 1, 1),
+            ("mphfk::(anonymous namespace)::k_tail(x)", 4000, 4300, 1, 1024),
+            ("mphfk::(anonymous namespace)::k_lookup(x)", 5000, 7000, 4096, 256)]
+    c.executemany("insert into kernels values (?,?,?,?,?)", rows)
+    c.commit()
+    out = io.StringIO()
+    profsum.steps(db, 5, out)
+    lines = out.getvalue().splitlines()
+    # step 0: two build kernels, 1.5 us busy over a 1.6 us span; step 1: the tail only
+    assert lines[1].split()[:5] == ["0", "2", "0.002", "0.002", "0.001"]
+    assert lines[2].split()[:5] == ["1", "1", "0.000", "0.000", "0.002"]
+    assert "mean k_lookup over steps 1..1" in lines[3] and lines[3].endswith("0.002 ms")
+    assert any(l.startswith("k_tail") for l in lines[5:])
+    assert not any("k_probe" in l for l in lines)
+    assert profsum.short("(anonymous namespace)::k_probe_copy(x)") == "k_probe_copy"
