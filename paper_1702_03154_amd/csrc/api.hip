@@ -360,6 +360,7 @@ class Builder {
 
     mphf_status run(const uint64_t* keys, uint64_t n, double gamma) {
         mphf_status st;
+        defer_ = true;   // the first level's radix passes are queued before the structure is allocated
         if ((st = setup(n, gamma)) != MPHF_OK) return st;
         return levels_and_finish(keys, n, 0, 0);
     }
@@ -622,7 +623,8 @@ class Builder {
             const uint64_t w0 = (level_size(gamma, n) + 63) / 64;
             uint64_t cap = (uint64_t)(expect * 1.02 / 64.0) + 4 * (uint64_t)o_.max_levels + 1024;
             if (cap < w0 + 1) cap = w0 + 1;
-            if ((st = ensure_words(cap)) != MPHF_OK) return st;
+            reserve_words_ = cap;
+            if (!defer_ && (st = reserve()) != MPHF_OK) return st;
         }
         tr_.mark("setup");
         return MPHF_OK;
@@ -693,6 +695,7 @@ class Builder {
 
     mphf_status finish() {
         mphf_status st;
+        if ((st = reserve()) != MPHF_OK) return st;
         if ((st = fallback_table()) != MPHF_OK) return st;
         tr_.mark("fallback table", (long)nleft_);
         if ((st = rank_and_lookup_layout()) != MPHF_OK) return st;
@@ -739,6 +742,38 @@ class Builder {
     const uint64_t* host_keys_ = nullptr;   // streaming build over a stored key set in host memory
     std::unique_lock<std::mutex> lock_;
     int ypar_ = 0;
+
+    // The structure's memory: A (reserve_words_ words, the expected size plus slack) and, sized for
+    // that many bits, the lookup sectors, superblocks and rank table with their temporaries.  Its
+    // host-side cost (large stream-ordered allocations) is paid once the first level's passes are
+    // queued, so that it overlaps them.
+    bool defer_ = false, reserved_ = false;
+    uint64_t reserve_words_ = 0;
+    uint8_t *pre_keep_ = nullptr, *pre_tmp_ = nullptr;
+    uint64_t pre_keep_bytes_ = 0, pre_tmp_bytes_ = 0;
+
+    static uint64_t up256(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+    uint64_t layout_keep_bytes(uint64_t bits) const {
+        const uint64_t ns = sector_count(bits), nr = (bits + o_.rank_sample - 1) / o_.rank_sample;
+        return ns ? up256(ns * 64) + up256(super_count(ns) * 8) + up256(nr * 8) : 0;
+    }
+    static uint64_t layout_tmp_bytes(uint64_t bits) {
+        const uint64_t ng = rank_sector_groups(bits);
+        return ng ? up256(ng * 4) + up256(ng * 8) + up256(scan_tmp_tiles(ng) * 8) : 0;
+    }
+
+    mphf_status reserve() {
+        if (reserved_) return MPHF_OK;
+        reserved_ = true;
+        mphf_status st;
+        if ((st = ensure_words(reserve_words_)) != MPHF_OK) return st;
+        const uint64_t bits = 64 * cap_words_;
+        pre_keep_bytes_ = layout_keep_bytes(bits);
+        pre_tmp_bytes_ = layout_tmp_bytes(bits);
+        if ((st = ar_.alloc(&pre_keep_, pre_keep_bytes_, "lookup sectors and rank table")) != MPHF_OK) return st;
+        if ((st = ar_.alloc(&pre_tmp_, pre_tmp_bytes_, "rank and sector temporaries")) != MPHF_OK) return st;
+        return MPHF_OK;
+    }
 
     void record(uint32_t d, uint64_t n, uint64_t m, uint64_t weight, uint64_t off, uint32_t path) {
         h_->level_path[d] = path;
@@ -903,7 +938,6 @@ class Builder {
         const uint64_t n = in.n;
         const uint64_t m = level_size(gamma_, n);
         const uint64_t wd = (m + 63) / 64;
-        if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
         const LevelHash L = make_level_hash(seeds_.s[d], m, off);
         const uint32_t pb = g.pbits;
         const uint64_t P = 1ull << pb;
@@ -916,6 +950,8 @@ class Builder {
         uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
         bool packed = false;
         if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, &packed, ovf)) != MPHF_OK) return st;
+        if ((st = reserve()) != MPHF_OK) return st;
+        if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
         // buckets: fill, finalize and filter in LDS
         const int yp = ypar_;
         ypar_ ^= 1;
@@ -949,6 +985,7 @@ class Builder {
     // Every remaining level in one workgroup (the set fits in its LDS).
     mphf_status tail(const KeySet& in, uint32_t d0, uint64_t off, uint32_t tk) {
         mphf_status st;
+        if ((st = reserve()) != MPHF_OK) return st;
         const uint32_t D = o_.max_levels;
         const uint64_t per = (uint64_t)std::ceil(gamma_ * tk) / 64 + 2;
         if ((st = ensure_words(off / 64 + (uint64_t)(D - d0) * per + 1)) != MPHF_OK) return st;
@@ -979,6 +1016,7 @@ class Builder {
     // partition overflows, or on request).  F is dense.
     mphf_status atomic_levels(const uint64_t* F, uint64_t n, uint32_t d0, uint64_t off) {
         mphf_status st;
+        if ((st = reserve()) != MPHF_OK) return st;
         const uint32_t D = o_.max_levels;
         const uint64_t m0 = level_size(gamma_, n);
         const uint64_t w0 = (m0 + 63) / 64;
@@ -1068,21 +1106,29 @@ class Builder {
         // the temporaries, each part on a 256-byte boundary
         auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
         const uint64_t sec_b = up(h_->nsec * 64), sup_b = up(super_count(h_->nsec) * 8), rank_b = up(h_->nrank * 8);
-        const uint64_t cnt_b = up(h_->nsec * 4), rc_b = up(h_->nrank * 4), pre_b = up(h_->nsec * 8);
-        const uint64_t tiles_b = up(scan_tmp_tiles(std::max(h_->nsec, h_->nrank)) * 8);
+        const uint64_t ng = rank_sector_groups(h_->total_bits);
+        const uint64_t cnt_b = up(ng * 4), pre_b = up(ng * 8), tiles_b = up(scan_tmp_tiles(ng) * 8);
         uint8_t *keep = nullptr, *tmp = nullptr;
-        if ((st = ar_.alloc(&keep, sec_b + sup_b + rank_b, "lookup sectors and rank table")) != MPHF_OK) return st;
-        if ((st = ar_.alloc(&tmp, cnt_b + rc_b + pre_b + tiles_b, "rank and sector temporaries")) != MPHF_OK) return st;
+        if (pre_keep_ && sec_b + sup_b + rank_b <= pre_keep_bytes_ && cnt_b + pre_b + tiles_b <= pre_tmp_bytes_) {
+            keep = pre_keep_;   // reserved with A (the levels stayed within the reservation)
+            tmp = pre_tmp_;
+        } else {
+            ar_.release(pre_keep_);
+            ar_.release(pre_tmp_);
+            if ((st = ar_.alloc(&keep, sec_b + sup_b + rank_b, "lookup sectors and rank table")) != MPHF_OK)
+                return st;
+            if ((st = ar_.alloc(&tmp, cnt_b + pre_b + tiles_b, "rank and sector temporaries")) != MPHF_OK) return st;
+        }
+        pre_keep_ = pre_tmp_ = nullptr;
         h_->sec = (uint32_t*)keep;
         h_->super = (uint64_t*)(keep + sec_b);
         h_->rank = (uint64_t*)(keep + sec_b + sup_b);
         h_->layout = keep;
         uint32_t* cnt = (uint32_t*)tmp;
-        uint32_t* rc = (uint32_t*)(tmp + cnt_b);
-        uint64_t* pre = (uint64_t*)(tmp + cnt_b + rc_b);
-        uint64_t* tiles = (uint64_t*)(tmp + cnt_b + rc_b + pre_b);
+        uint64_t* pre = (uint64_t*)(tmp + cnt_b);
+        uint64_t* tiles = (uint64_t*)(tmp + cnt_b + pre_b);
         HIP_TRY(launch_rank_sectors(words_, h_->total_bits, o_.rank_sample, h_->rank, h_->nrank, h_->sec, h_->super,
-                                    cnt, rc, pre, tiles, s_),
+                                    cnt, pre, tiles, s_),
                 "rank and sectors");
         ar_.keep(keep);
         return MPHF_OK;

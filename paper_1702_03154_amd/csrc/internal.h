@@ -258,8 +258,10 @@ uint64_t super_count(uint64_t nsec);
 // read of A: tmp_counts holds a u32 per sector, tmp_rank_counts a u32 per rank entry, tmp_pre a u64
 // per sector, tmp_tiles scan_tmp_tiles(max(sectors, rank entries)).
 hipError_t launch_rank_sectors(const uint64_t* words, uint64_t total_bits, uint32_t rank_sample, uint64_t* rank,
-                               uint64_t nrank, uint32_t* sec, uint64_t* super, uint32_t* tmp_counts,
-                               uint32_t* tmp_rank_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s);
+                               uint64_t nrank, uint32_t* sec, uint64_t* super, uint32_t* tmp_group_sums,
+                               uint64_t* tmp_group_pre, uint64_t* tmp_tiles, hipStream_t s);
+// Workgroups of the sector layout (256 sectors each): the sizes of the two temporaries above.
+uint64_t rank_sector_groups(uint64_t total_bits);
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
                          uint32_t nlev, const uint32_t* sec, const uint64_t* super,
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);

@@ -183,6 +183,31 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, uint64_t* __restri
     }
 }
 
+// The whole scan in one workgroup, tile after tile, for inputs of at most SCAN_SINGLE entries (one
+// launch instead of three; the per-level counts of the small levels).
+constexpr uint64_t SCAN_SINGLE = 4 * SCAN_TILE;
+
+__global__ void k_scan_single(const uint32_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n) {
+    __shared__ uint64_t sh[NT / 64 + 1];
+    uint64_t carry = 0;
+    for (uint64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
+        const uint64_t i0 = t0 + (uint64_t)threadIdx.x * SCAN_ITEMS;
+        uint32_t v[SCAN_ITEMS];
+        uint64_t s = 0;
+        for (int it = 0; it < SCAN_ITEMS; ++it) {
+            v[it] = i0 + it < n ? in[i0 + it] : 0;
+            s += v[it];
+        }
+        uint64_t total;
+        uint64_t run = carry + block_exclusive_sum<NT>(s, sh, &total);
+        for (int it = 0; it < SCAN_ITEMS; ++it) {
+            if (i0 + it < n) out[i0 + it] = run;
+            run += v[it];
+        }
+        carry += total;
+    }
+}
+
 // ---------------------------------------------------------------- radix sort (fallback keys)
 
 constexpr int RADIX_ROUNDS = 8;
@@ -260,64 +285,100 @@ __global__ void k_find_duplicates(const uint64_t* __restrict__ s, uint64_t n,
 // small aligned unit holding both the probed bit and what its rank needs: the 64-byte sectors of
 // device.h (Section 3.1's counters, here one 32-bit counter per 480 positions plus superblocks).
 //
-// Sector counts and rank-block counts from one read of A: workgroup g covers the 256 sectors
-// 256 g .. 256 g + 255, i.e. bits [122880 g, 122880 (g+1)), which is exactly 240 rank blocks of 512
-// positions (120 of 1024), so its rank blocks are counted in LDS and written once.  A sector's 480
-// bits meet at most two rank blocks, split on a 32-bit word boundary.
+// Sectors, superblocks and the rank table in two reads of A.  Workgroup g covers the 256 sectors
+// 256 g .. 256 g + 255, i.e. the 3840 u32 words of bits [122880 g, 122880 (g+1)), which is exactly
+// 240 rank blocks of 512 positions (120 of 1024).  The first kernel counts the ones of each
+// workgroup's range; one scan of those counts gives every workgroup the ones before it; the second
+// kernel loads its range into LDS again, counts its sectors and rank blocks there, scans them in
+// the workgroup and writes its sectors, its rank entries and, at a superblock's first workgroup
+// (2^21 sectors = 2^13 workgroups), the superblock entry.  Both read A with 16-byte coalesced loads.
 constexpr uint32_t SR_SECTORS = 256;
 constexpr uint64_t SR_BITS = SR_SECTORS * SEC_BITS;   // 122880
+constexpr uint32_t SR_WORDS = SR_SECTORS * 15;        // 3840 u32 words of A per workgroup
+constexpr uint32_t SUPER_GROUPS_SHIFT = SUPER_SHIFT - 8;   // workgroups per superblock: 2^13
 
-__global__ void __launch_bounds__(SR_SECTORS)
-k_sector_rank_counts(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec, uint32_t rshift,
-                     uint64_t nrank, uint32_t* __restrict__ sec_counts, uint32_t* __restrict__ rank_counts) {
-    __shared__ uint32_t rc[SR_BITS / 512];
-    const uint32_t nrb = (uint32_t)(SR_BITS >> rshift);   // rank blocks of this workgroup
-    for (uint32_t i = threadIdx.x; i < nrb; i += SR_SECTORS) rc[i] = 0;
-    __syncthreads();
-    const uint64_t j = (uint64_t)blockIdx.x * SR_SECTORS + threadIdx.x;
-    if (j < nsec) {
-        const uint64_t bit0 = j * SEC_BITS;
-        const uint64_t b0 = bit0 >> rshift;
-        // words of this sector before the next rank block's first bit (15 if it starts later)
-        const uint64_t split = ((b0 + 1) << rshift) - bit0;
-        const uint32_t wsplit = split >= SEC_BITS ? 15u : (uint32_t)(split >> 5);
-        uint32_t c0 = 0, c1 = 0;
-#pragma unroll
-        for (uint32_t w = 0; w < 15; ++w) {
-            const uint64_t src = 15 * j + w;
-            const uint32_t c = src < nwords32 ? __popc(A32[src]) : 0u;
-            if (w < wsplit) c0 += c; else c1 += c;
-        }
-        sec_counts[j] = c0 + c1;
-        const uint32_t local = (uint32_t)(b0 - (((uint64_t)blockIdx.x * SR_BITS) >> rshift));
-        if (c0) atomicAdd(&rc[local], c0);
-        if (c1) atomicAdd(&rc[local + 1], c1);
-    }
-    __syncthreads();
-    const uint64_t r0 = ((uint64_t)blockIdx.x * SR_BITS) >> rshift;
-    for (uint32_t i = threadIdx.x; i < nrb; i += SR_SECTORS)
-        if (r0 + i < nrank) rank_counts[r0 + i] = rc[i];
+// The u32 words [w0, w0 + 4) of A, words at or past nwords32 read as 0.
+__device__ __forceinline__ uint4 load_a4(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t w0) {
+    if (w0 + 4 <= nwords32) return *(const uint4*)(A32 + w0);
+    uint4 v;
+    v.x = w0 < nwords32 ? A32[w0] : 0u;
+    v.y = w0 + 1 < nwords32 ? A32[w0 + 1] : 0u;
+    v.z = w0 + 2 < nwords32 ? A32[w0 + 2] : 0u;
+    v.w = 0u;   // nwords32 is even, so w0 + 3 < nwords32 implies the whole vector is in range
+    return v;
 }
 
-// One thread per u32 word of the sector layout.
-__global__ void k_sector_write(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec,
-                               const uint64_t* __restrict__ pre, uint32_t* __restrict__ sec,
-                               uint64_t* __restrict__ super) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t total = nsec * SEC_WORDS;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        const uint64_t j = t / SEC_WORDS;
-        const uint32_t w = (uint32_t)(t % SEC_WORDS);
-        uint32_t v;
-        if (w == 0) {
-            const uint64_t sj = j & ~((1ull << SUPER_SHIFT) - 1);
-            v = (uint32_t)(pre[j] - pre[sj]);
-            if (j == sj) super[j >> SUPER_SHIFT] = pre[j];
+__global__ void __launch_bounds__(SR_SECTORS)
+k_sector_group_sums(const uint32_t* __restrict__ A32, uint64_t nwords32, uint32_t* __restrict__ group_sums) {
+    __shared__ uint32_t part[SR_SECTORS / 64];
+    const uint64_t w0 = (uint64_t)blockIdx.x * SR_WORDS;
+    uint32_t c = 0;
+    for (uint32_t i = threadIdx.x; i < SR_WORDS / 4; i += SR_SECTORS) {
+        const uint4 v = load_a4(A32, nwords32, w0 + 4ull * i);
+        c += __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+    }
+    c = wave_sum(c);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t i = 0; i < SR_SECTORS / 64; ++i) t += part[i];
+        group_sums[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(SR_SECTORS)
+k_sector_layout(const uint32_t* __restrict__ A32, uint64_t nwords32, uint64_t nsec, uint32_t rshift, uint64_t nrank,
+                const uint64_t* __restrict__ group_pre, uint32_t* __restrict__ sec, uint64_t* __restrict__ super,
+                uint64_t* __restrict__ rank) {
+    __shared__ uint4 w4[SR_WORDS / 4];
+    __shared__ uint32_t cnt[SR_SECTORS];
+    __shared__ uint32_t sh[SR_SECTORS / 64 + 1];
+    const uint32_t* w = (const uint32_t*)w4;
+    const uint64_t g = blockIdx.x;
+    const uint64_t w0 = g * SR_WORDS;
+    for (uint32_t i = threadIdx.x; i < SR_WORDS / 4; i += SR_SECTORS) w4[i] = load_a4(A32, nwords32, w0 + 4ull * i);
+    __syncthreads();
+    const uint64_t gp = group_pre[g];                                   // ones before this workgroup
+    const uint64_t sp = group_pre[(g >> SUPER_GROUPS_SHIFT) << SUPER_GROUPS_SHIFT];   // ... its superblock
+    // sector tid: words 15 tid .. 15 tid + 14 (stride 15: no bank conflicts)
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 15; ++k) c += __popc(w[15 * threadIdx.x + k]);
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_sum<SR_SECTORS>(c, sh, &tot);
+    cnt[threadIdx.x] = (uint32_t)(gp - sp) + ex;   // below 2^21 * 480
+    // rank block tid (2^rshift positions = 2^(rshift-5) words), words read in a rotated order
+    const uint32_t rw = 1u << (rshift - 5), nrb = (uint32_t)(SR_BITS >> rshift);
+    uint32_t rc = 0;
+    if (threadIdx.x < nrb)
+        for (uint32_t q = 0; q < rw; ++q) rc += __popc(w[threadIdx.x * rw + ((q + threadIdx.x) & (rw - 1))]);
+    const uint32_t rex = block_exclusive_sum<SR_SECTORS>(rc, sh, &tot);
+    const uint64_t r = g * nrb + threadIdx.x;
+    if (threadIdx.x < nrb && r < nrank) rank[r] = gp + rex;
+    if (threadIdx.x == 0 && (g & ((1ull << SUPER_GROUPS_SHIFT) - 1)) == 0) super[g >> SUPER_GROUPS_SHIFT] = gp;
+    // (block_exclusive_sum ends with a barrier, so cnt[] is complete)
+    // the workgroup's 256 sectors as 1024 16-byte pieces: piece u is words 4(u&3) .. 4(u&3)+3 of
+    // sector u>>2, word 0 of a sector being its counter and word k its A word k-1
+    uint4* out4 = (uint4*)(sec + g * SR_SECTORS * SEC_WORDS);
+    const uint64_t nsec_here = nsec - g * SR_SECTORS;
+    for (uint32_t u = threadIdx.x; u < SR_SECTORS * 4; u += SR_SECTORS) {
+        const uint32_t j = u >> 2, p = u & 3;
+        if (j >= nsec_here) break;
+        const uint32_t b = 15 * j + 4 * p;   // A word of this piece's second u32 (first when p > 0, minus 1)
+        uint4 v;
+        if (p == 0) {
+            v.x = cnt[j];
+            v.y = w[b];
+            v.z = w[b + 1];
+            v.w = w[b + 2];
         } else {
-            const uint64_t src = 15 * j + (w - 1);
-            v = src < nwords32 ? A32[src] : 0u;
+            v.x = w[b - 1];
+            v.y = w[b];
+            v.z = w[b + 1];
+            v.w = w[b + 2];
         }
-        sec[t] = v;
+        out4[u] = v;
     }
 }
 
@@ -425,6 +486,10 @@ uint64_t scan_tmp_tiles(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
                                  hipStream_t s) {
     if (!n) return hipSuccess;
+    if (n <= SCAN_SINGLE) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(NT), 0, s, in, out, n);
+        return hipGetLastError();
+    }
     const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(NT), 0, s, in, n, tmp_tiles);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(NT), 0, s, tmp_tiles, nt);
@@ -467,23 +532,24 @@ uint64_t sector_count(uint64_t total_bits) { return (total_bits + SEC_BITS - 1) 
 uint64_t super_count(uint64_t nsec) { return (nsec >> SUPER_SHIFT) + 1; }
 
 hipError_t launch_rank_sectors(const uint64_t* words, uint64_t total_bits, uint32_t rank_sample, uint64_t* rank,
-                               uint64_t nrank, uint32_t* sec, uint64_t* super, uint32_t* tmp_counts,
-                               uint32_t* tmp_rank_counts, uint64_t* tmp_pre, uint64_t* tmp_tiles, hipStream_t s) {
+                               uint64_t nrank, uint32_t* sec, uint64_t* super, uint32_t* tmp_group_sums,
+                               uint64_t* tmp_group_pre, uint64_t* tmp_tiles, hipStream_t s) {
     const uint64_t ns = sector_count(total_bits);
     if (!ns) return hipSuccess;
     if (rank_sample != 512 && rank_sample != 1024) return hipErrorInvalidValue;
     const uint64_t nw32 = total_bits / 32;
-    hipLaunchKernelGGL(k_sector_rank_counts, dim3((unsigned)((ns + SR_SECTORS - 1) / SR_SECTORS)), dim3(SR_SECTORS),
-                       0, s, (const uint32_t*)words, nw32, ns, rank_sample == 512 ? 9u : 10u, nrank, tmp_counts,
-                       tmp_rank_counts);
+    const uint64_t ng = rank_sector_groups(total_bits);
+    hipLaunchKernelGGL(k_sector_group_sums, dim3((unsigned)ng), dim3(SR_SECTORS), 0, s, (const uint32_t*)words, nw32,
+                       tmp_group_sums);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_exclusive_scan(tmp_rank_counts, rank, nrank, tmp_tiles, s)) != hipSuccess) return e;
-    if ((e = launch_exclusive_scan(tmp_counts, tmp_pre, ns, tmp_tiles, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sector_write, dim3(grid_for(ns * SEC_WORDS, NT * 4)), dim3(NT), 0, s,
-                       (const uint32_t*)words, nw32, ns, tmp_pre, sec, super);
+    if ((e = launch_exclusive_scan(tmp_group_sums, tmp_group_pre, ng, tmp_tiles, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sector_layout, dim3((unsigned)ng), dim3(SR_SECTORS), 0, s, (const uint32_t*)words, nw32, ns,
+                       rank_sample == 512 ? 9u : 10u, nrank, tmp_group_pre, sec, super, rank);
     return hipGetLastError();
 }
+
+uint64_t rank_sector_groups(uint64_t total_bits) { return (sector_count(total_bits) + SR_SECTORS - 1) / SR_SECTORS; }
 
 hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const DevLevel* lev,
                          uint32_t nlev, const uint32_t* sec, const uint64_t* super,
