@@ -4,6 +4,7 @@
 // streamed, k-mer and serving paths); the host only sizes levels, allocates, and reads one count
 // back per level.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -607,7 +608,7 @@ class Builder {
         if (cached_ && ws_->host) {
             host_ = ws_->host;
         } else {
-            HIP_TRY(hipHostMalloc((void**)&host_, 4096, hipHostMallocDefault), "hipHostMalloc");
+            HIP_TRY(hipHostMalloc((void**)&host_, 4096, hipHostMallocCoherent), "hipHostMalloc");
             if (cached_) ws_->host = host_;
         }
         HIP_TRY(hipHostGetDevicePointer((void**)&host_dev_, host_, 0), "hipHostGetDevicePointer");
@@ -773,6 +774,30 @@ class Builder {
         if ((st = ar_.alloc(&pre_keep_, pre_keep_bytes_, "lookup sectors and rank table")) != MPHF_OK) return st;
         if ((st = ar_.alloc(&pre_tmp_, pre_tmp_bytes_, "rank and sector temporaries")) != MPHF_OK) return st;
         return MPHF_OK;
+    }
+
+    // Report sequence numbers: distinct per report of this process, so that a value left in the
+    // (cached, reused) pinned buffer by an earlier build is never taken for a new one.
+    static uint64_t next_seq() {
+        static std::atomic<uint64_t> c{1};
+        return c.fetch_add(1);
+    }
+
+    // Waits until the report kernel has written `seq` (and so its values) into host_[2], polling the
+    // coherent pinned buffer; every 256 polls the stream is queried, so that a failed or finished
+    // stream ends the wait.
+    mphf_status wait_report(uint64_t seq) {
+        volatile uint64_t* const flag = host_ + 2;
+        for (uint32_t i = 1;; ++i) {
+            if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return MPHF_OK;
+            if ((i & 255) == 0) {
+                const hipError_t e = hipStreamQuery(s_);
+                if (e == hipErrorNotReady) continue;
+                if (e != hipSuccess) return hip_fail(e, "level report");
+                if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return MPHF_OK;
+                return fail(MPHF_E_DEVICE, "level report not written");
+            }
+        }
     }
 
     void record(uint32_t d, uint64_t n, uint64_t m, uint64_t weight, uint64_t off, uint32_t path) {
@@ -966,8 +991,9 @@ class Builder {
         if ((st = prefix(ws_->surv[yp], B, ws_->preY[yp])) != MPHF_OK) return st;
         // the overflow flag and the survivor total, written to pinned host memory by one small kernel
         // (which also clears the flag for the next level)
-        HIP_TRY(launch_report(ovf, ws_->preY[yp] + B, host_dev_, s_), "report");
-        HIP_TRY(hipStreamSynchronize(s_), "level sync");
+        const uint64_t seq = next_seq();
+        HIP_TRY(launch_report(ovf, ws_->preY[yp] + B, host_dev_, seq, s_), "report");
+        if ((st = wait_report(seq)) != MPHF_OK) return st;
         if (host_[0]) return MPHF_OK;   // overflow: redo with atomics
         const uint64_t nnext = host_[1];
         if (nnext > n) return fail(MPHF_E_DEVICE, "survivors exceed the level's keys");

@@ -268,7 +268,8 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
 hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
                             hipStream_t s);
 // out[0] = *flag, out[1] = *total (out: host memory mapped for the device), then *flag = 0.
-hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, hipStream_t s);
+hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, uint64_t seq,
+                         hipStream_t s);
 
 // Launch configuration of the batched build kernel: threads per workgroup (128, 256 or 512), keys
 // per thread in flight (4, 8 or 16) and workgroups per CU (1..8, further bounded by LDS).

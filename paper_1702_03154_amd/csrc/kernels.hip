@@ -403,13 +403,18 @@ __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* _
     }
 }
 
-// A level's overflow flag and survivor total written to host memory the device can write (one small
-// kernel rather than two copies), and the flag cleared for the next level.
-__global__ void k_report(unsigned long long* flag, const uint64_t* __restrict__ total, uint64_t* out) {
+// A level's overflow flag and survivor total written to coherent host memory the device can write
+// (one small kernel rather than two copies), then the sequence number `seq` after a system-scope
+// fence, so that the host may poll out[2] instead of waiting for the stream; the flag is cleared
+// for the next level.
+__global__ void k_report(unsigned long long* flag, const uint64_t* __restrict__ total, uint64_t* out,
+                         uint64_t seq) {
     if (threadIdx.x == 0) {
         out[0] = *flag;
         out[1] = *total;
         *flag = 0;
+        __threadfence_system();
+        __hip_atomic_store(out + 2, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -560,8 +565,9 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
     return hipGetLastError();
 }
 
-hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, flag, total, out);
+hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, uint64_t seq,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, flag, total, out, seq);
     return hipGetLastError();
 }
 
