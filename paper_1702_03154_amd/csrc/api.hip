@@ -649,25 +649,72 @@ class Builder {
         const uint32_t tk = tail_capacity(gamma);
         const BucketGeometry geo = geo_;
         bool fallback = atomic_only || geo.pbits == 0;
+        // Level d is queued (exactly, or ahead of its key count and then accepted) before the host
+        // waits for level d - 1's report, so that the device never waits for the host between levels.
+        SpecLevel* const spec = (SpecLevel*)(dev_ + 144);
+        QueuedLevel q;
+        bool have = false;   // q holds level d, queued
         while (!fallback && cur.n > 0 && d < D) {
-            if (cur.n <= tk) {
-                if ((st = tail(cur, d, off, tk)) != MPHF_OK) return st;
-                tr_.mark("tail", (long)h_->num_levels);
-                cur.n = 0;   // the tail built every remaining level and wrote the leftovers
-                d = h_->num_levels;
-                break;
+            if (!have) {
+                if (cur.n <= tk) {
+                    if ((st = tail(cur, d, off, tk)) != MPHF_OK) return st;
+                    tr_.mark("tail", (long)h_->num_levels);
+                    cur.n = 0;   // the tail built every remaining level and wrote the leftovers
+                    d = h_->num_levels;
+                    break;
+                }
+                bool queued = false;
+                if ((st = queue_level(cur, d, off, geo, SpecArgs(), 0, 0, &q, &queued)) != MPHF_OK) return st;
+                if (!queued) {
+                    fallback = true;
+                    break;
+                }
+            }
+            const uint64_t m_d = level_size(gamma, cur.n);
+            const uint64_t off_next = off + 64 * ((m_d + 63) / 64);
+            // level d + 1 queued ahead, when its key count is sure to stay above the tail's
+            QueuedLevel q2;
+            bool ahead = false;
+            uint64_t lo = 0, hi = 0;
+            if (ahead_ != AHEAD_OFF && d + 1 < D) {
+                survivor_bounds(cur.n, m_d, &lo, &hi);
+                if (ahead_ == AHEAD_REJECT) hi = lo;   // (a test mode: nearly every level queued ahead is redone)
+                if (lo > tk) {
+                    KeySet nin;
+                    nin.base = ws_->Y[q.yp];
+                    nin.stride = geo.kcap;
+                    nin.pre = ws_->preY[q.yp];
+                    nin.nseg = (uint32_t)((m_d + (1ull << geo.pbits) - 1) >> geo.pbits);
+                    nin.n = hi;
+                    SpecArgs sa;
+                    sa.mode = 1;
+                    sa.total = ws_->preY[q.yp] + q.B;
+                    sa.prev_flag = (const unsigned long long*)(dev_ + 140);
+                    sa.gamma = gamma;
+                    sa.seed = seeds_.s[d + 1];
+                    sa.bit_off = off_next;
+                    sa.lo = lo;
+                    sa.hi = hi;
+                    sa.out = spec;
+                    if ((st = queue_level(nin, d + 1, off_next, geo, sa, lo, hi, &q2, &ahead)) != MPHF_OK) return st;
+                }
             }
             KeySet next;
             bool ok = false;
-            if ((st = partitioned_level(cur, d, off, geo, &next, &ok)) != MPHF_OK) return st;
+            if ((st = finish_level(q, geo, &next, &ok)) != MPHF_OK) return st;
             tr_.mark("partitioned level", (long)d);
-            if (!ok) {
+            if (!ok) {   // (a level queued ahead saw the flag and did nothing)
                 fallback = true;
                 break;
             }
-            off += 64 * ((h_->level_m[d] + 63) / 64);
+            off = off_next;
             ++d;
             cur = next;
+            have = ahead && cur.n >= lo && cur.n <= hi;   // else it did nothing and is queued again
+            if (have) {
+                q = q2;
+                q.n = cur.n;
+            }
         }
         if (cur.n > 0) {
             // dense copy of what is left: either the input of the global-atomic levels, or the
@@ -742,12 +789,22 @@ class Builder {
     bool cached_ = false;
     const uint64_t* host_keys_ = nullptr;   // streaming build over a stored key set in host memory
     std::unique_lock<std::mutex> lock_;
-    int ypar_ = 0;
 
     // The structure's memory: A (reserve_words_ words, the expected size plus slack) and, sized for
     // that many bits, the lookup sectors, superblocks and rank table with their temporaries.  Its
     // host-side cost (large stream-ordered allocations) is paid once the first level's passes are
     // queued, so that it overlaps them.
+    // Levels queued ahead of their key count: on, off, or (a test mode) with bounds that nearly
+    // every level misses, so that the redo runs; from MPHF_LEVELS_AHEAD (unset or 1, 0, "reject").
+    enum { AHEAD_ON, AHEAD_OFF, AHEAD_REJECT };
+    int ahead_ = ahead_mode();
+    static int ahead_mode() {
+        const char* e = std::getenv("MPHF_LEVELS_AHEAD");
+        if (!e || !*e || std::strcmp(e, "1") == 0) return AHEAD_ON;
+        if (std::strcmp(e, "reject") == 0) return AHEAD_REJECT;
+        return AHEAD_OFF;
+    }
+
     bool defer_ = false, reserved_ = false;
     uint64_t reserve_words_ = 0;
     uint8_t *pre_keep_ = nullptr, *pre_tmp_ = nullptr;
@@ -783,11 +840,13 @@ class Builder {
         return c.fetch_add(1);
     }
 
-    // Waits until the report kernel has written `seq` (and so its values) into host_[2], polling the
-    // coherent pinned buffer; every 256 polls the stream is queried, so that a failed or finished
-    // stream ends the wait.
-    mphf_status wait_report(uint64_t seq) {
-        volatile uint64_t* const flag = host_ + 2;
+    // Waits until the report kernel has written `seq` (and so its values) into word 2 of its slot,
+    // polling the coherent pinned buffer; every 256 polls the stream is queried, so that a failed or
+    // finished stream ends the wait.  Report slots (four words each, two of them) sit past every
+    // other use of the buffer.
+    static constexpr uint32_t REPORT_WORDS = 280;
+    mphf_status wait_report(uint64_t seq, uint32_t slot) {
+        volatile uint64_t* const flag = host_ + REPORT_WORDS + 4 * slot + 2;
         for (uint32_t i = 1;; ++i) {
             if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == seq) return MPHF_OK;
             if ((i & 255) == 0) {
@@ -880,10 +939,10 @@ class Builder {
     }
 
     // Exclusive prefix of `n` u32 counts (the array has a trailing 0 at index n) into pre[0..n].
-    mphf_status prefix(const uint32_t* cnt, uint64_t n, uint64_t* pre) {
+    mphf_status prefix(const uint32_t* cnt, uint64_t n, uint64_t* pre, const uint64_t* skip = nullptr) {
         mphf_status st;
         if ((st = ensure(&ws_->tiles, &ws_->capTiles, scan_tmp_tiles(n + 1), "scan tiles")) != MPHF_OK) return st;
-        HIP_TRY(launch_exclusive_scan(cnt, pre, n + 1, ws_->tiles, s_), "prefix");
+        HIP_TRY(launch_exclusive_scan(cnt, pre, n + 1, ws_->tiles, s_, skip), "prefix");
         return MPHF_OK;
     }
 
@@ -892,10 +951,19 @@ class Builder {
     // regions (xcap records each, *S per bucket) with their counts in ws_->cntX; region overflows
     // and configuration errors are flagged in *ovf.  A record is the level hash h (one pass) or,
     // *packed, (q << pb) | (pos mod 2^pb) for h = q m + pos (two passes).
+    //
+    // For a level queued ahead of its key count (spec.mode != 0), in.n and m are the upper bounds the
+    // launches are sized for, m_lo the lower bound of m (region capacities take the larger density),
+    // and the kernels take the level hash from the device.
     mphf_status partition_buckets(const KeySet& in, const LevelHash& L, uint64_t m, uint32_t pb, uint64_t** X,
-                                  uint64_t* xcap, uint32_t* S, bool* packed, unsigned long long* ovf) {
+                                  uint64_t* xcap, uint32_t* S, bool* packed, unsigned long long* ovf,
+                                  const SpecArgs& spec = SpecArgs(), uint64_t m_lo = 0) {
         mphf_status st;
         const uint64_t n = in.n;
+        const uint64_t md = spec.mode ? m_lo : m;   // positions for the key density
+        const uint64_t* skip = spec.mode ? &spec.out->skip : nullptr;
+        SpecArgs later = spec;   // the second pass reads what the first derived
+        if (spec.mode) later.mode = 2;
         const uint64_t P = 1ull << pb;
         const uint64_t B = (m + P - 1) / P;
         const uint32_t lb = ceil_log2(B);
@@ -904,13 +972,13 @@ class Builder {
             // one pass: every workgroup scatters its share straight into the buckets
             uint64_t W = (n + 8191) / 8192;
             W = std::max<uint64_t>(1, std::min<uint64_t>(W, 256));
-            const uint64_t cap = region_cap((double)n / W * (double)P / (double)m);
+            const uint64_t cap = region_cap((double)n / W * (double)P / (double)md);
             if ((st = ensure(&ws_->X, &ws_->capX, B * W * cap + 16, "partition X")) != MPHF_OK) return st;
             *X = line_align(ws_->X);
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(B <= 256 ? 8 : 10, false, in.base, in.stride, in.pre, 1, in.nseg,
                                      (uint32_t)W, L, pb, 0, false, 0, B, *X, cap, (uint32_t)W,
-                                     ws_->cntX, ovf, n, in.nseg, s_),
+                                     ws_->cntX, ovf, n, in.nseg, s_, 0, nullptr, 0, spec),
                     "partition");
             *xcap = cap;
             *S = (uint32_t)W;
@@ -921,7 +989,7 @@ class Builder {
             const uint64_t C = (B + (1ull << fb) - 1) >> fb;
             uint64_t W = (n + 65535) / 65536;
             W = std::max<uint64_t>(1, std::min<uint64_t>(W, PART_WGS));
-            const double pc = (double)(P << fb) / (double)m;
+            const double pc = (double)(P << fb) / (double)md;
             const uint64_t cap1 = region_cap((double)n / W * pc);
             if ((st = ensure(&ws_->Z, &ws_->capZ, C * W * cap1 + 16, "partition Z")) != MPHF_OK) return st;
             uint64_t* const Z = line_align(ws_->Z);
@@ -930,11 +998,11 @@ class Builder {
             // 2^7 times the coarse bin, so q < 2^64 / m fits above it
             HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
                                      fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, n, in.nseg, s_,
-                                     3, nullptr, pb + fb),
+                                     3, nullptr, pb + fb, spec),
                     "partition 1");
             // (the pass writes the count after the last region as 0, for the scan's total)
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;
-            if ((st = prefix(ws_->cntZ, C * W, ws_->preZ)) != MPHF_OK) return st;
+            if ((st = prefix(ws_->cntZ, C * W, ws_->preZ, skip)) != MPHF_OK) return st;
             const uint64_t K = slots_per_group(C, n);
             const double bin_keys = (double)n * pc;
             const double e2 = bin_keys / (double)K / (double)(1ull << fb) * (1.0 + 8.0 / std::sqrt(bin_keys));
@@ -944,7 +1012,7 @@ class Builder {
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * K + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(fb <= 8 ? 8 : 10, true, Z, cap1, ws_->preZ, (uint32_t)C, (uint32_t)W,
                                      (uint32_t)K, L, pb, 0, true, fb, B, *X, cap2, (uint32_t)K,
-                                     ws_->cntX, ovf, n, C * W, s_, 4, nullptr, pb + fb),
+                                     ws_->cntX, ovf, n, C * W, s_, 4, nullptr, pb + fb, later),
                     "partition 2");
             *xcap = cap2;
             *S = (uint32_t)K;
@@ -953,17 +1021,31 @@ class Builder {
         return MPHF_OK;
     }
 
-    // One level by radix partition + per-bucket LDS pass.  *ok = false means a region or a
-    // bucket overflowed its capacity (only for adversarial key sets): nothing of the level is
-    // kept and the caller redoes it with global atomics.
-    mphf_status partitioned_level(const KeySet& in, uint32_t d, uint64_t off, const BucketGeometry& g,
-                                  KeySet* out, bool* ok) {
+    // A partitioned level on the stream: its geometry, where its survivors go and its report.
+    struct QueuedLevel {
+        uint32_t d = 0;
+        uint64_t off = 0;
+        uint64_t n = 0;      // the level's keys (for a level queued ahead: set once known)
+        uint64_t B = 0;      // buckets launched (for a level queued ahead: for its largest size)
+        uint32_t lb = 0;
+        int yp = 0;          // survivor buffers (by level parity)
+        uint64_t seq = 0;    // its report's sequence number
+        uint32_t slot = 0;   // its report's slot in the pinned buffer
+    };
+
+    // Queues level d by radix partition + per-bucket LDS pass over `in`.  Exact (sa.mode == 0):
+    // in.n keys.  Ahead of its key count: between lo and hi keys, the level hash derived on the
+    // device by the level's first pass from the survivor total before it (sa), the launches sized for
+    // hi keys.  *queued = false when the level would need more than 2^18 buckets (nothing queued).
+    mphf_status queue_level(const KeySet& in, uint32_t d, uint64_t off, const BucketGeometry& g,
+                            const SpecArgs& sa, uint64_t lo, uint64_t hi, QueuedLevel* q, bool* queued) {
+        const SpecLevel* spec = sa.mode ? sa.out : nullptr;
         mphf_status st;
-        *ok = false;
-        const uint64_t n = in.n;
-        const uint64_t m = level_size(gamma_, n);
+        *queued = false;
+        const uint64_t m = level_size(gamma_, spec ? hi : in.n);
+        const uint64_t m_lo = spec ? level_size(gamma_, lo) : m;
         const uint64_t wd = (m + 63) / 64;
-        const LevelHash L = make_level_hash(seeds_.s[d], m, off);
+        const LevelHash L = spec ? LevelHash{} : make_level_hash(seeds_.s[d], m, off);
         const uint32_t pb = g.pbits;
         const uint64_t P = 1ull << pb;
         const uint64_t B = (m + P - 1) / P;
@@ -974,38 +1056,71 @@ class Builder {
         uint32_t S;
         uint64_t* X = nullptr;   // regions of the buckets, on a 128-byte line
         bool packed = false;
-        if ((st = partition_buckets(in, L, m, pb, &X, &xcap, &S, &packed, ovf)) != MPHF_OK) return st;
+        KeySet sized = in;
+        if (spec) sized.n = hi;
+        if ((st = partition_buckets(sized, L, m, pb, &X, &xcap, &S, &packed, ovf, sa, m_lo)) != MPHF_OK) return st;
         if ((st = reserve()) != MPHF_OK) return st;
         if ((st = ensure_words(off / 64 + wd + 1)) != MPHF_OK) return st;
         // buckets: fill, finalize and filter in LDS
-        const int yp = ypar_;
-        ypar_ ^= 1;
+        const int yp = (int)(d & 1);
         if ((st = ensure(&ws_->Y[yp], &ws_->capY[yp], B * g.kcap, "survivors")) != MPHF_OK) return st;
         if ((st = ensure(&ws_->surv[yp], &ws_->capSurv[yp], B + 1, "survivor counts")) != MPHF_OK) return st;
         if ((st = ensure(&ws_->preY[yp], &ws_->capPreY[yp], B + 1, "survivor prefix")) != MPHF_OK) return st;
         uint64_t* C_level = coll_ ? coll_ + off / 64 : nullptr;
         HIP_TRY(launch_bucket(X, xcap, ws_->cntX, S, B, L, pb, packed, g.kcap, words_ + off / 64, C_level, wd,
-                              ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_),
+                              ws_->Y[yp], g.kcap, ws_->surv[yp], ovf, s_, spec),
                 "bucket");
         // (the bucket pass writes the count after the last bucket as 0, for the scan's total)
-        if ((st = prefix(ws_->surv[yp], B, ws_->preY[yp])) != MPHF_OK) return st;
+        if ((st = prefix(ws_->surv[yp], B, ws_->preY[yp], spec ? &spec->skip : nullptr)) != MPHF_OK) return st;
         // the overflow flag and the survivor total, written to pinned host memory by one small kernel
-        // (which also clears the flag for the next level)
-        const uint64_t seq = next_seq();
-        HIP_TRY(launch_report(ovf, ws_->preY[yp] + B, host_dev_, seq, s_), "report");
-        if ((st = wait_report(seq)) != MPHF_OK) return st;
-        if (host_[0]) return MPHF_OK;   // overflow: redo with atomics
-        const uint64_t nnext = host_[1];
-        if (nnext > n) return fail(MPHF_E_DEVICE, "survivors exceed the level's keys");
-        record(d, n, m, n - nnext, off,
-               B <= 1024 ? MPHF_PATH_ONE_PASS : lb - 8 > 8 ? MPHF_PATH_TWO_PASS_WIDE : MPHF_PATH_TWO_PASS);
-        out->base = ws_->Y[yp];
+        // (which also clears the flag for the next level and keeps it for a level queued behind)
+        q->d = d;
+        q->off = off;
+        q->n = spec ? 0 : in.n;
+        q->B = B;
+        q->lb = lb;
+        q->yp = yp;
+        q->seq = next_seq();
+        q->slot = d & 1;
+        HIP_TRY(launch_report(ovf, ws_->preY[yp] + B, host_dev_ + REPORT_WORDS + 4 * q->slot, q->seq,
+                              (unsigned long long*)(dev_ + 140), s_),
+                "report");
+        *queued = true;
+        return MPHF_OK;
+    }
+
+    // Waits for a queued level's report.  *ok = false means a region or a bucket overflowed its
+    // capacity (only for adversarial key sets): nothing of the level is kept and the caller redoes
+    // it with global atomics.  Else the level is recorded and *out describes its survivors.
+    mphf_status finish_level(const QueuedLevel& q, const BucketGeometry& g, KeySet* out, bool* ok) {
+        mphf_status st;
+        *ok = false;
+        if ((st = wait_report(q.seq, q.slot)) != MPHF_OK) return st;
+        const uint64_t* r = host_ + REPORT_WORDS + 4 * q.slot;
+        if (r[0]) return MPHF_OK;   // overflow: redo with atomics
+        const uint64_t nnext = r[1];
+        if (nnext > q.n) return fail(MPHF_E_DEVICE, "survivors exceed the level's keys");
+        const uint64_t m = level_size(gamma_, q.n);
+        record(q.d, q.n, m, q.n - nnext, q.off,
+               q.B <= 1024 ? MPHF_PATH_ONE_PASS : q.lb - 8 > 8 ? MPHF_PATH_TWO_PASS_WIDE : MPHF_PATH_TWO_PASS);
+        out->base = ws_->Y[q.yp];
         out->stride = g.kcap;
-        out->pre = ws_->preY[yp];
-        out->nseg = (uint32_t)B;
+        out->pre = ws_->preY[q.yp];
+        out->nseg = (uint32_t)((m + (1ull << g.pbits) - 1) >> g.pbits);   // buckets past m hold no survivors
         out->n = nnext;
         *ok = true;
         return MPHF_OK;
+    }
+
+    // Bounds on the survivors of a level of n keys in m positions for queueing the next level ahead:
+    // the expected number of keys sharing a position, n (1 - (1 - 1/m)^(n-1)), within 10 sqrt(n) + 64
+    // (the standard deviation is below sqrt(n) / 2).
+    static void survivor_bounds(uint64_t n, uint64_t m, uint64_t* lo, uint64_t* hi) {
+        const double e = (double)n * -std::expm1((double)(n - 1) * std::log1p(-1.0 / (double)m));
+        const double w = 10.0 * std::sqrt((double)n) + 64.0;
+        *lo = e - w > 1.0 ? (uint64_t)(e - w) : 1;
+        *hi = (uint64_t)std::ceil(e + w);
+        if (*hi > n) *hi = n;
     }
 
     // Every remaining level in one workgroup (the set fits in its LDS).

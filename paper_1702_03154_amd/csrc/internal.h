@@ -118,6 +118,28 @@ struct TailSummary {
     uint64_t bit_end;     // bit offset after the last level built
 };
 
+// A level queued before the host knows its key count: its first partition pass derives the level
+// hash from the previous level's survivor total on the device.  The host sized the launches for n
+// in [lo, hi]; if the total falls outside, or the previous level overflowed, skip is set and every
+// kernel of the level returns at once (the host then queues the level again with its exact size).
+struct SpecLevel {
+    LevelHash L;
+    uint64_t n;
+    uint64_t skip;
+};
+
+// How a partition pass of such a level gets it: mode 1 (the level's first pass) derives it from the
+// survivor total at `total`, every workgroup for itself and workgroup 0 also into *out, with n in
+// [lo, hi] and *prev_flag == 0 required; mode 2 (a later pass) reads *out; mode 0: an exact level.
+struct SpecArgs {
+    uint32_t mode = 0;
+    const uint64_t* total = nullptr;
+    const unsigned long long* prev_flag = nullptr;
+    double gamma = 0;
+    uint64_t seed = 0, bit_off = 0, lo = 0, hi = 0;
+    SpecLevel* out = nullptr;
+};
+
 // Batched builds: per set and per (set, level) records.
 struct BatchSet {
     uint64_t n;            // keys of the set
@@ -172,7 +194,8 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
                             uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig = 0,
-                            const uint64_t* dbase = nullptr, uint32_t pack_shift = 0);
+                            const uint64_t* dbase = nullptr, uint32_t pack_shift = 0,
+                            const SpecArgs& spec = SpecArgs());
 // Hash-set partition helpers: keys per (set, workgroup) over the slices of a partition pass, every
 // K-th entry of their prefix (the set offsets), and a two-word device write.
 hipError_t launch_slice_counts(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t groups,
@@ -197,7 +220,8 @@ hipError_t launch_accumulate(const uint64_t* in, uint64_t in_cap, const uint32_t
 hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
                          uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint32_t kcap,
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
-                         uint32_t* surv, unsigned long long* overflow, hipStream_t s);
+                         uint32_t* surv, unsigned long long* overflow, hipStream_t s,
+                         const SpecLevel* spec = nullptr);
 hipError_t launch_gather(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
                          uint64_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_tail(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t nseg,
@@ -217,8 +241,9 @@ hipError_t launch_filter_fill(const uint64_t* Fin, uint64_t n, const uint64_t* w
                               unsigned long long* count, uint64_t* W, const LevelHash& Lnext,
                               bool do_fill, hipStream_t s);
 uint64_t scan_tmp_tiles(uint64_t n);
+// (skip: a device word; nonzero when the kernels run makes them return at once)
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
-                                 hipStream_t s);
+                                 hipStream_t s, const uint64_t* skip = nullptr);
 // streaming build (stream.hip)
 // keys = NULL: key i of the range is output kstart + i of the generated stream; else keys[i] (a chunk of a
 // stored key set on the device).
@@ -267,9 +292,11 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s);
 hipError_t launch_positions(const uint64_t* keys, uint64_t n, const LevelHash& L, uint64_t* out,
                             hipStream_t s);
-// out[0] = *flag, out[1] = *total (out: host memory mapped for the device), then *flag = 0.
+// out[0] = *flag, out[1] = *total (out: host memory mapped for the device), *last = *flag, then
+// *flag = 0 and out[2] = seq.
 hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, uint64_t seq,
-                         hipStream_t s);
+                         unsigned long long* last, hipStream_t s);
+
 
 // Launch configuration of the batched build kernel: threads per workgroup (128, 256 or 512), keys
 // per thread in flight (4, 8 or 16) and workgroups per CU (1..8, further bounded by LDS).

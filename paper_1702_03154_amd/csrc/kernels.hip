@@ -134,7 +134,8 @@ constexpr int SCAN_ITEMS = 16;
 constexpr uint64_t SCAN_TILE = (uint64_t)NT * SCAN_ITEMS;
 
 __global__ void k_scan_tile_sums(const uint32_t* __restrict__ in, uint64_t n,
-                                 uint64_t* __restrict__ tile_sums) {
+                                 uint64_t* __restrict__ tile_sums, const uint64_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ uint64_t part[NT / 64];
     const uint64_t t = blockIdx.x;
     const uint64_t i0 = t * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
@@ -151,7 +152,8 @@ __global__ void k_scan_tile_sums(const uint32_t* __restrict__ in, uint64_t n,
     }
 }
 
-__global__ void k_scan_tiles(uint64_t* __restrict__ tile_sums, uint64_t ntiles) {
+__global__ void k_scan_tiles(uint64_t* __restrict__ tile_sums, uint64_t ntiles, const uint64_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ uint64_t sh[NT / 64 + 1];
     uint64_t carry = 0;
     for (uint64_t c0 = 0; c0 < ntiles; c0 += NT) {
@@ -165,7 +167,8 @@ __global__ void k_scan_tiles(uint64_t* __restrict__ tile_sums, uint64_t ntiles) 
 }
 
 __global__ void k_scan_apply(const uint32_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n,
-                             const uint64_t* __restrict__ tile_off) {
+                             const uint64_t* __restrict__ tile_off, const uint64_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ uint64_t sh[NT / 64 + 1];
     const uint64_t t = blockIdx.x;
     const uint64_t i0 = t * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
@@ -187,7 +190,9 @@ __global__ void k_scan_apply(const uint32_t* __restrict__ in, uint64_t* __restri
 // launch instead of three; the per-level counts of the small levels).
 constexpr uint64_t SCAN_SINGLE = 4 * SCAN_TILE;
 
-__global__ void k_scan_single(const uint32_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n) {
+__global__ void k_scan_single(const uint32_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t n,
+                              const uint64_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ uint64_t sh[NT / 64 + 1];
     uint64_t carry = 0;
     for (uint64_t t0 = 0; t0 < n; t0 += SCAN_TILE) {
@@ -408,10 +413,12 @@ __global__ void k_lookup(const uint64_t* __restrict__ q, uint64_t n, uint64_t* _
 // fence, so that the host may poll out[2] instead of waiting for the stream; the flag is cleared
 // for the next level.
 __global__ void k_report(unsigned long long* flag, const uint64_t* __restrict__ total, uint64_t* out,
-                         uint64_t seq) {
+                         uint64_t seq, unsigned long long* last) {
     if (threadIdx.x == 0) {
-        out[0] = *flag;
+        const unsigned long long f = *flag;
+        out[0] = f;
         out[1] = *total;
+        *last = f;   // for a level queued behind this one
         *flag = 0;
         __threadfence_system();
         __hip_atomic_store(out + 2, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -489,16 +496,16 @@ hipError_t launch_filter_fill(const uint64_t* Fin, uint64_t n, const uint64_t* w
 uint64_t scan_tmp_tiles(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
 hipError_t launch_exclusive_scan(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp_tiles,
-                                 hipStream_t s) {
+                                 hipStream_t s, const uint64_t* skip) {
     if (!n) return hipSuccess;
     if (n <= SCAN_SINGLE) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(NT), 0, s, in, out, n);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(NT), 0, s, in, out, n, skip);
         return hipGetLastError();
     }
     const uint64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(NT), 0, s, in, n, tmp_tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(NT), 0, s, tmp_tiles, nt);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(NT), 0, s, in, out, n, tmp_tiles);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nt), dim3(NT), 0, s, in, n, tmp_tiles, skip);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(NT), 0, s, tmp_tiles, nt, skip);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(NT), 0, s, in, out, n, tmp_tiles, skip);
     return hipGetLastError();
 }
 
@@ -566,8 +573,8 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
 }
 
 hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64_t* out, uint64_t seq,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, flag, total, out, seq);
+                         unsigned long long* last, hipStream_t s) {
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(64), 0, s, flag, total, out, seq, last);
     return hipGetLastError();
 }
 

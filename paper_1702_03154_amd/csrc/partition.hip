@@ -298,7 +298,25 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
             uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift, uint32_t pack_shift,
             uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
             uint64_t out_cap, uint32_t S_out, uint32_t* __restrict__ out_cnt,
-            unsigned long long* overflow, const uint64_t* __restrict__ dbase) {
+            unsigned long long* overflow, const uint64_t* __restrict__ dbase, SpecArgs spec) {
+    if (spec.mode) {   // a level queued ahead: its hash from the device, or nothing to do
+        __shared__ SpecLevel sl;
+        if (threadIdx.x == 0) {
+            if (spec.mode == 1) {   // m = ceil(gamma n) in IEEE double, as the host computes it
+                const uint64_t n = *spec.total;
+                const bool skip = *spec.prev_flag != 0 || n < spec.lo || n > spec.hi;
+                sl.L = device_level_hash(spec.seed, skip ? 1 : (uint64_t)ceil(spec.gamma * (double)n), spec.bit_off);
+                sl.n = n;
+                sl.skip = skip ? 1 : 0;
+                if (blockIdx.x == 0) *spec.out = sl;
+            } else {
+                sl = *spec.out;
+            }
+        }
+        __syncthreads();
+        if (sl.skip) return;
+        L = sl.L;
+    }
     constexpr int NB = 1 << DBITS;
     constexpr bool WC = DBITS == 8;
     constexpr bool DENSE = DIG == 2;
@@ -512,12 +530,24 @@ __global__ void __launch_bounds__(KT)
 k_bucket(const uint64_t* __restrict__ in, uint64_t in_cap, const uint32_t* __restrict__ cnt,
          uint32_t S, LevelHash L, uint32_t pbits, uint32_t kcap, uint64_t* __restrict__ A,
          uint64_t* __restrict__ Cout, uint64_t level_words, uint64_t* __restrict__ Y, uint64_t ycap,
-         uint32_t* __restrict__ surv, unsigned long long* overflow) {
+         uint32_t* __restrict__ surv, unsigned long long* overflow, const SpecLevel* __restrict__ spec) {
     __shared__ uint32_t pool[BUCKET_LDS / 4];
     __shared__ uint32_t wsum[KT / 64 + 1];
     __shared__ uint32_t segoff[257];
     const uint64_t b = blockIdx.x;
     const uint32_t P = 1u << pbits;
+    if (spec) {   // a level queued ahead: its hash and size from the device; buckets past it are empty
+        if (spec->skip) return;
+        L = spec->L;
+        level_words = (L.m + 63) / 64;
+        if (b >= (L.m + P - 1) >> pbits) {
+            if (threadIdx.x == 0) {
+                surv[b] = 0;
+                if (b == 0) surv[gridDim.x] = 0;
+            }
+            return;
+        }
+    }
     uint32_t* Abits = pool;
     uint32_t* Cbits = pool + (P >> 5);
     uint16_t* lps = (uint16_t*)(pool + 2 * (P >> 5));
@@ -931,7 +961,7 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
                             uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig, const uint64_t* dbase,
-                            uint32_t pack_shift) {
+                            uint32_t pack_shift, const SpecArgs& spec) {
     const dim3 grid(groups * K);
     const uint32_t gr = grouped ? 1u : 0u;
     // segments averaging under half a tile: tiles span segments
@@ -939,7 +969,7 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
 #define MPHF_PART(DB, HS, SP, DG)                                                                     \
     hipLaunchKernelGGL((k_partition<DB, HS, SP, DG>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
                        pbits, out_shift, pack_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt,  \
-                       overflow, dbase)
+                       overflow, dbase, spec)
     if (dig == 1) {
         // regions by the top bits: the first pass over a dense key array
         if (hashed || dbits > 8 || span) return hipErrorInvalidValue;
@@ -976,17 +1006,17 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
 hipError_t launch_bucket(const uint64_t* in, uint64_t in_cap, const uint32_t* cnt, uint32_t S,
                          uint64_t nbuckets, const LevelHash& L, uint32_t pbits, bool packed, uint32_t kcap,
                          uint64_t* A, uint64_t* Cout, uint64_t level_words, uint64_t* Y, uint64_t ycap,
-                         uint32_t* surv, unsigned long long* overflow, hipStream_t s) {
+                         uint32_t* surv, unsigned long long* overflow, hipStream_t s, const SpecLevel* spec) {
     // local positions are 16-bit, and the A and C bits and the positions must fit the LDS pool
     if (pbits < 6 || pbits > 16 || kcap > (uint32_t)(KT * BI) ||
         (1u << pbits) / 4 + 2ull * kcap > (uint64_t)BUCKET_LDS)
         return hipErrorInvalidValue;
     if (packed)
         hipLaunchKernelGGL(k_bucket<true>, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
-                           pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+                           pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow, spec);
     else
         hipLaunchKernelGGL(k_bucket<false>, dim3((unsigned)nbuckets), dim3(KT), 0, s, in, in_cap, cnt, S, L,
-                           pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow);
+                           pbits, kcap, A, Cout, level_words, Y, ycap, surv, overflow, spec);
     return hipGetLastError();
 }
 

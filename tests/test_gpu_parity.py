@@ -344,3 +344,22 @@ def test_level1_bucket_overflow_falls_back_with_hashed_survivors(M):
     def want(p):
         assert p[0] == "one_pass" and set(p[1:]) == {"atomic"}, p
     check_against_oracle(M, k, gamma, bucket_bits=bits, paths=want, queries_np=keys_np(5000, seed=58))
+
+
+@pytest.mark.parametrize("mode", ["1", "0", "reject"])
+@pytest.mark.parametrize("n,gamma", [(200_000, 2.0), (200_000, 1.0), (3_000_000, 2.0), (20_000_000, 2.0)])
+def test_levels_queued_ahead(M, monkeypatch, mode, n, gamma):
+    """A partitioned level is queued before the host knows its key count, sized for bounds on the
+    survivors of the level before it, with its level hash derived on the device; a level whose count
+    falls outside the bounds does nothing and is queued again exactly.  On (the default), off, and a
+    mode whose bounds nearly every level misses (so the redo runs at every level after the first)
+    must all give the oracle's structure and labels, on one-pass and two-pass levels."""
+    monkeypatch.setenv("MPHF_LEVELS_AHEAD", mode)
+    check_against_oracle(M, keys_np(n, seed=n + 3), gamma, queries_np=keys_np(3000, seed=99))
+
+
+def test_levels_queued_ahead_after_a_level0_overflow(M, monkeypatch):
+    """Adversarial keys overflow a level-0 bucket: the level queued ahead sees the overflow flag and
+    does nothing, and the atomic redo from level 0 must equal the oracle."""
+    monkeypatch.setenv("MPHF_LEVELS_AHEAD", "1")
+    test_bucket_overflow_falls_back_to_atomic_levels(M)
