@@ -845,6 +845,8 @@ class Builder {
     // finished stream ends the wait.  Report slots (four words each, two of them) sit past every
     // other use of the buffer.
     static constexpr uint32_t REPORT_WORDS = 280;
+    static_assert(REPORT_WORDS * 8 >= 8 * 8 + sizeof(TailLevel) * MPHF_MAX_LEVELS && (REPORT_WORDS + 8) * 8 <= 4096,
+                  "report slots after the tail's records, inside the pinned buffer");
     mphf_status wait_report(uint64_t seq, uint32_t slot) {
         volatile uint64_t* const flag = host_ + REPORT_WORDS + 4 * slot + 2;
         for (uint32_t i = 1;; ++i) {

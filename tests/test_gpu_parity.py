@@ -363,3 +363,38 @@ def test_levels_queued_ahead_after_a_level0_overflow(M, monkeypatch):
     does nothing, and the atomic redo from level 0 must equal the oracle."""
     monkeypatch.setenv("MPHF_LEVELS_AHEAD", "1")
     test_bucket_overflow_falls_back_to_atomic_levels(M)
+
+
+def test_concurrent_builds_on_threads_and_streams(M):
+    """Four host threads build at once, each on its own stream: one takes the device's cached
+    workspace, the others private temporaries, each polls its own reports and queues its levels
+    ahead.  Every function must equal the oracle's (bits, rank table, labels)."""
+    import threading
+
+    sets = [keys_np(300_000 + 20_000 * i, seed=70 + i) for i in range(4)]
+    tens = [torch.from_numpy(k.view(np.int64)).cuda() for k in sets]
+    streams = [torch.cuda.Stream() for _ in sets]
+    torch.cuda.synchronize()
+    built, errors = [None] * len(sets), []
+
+    def run(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                built[i] = M.build(tens[i], 2.0, seed=i, stream=streams[i])
+        except Exception as e:   # reported below
+            errors.append(e)
+
+    ts = [threading.Thread(target=run, args=(i,)) for i in range(len(sets))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for i, k in enumerate(sets):
+        st = O.build(k, 2.0, i)
+        ex = built[i].export()
+        assert np.array_equal(ex["words"], st.words), i
+        assert np.array_equal(ex["rank"], st.rank), i
+        assert built[i].stats()["level_n"] == [l.n for l in st.levels], i
+        assert np.array_equal(host(built[i].lookup(tens[i])), O.lookup(st, k)), i
