@@ -76,10 +76,10 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // SPAN = true (inputs of small segments) a tile is a dense range across up to TSEG segments, each
 // key found in the segment boundaries staged in LDS.
 //
-// DIG = 3 (first of two passes) writes, instead of h, the packed record (q << pack_shift) |
-// (pos mod 2^pack_shift) where h = q m + pos: with pack_shift = the coarse bin's bits the record
-// keeps everything the later passes need (q < 2^64 / m fits above them, the bin is the region) and
-// spares them the division.  DIG = 4 (second pass) reads such records and writes
+// DIG = 3 or 5 (first of two passes; 5 when m < 2^32) writes, instead of h, the packed record
+// (q << pack_shift) | (pos mod 2^pack_shift) where h = q m + pos: with pack_shift = the coarse
+// bin's bits the record keeps everything the later passes need (q < 2^64 / m fits above them, the
+// bin is the region) and spares them the division.  DIG = 4 (second pass) reads such records and writes
 // (q << pbits) | (pos mod 2^pbits) for the bucket pass, which forms h = q m + pos again and
 // recovers the surviving keys from it.
 //
@@ -134,11 +134,13 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
             const uint64_t local = k[it] & ((1ull << pack_shift) - 1);
             bin = bin_base + (local >> pbits);
             k[it] = ((k[it] >> pack_shift) << pbits) | (local & ((1ull << pbits) - 1));
-        } else if constexpr (DIG == 3) {
-            // level position of h = q * m + pos, written as (q << pack_shift) | (pos mod 2^pack_shift)
+        } else if constexpr (DIG == 3 || DIG == 5) {
+            // level position of h = q * m + pos, written as (q << pack_shift) | (pos mod 2^pack_shift);
+            // DIG = 5 (m < 2^32): pos < 2^32, so the low 32 bits of h - q m are all of it
             const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
-            uint64_t q;
-            const uint64_t pos = divmod_invariant(h, L.m, L.magic, L.sh1, L.sh2, &q);
+            const uint64_t t = __umul64hi(L.magic, h);
+            const uint64_t q = (t + ((h - t) >> L.sh1)) >> L.sh2;
+            const uint64_t pos = DIG == 5 ? (uint64_t)((uint32_t)h - (uint32_t)q * (uint32_t)L.m) : h - q * L.m;
             bin = (pos >> pbits) >> out_shift;
             k[it] = (q << pack_shift) | (pos & ((1ull << pack_shift) - 1));
         } else {
@@ -987,7 +989,12 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
     } else if (dig == 3) {
         // packed records: the first of two passes over keys
         if (hashed || dbits > 8 || pack_shift > 56) return hipErrorInvalidValue;
-        if (span) MPHF_PART(8, false, true, 3); else MPHF_PART(8, false, false, 3);
+        const uint64_t m_max = spec.mode ? (uint64_t)std::ceil(spec.gamma * (double)spec.hi) : L.m;
+        if ((m_max >> 32) == 0) {   // pos < m < 2^32: its low 32 bits suffice
+            if (span) MPHF_PART(8, false, true, 5); else MPHF_PART(8, false, false, 5);
+        } else {
+            if (span) MPHF_PART(8, false, true, 3); else MPHF_PART(8, false, false, 3);
+        }
     } else if (dig == 4) {
         // packed records in and out: the second pass
         if (!hashed || pack_shift > 56 || pack_shift < pbits) return hipErrorInvalidValue;
