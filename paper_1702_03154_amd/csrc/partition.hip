@@ -127,20 +127,30 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
     for (int it = 0; it < PITEMS; ++it) {
         const uint32_t j = it * PT + threadIdx.x;
         uint64_t bin;
-        if constexpr (DIG == 4) {
+        bool in_range;   // the bin is one this workgroup may write
+        if constexpr (DIG == 5) {
+            // m < 2^32 (first of two passes, never grouped): pos < 2^32, so the low 32 bits of
+            // h - q m are all of it, and the bin is a 32-bit shift of it
+            const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
+            const uint64_t t = __umul64hi(L.magic, h);
+            const uint64_t q = (t + ((h - t) >> L.sh1)) >> L.sh2;
+            const uint32_t pos = (uint32_t)h - (uint32_t)q * (uint32_t)L.m;
+            const uint32_t b32 = pos >> (pbits + out_shift);
+            bin = b32;
+            in_range = b32 < (uint32_t)lim;
+            k[it] = (q << pack_shift) | (pos & ((1ull << pack_shift) - 1));
+        } else if constexpr (DIG == 4) {
             // packed input (q << pack_shift) | (position inside the group's coarse bin): the
             // bucket is known without a division; the output keeps q and the position inside the
             // bucket
             const uint64_t local = k[it] & ((1ull << pack_shift) - 1);
             bin = bin_base + (local >> pbits);
             k[it] = ((k[it] >> pack_shift) << pbits) | (local & ((1ull << pbits) - 1));
-        } else if constexpr (DIG == 3 || DIG == 5) {
-            // level position of h = q * m + pos, written as (q << pack_shift) | (pos mod 2^pack_shift);
-            // DIG = 5 (m < 2^32): pos < 2^32, so the low 32 bits of h - q m are all of it
+        } else if constexpr (DIG == 3) {
+            // level position of h = q * m + pos, written as (q << pack_shift) | (pos mod 2^pack_shift)
             const uint64_t h = HASHED ? k[it] : fmix64(k[it] ^ L.seed);
-            const uint64_t t = __umul64hi(L.magic, h);
-            const uint64_t q = (t + ((h - t) >> L.sh1)) >> L.sh2;
-            const uint64_t pos = DIG == 5 ? (uint64_t)((uint32_t)h - (uint32_t)q * (uint32_t)L.m) : h - q * L.m;
+            uint64_t q;
+            const uint64_t pos = divmod_invariant(h, L.m, L.magic, L.sh1, L.sh2, &q);
             bin = (pos >> pbits) >> out_shift;
             k[it] = (q << pack_shift) | (pos & ((1ull << pack_shift) - 1));
         } else {
@@ -154,8 +164,9 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
             }
         }
         // bin - bin_base wraps above lim (<= 2^DBITS) for a bin below the group's first
-        const uint64_t rel = bin - bin_base;
-        const bool ok = j < tn && rel < lim;
+        const uint64_t rel = DIG == 5 ? bin : bin - bin_base;
+        if constexpr (DIG != 5) in_range = rel < lim;
+        const bool ok = j < tn && in_range;
         bad |= j < tn && !ok;
         dg[it] = ok ? (uint32_t)rel : (uint32_t)NB;
         rk[it] = 0;
@@ -990,6 +1001,7 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
         // packed records: the first of two passes over keys
         if (hashed || dbits > 8 || pack_shift > 56) return hipErrorInvalidValue;
         const uint64_t m_max = spec.mode ? (uint64_t)std::ceil(spec.gamma * (double)spec.hi) : L.m;
+        if (grouped) return hipErrorInvalidValue;
         if ((m_max >> 32) == 0) {   // pos < m < 2^32: its low 32 bits suffice
             if (span) MPHF_PART(8, false, true, 5); else MPHF_PART(8, false, false, 5);
         } else {
