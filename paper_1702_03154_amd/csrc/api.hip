@@ -313,6 +313,7 @@ struct KeySet {
     const uint64_t* pre = nullptr;
     uint32_t nseg = 0;
     uint64_t n = 0;
+    uint64_t gen[2] = {0, 0};   // with base == nullptr: one segment of generated keys (seed, first index)
 };
 
 // Capacity of a region expected to receive e keys: 8 standard deviations and a margin above e,
@@ -444,7 +445,7 @@ class Builder {
         if ((st = ar_.alloc(&dense, nd, "streamed survivors")) != MPHF_OK) return st;
         tr_.mark("collect alloc", (long)nd);
         bool collected = false;
-        if (chunk && walkable && !(o_.flags & MPHF_FLAG_ATOMIC_LEVELS)) {
+        if (pre0 && walkable && !(o_.flags & MPHF_FLAG_ATOMIC_LEVELS)) {   // (pre0: the chunked scans ran)
             // chunk by chunk, the levels walked by bucket
             unsigned long long* ovf = (unsigned long long*)(dev_ + 129);
             HIP_TRY(launch_zero(dev_ + 129, 1, s_), "zero overflow");
@@ -459,6 +460,7 @@ class Builder {
                     fits = false;
                     break;
                 }
+                if (in.n && !in.base) return fail(MPHF_E_DEVICE, "collect before any streamed level");
                 if (in.n) HIP_TRY(launch_gather(in.base, in.stride, in.pre, in.nseg, in.n, dense + got, s_), "gather");
                 got += in.n;
             }
@@ -513,17 +515,23 @@ class Builder {
     }
 
     // The keys of stream chunk [c0, c0 + c) that no finished level 0..d-1 placed (the walk of
-    // Algorithm 3 over those levels), found by bucket: the chunk is generated into `chunk`, and for
+    // Algorithm 3 over those levels), found by bucket: the chunk is copied into `chunk` (a stored key
+    // set) or generated by the first radix pass (a generated stream), and for
     // each finished level j its keys are partitioned by bucket of level j and tested against A_j
     // in LDS (k_bucket_test).  *out gets them as the regions of ws_->Y[0] with prefix ws_->preY[0].
     // Region overflows (adversarial streams only) are flagged in *ovf.
     mphf_status stream_unplaced(uint64_t kseed, uint64_t kstart, uint64_t c0, uint64_t c, uint32_t d,
                                 uint64_t* chunk, uint64_t* pre0, KeySet* out, unsigned long long* ovf) {
         mphf_status st;
-        if ((st = load_chunk(kseed, kstart, c0, c, chunk)) != MPHF_OK) return st;
-        HIP_TRY(launch_pair(pre0, 0, c, s_), "chunk prefix");
         KeySet cur;
-        cur.base = chunk;
+        if (host_keys_) {
+            if ((st = load_chunk(kseed, kstart, c0, c, chunk)) != MPHF_OK) return st;
+            cur.base = chunk;
+        } else {   // generated keys: the first radix pass makes them itself
+            cur.gen[0] = kseed;
+            cur.gen[1] = kstart + c0;
+        }
+        HIP_TRY(launch_pair(pre0, 0, c, s_), "chunk prefix");
         cur.pre = pre0;
         cur.nseg = 1;
         cur.n = c;
@@ -569,7 +577,8 @@ class Builder {
         mphf_status st;
         *done = false;
         const uint64_t ch = chunk_keys(n, budget);
-        if (!*chunk && (st = ar_.alloc(chunk, ch, "stream chunk")) != MPHF_OK) return st;
+        // (a generated chunk is never stored: its first radix pass makes the keys)
+        if (host_keys_ && !*chunk && (st = ar_.alloc(chunk, ch, "stream chunk")) != MPHF_OK) return st;
         if (!*pre0 && (st = ar_.alloc(pre0, 2, "chunk prefix")) != MPHF_OK) return st;
         HIP_TRY(accumulate_setup(), "accumulate setup");
         HIP_TRY(bucket_test_setup(), "bucket test setup");
@@ -980,7 +989,7 @@ class Builder {
             if ((st = ensure(&ws_->cntX, &ws_->capCntX, B * W + 1, "counts X")) != MPHF_OK) return st;
             HIP_TRY(launch_partition(B <= 256 ? 8 : 10, false, in.base, in.stride, in.pre, 1, in.nseg,
                                      (uint32_t)W, L, pb, 0, false, 0, B, *X, cap, (uint32_t)W,
-                                     ws_->cntX, ovf, n, in.nseg, s_, 0, nullptr, 0, spec),
+                                     ws_->cntX, ovf, n, in.nseg, s_, 0, nullptr, 0, spec, in.base ? nullptr : in.gen),
                     "partition");
             *xcap = cap;
             *S = (uint32_t)W;
@@ -1000,7 +1009,7 @@ class Builder {
             // 2^7 times the coarse bin, so q < 2^64 / m fits above it
             HIP_TRY(launch_partition(8, false, in.base, in.stride, in.pre, 1, in.nseg, (uint32_t)W, L, pb,
                                      fb, false, 0, C, Z, cap1, (uint32_t)W, ws_->cntZ, ovf, n, in.nseg, s_,
-                                     3, nullptr, pb + fb, spec),
+                                     3, nullptr, pb + fb, spec, in.base ? nullptr : in.gen),
                     "partition 1");
             // (the pass writes the count after the last region as 0, for the scan's total)
             if ((st = ensure(&ws_->preZ, &ws_->capPreZ, C * W + 1, "prefix Z")) != MPHF_OK) return st;

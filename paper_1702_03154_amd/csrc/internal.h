@@ -104,6 +104,15 @@ __device__ __forceinline__ void walk_levels(const uint64_t (&x)[QP], bool (&pend
     }
 }
 
+// Key i of a generated stream: output i of SplitMix64 (Steele, Lea and Flood 2014) started at
+// `seed`; the streaming build generates its chunks (and a first radix pass its keys) from it.
+__device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 struct SeedTable {
     uint64_t s[64];
 };
@@ -195,7 +204,7 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
                             uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig = 0,
                             const uint64_t* dbase = nullptr, uint32_t pack_shift = 0,
-                            const SpecArgs& spec = SpecArgs());
+                            const SpecArgs& spec = SpecArgs(), const uint64_t* gen = nullptr);
 // Hash-set partition helpers: keys per (set, workgroup) over the slices of a partition pass, every
 // K-th entry of their prefix (the set offsets), and a two-word device write.
 hipError_t launch_slice_counts(const uint64_t* in, uint64_t in_stride, const uint64_t* pre, uint32_t groups,

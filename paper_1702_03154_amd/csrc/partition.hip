@@ -92,6 +92,13 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 
 constexpr int LW = 16;   // keys per 128-byte line
 
+// Keys generated instead of read (a first pass over a chunk of a generated stream): the key of
+// dense index i is stream_key(seed, start + i).
+struct GenKeys {
+    uint64_t seed, start;
+    uint32_t on;
+};
+
 template <int NB, bool WC, bool DENSE>
 struct PartLds {
     static constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
@@ -305,13 +312,13 @@ __device__ __forceinline__ void load_tile(uint64_t (&k)[PITEMS], const uint64_t*
 }
 
 // (6 waves per SIMD: two workgroups of 12 waves per compute unit, as the LDS allows, at 80 VGPRs)
-template <int DBITS, bool HASHED, bool SPAN, int DIG>
+template <int DBITS, bool HASHED, bool SPAN, int DIG, bool GEN = false>
 __global__ void __launch_bounds__(PT, 6)
 k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __restrict__ pre,
             uint32_t SG, uint32_t K, LevelHash L, uint32_t pbits, uint32_t out_shift, uint32_t pack_shift,
             uint32_t grouped, uint32_t group_shift, uint64_t nbins, uint64_t* __restrict__ out,
             uint64_t out_cap, uint32_t S_out, uint32_t* __restrict__ out_cnt,
-            unsigned long long* overflow, const uint64_t* __restrict__ dbase, SpecArgs spec) {
+            unsigned long long* overflow, const uint64_t* __restrict__ dbase, SpecArgs spec, GenKeys gk) {
     if (spec.mode) {   // a level queued ahead: its hash from the device, or nothing to do
         __shared__ SpecLevel sl;
         if (threadIdx.x == 0) {
@@ -390,9 +397,17 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
         };
         // the tile [t, e) from segment s and, past se, segment s + 1
         auto load = [&](uint64_t (&k)[PITEMS], uint64_t t, uint64_t e) {
-            const uint64_t n1 = (se < e ? se : e) - t;
-            load_tile(k, in + (uint64_t)s * in_stride + (t - sb), (uint32_t)n1, in + (uint64_t)(s + 1) * in_stride,
-                      (uint32_t)(e - t));
+            if constexpr (GEN) {   // one segment of generated keys: dense index = stream index
+#pragma unroll
+                for (int it = 0; it < PITEMS; ++it) {
+                    const uint64_t j = it * PT + threadIdx.x;
+                    k[it] = stream_key(gk.seed, gk.start + t + (t + j < e ? j : e - 1 - t));
+                }
+            } else {
+                const uint64_t n1 = (se < e ? se : e) - t;
+                load_tile(k, in + (uint64_t)s * in_stride + (t - sb), (uint32_t)n1,
+                          in + (uint64_t)(s + 1) * in_stride, (uint32_t)(e - t));
+            }
         };
         uint64_t kn[PITEMS];
         uint64_t t0 = lo, te = lo;
@@ -974,15 +989,21 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
                             uint32_t group_shift, uint64_t nbins, uint64_t* out, uint64_t out_cap,
                             uint32_t S_out, uint32_t* out_cnt, unsigned long long* overflow,
                             uint64_t n_in, uint64_t nseg_in, hipStream_t s, int dig, const uint64_t* dbase,
-                            uint32_t pack_shift, const SpecArgs& spec) {
+                            uint32_t pack_shift, const SpecArgs& spec, const uint64_t* gen) {
     const dim3 grid(groups * K);
+    GenKeys gk{0, 0, 0};
+    if (gen) {   // generated keys: one segment, never records
+        if (hashed || nseg_in != 1 || (dig != 0 && dig != 3)) return hipErrorInvalidValue;
+        gk = GenKeys{gen[0], gen[1], 1};
+    }
     const uint32_t gr = grouped ? 1u : 0u;
     // segments averaging under half a tile: tiles span segments
-    const bool span = nseg_in > 0 && n_in / nseg_in < (uint64_t)(PTILE / 2);
-#define MPHF_PART(DB, HS, SP, DG)                                                                     \
-    hipLaunchKernelGGL((k_partition<DB, HS, SP, DG>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
-                       pbits, out_shift, pack_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt,  \
-                       overflow, dbase, spec)
+    const bool span = !gen && nseg_in > 0 && n_in / nseg_in < (uint64_t)(PTILE / 2);
+#define MPHF_PART_G(DB, HS, SP, DG, GN)                                                                   \
+    hipLaunchKernelGGL((k_partition<DB, HS, SP, DG, GN>), grid, dim3(PT), 0, s, in, in_stride, pre, SG, K, L, \
+                       pbits, out_shift, pack_shift, gr, group_shift, nbins, out, out_cap, S_out, out_cnt,      \
+                       overflow, dbase, spec, gk)
+#define MPHF_PART(DB, HS, SP, DG) MPHF_PART_G(DB, HS, SP, DG, false)
     if (dig == 1) {
         // regions by the top bits: the first pass over a dense key array
         if (hashed || dbits > 8 || span) return hipErrorInvalidValue;
@@ -1003,9 +1024,11 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
         const uint64_t m_max = spec.mode ? (uint64_t)std::ceil(spec.gamma * (double)spec.hi) : L.m;
         if (grouped) return hipErrorInvalidValue;
         if ((m_max >> 32) == 0) {   // pos < m < 2^32: its low 32 bits suffice
-            if (span) MPHF_PART(8, false, true, 5); else MPHF_PART(8, false, false, 5);
+            if (gk.on) MPHF_PART_G(8, false, false, 5, true);
+            else if (span) MPHF_PART(8, false, true, 5); else MPHF_PART(8, false, false, 5);
         } else {
-            if (span) MPHF_PART(8, false, true, 3); else MPHF_PART(8, false, false, 3);
+            if (gk.on) MPHF_PART_G(8, false, false, 3, true);
+            else if (span) MPHF_PART(8, false, true, 3); else MPHF_PART(8, false, false, 3);
         }
     } else if (dig == 4) {
         // packed records in and out: the second pass
@@ -1015,10 +1038,13 @@ hipError_t launch_partition(int dbits, bool hashed, const uint64_t* in, uint64_t
     } else {
         // level hashes: one pass over keys
         if (hashed) return hipErrorInvalidValue;
-        if (dbits <= 8) { if (span) MPHF_PART(8, false, true, 0); else MPHF_PART(8, false, false, 0); }
+        if (gk.on) {
+            if (dbits <= 8) MPHF_PART_G(8, false, false, 0, true); else MPHF_PART_G(10, false, false, 0, true);
+        } else if (dbits <= 8) { if (span) MPHF_PART(8, false, true, 0); else MPHF_PART(8, false, false, 0); }
         else { if (span) MPHF_PART(10, false, true, 0); else MPHF_PART(10, false, false, 0); }
     }
 #undef MPHF_PART
+#undef MPHF_PART_G
     return hipGetLastError();
 }
 

@@ -20,13 +20,6 @@ namespace {
 
 constexpr int ZT = 256;
 
-__device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t i) {
-    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 // True if x was placed at one of the levels 0..d-1 (its bit is set in A there).
 __device__ __forceinline__ bool placed_before(uint64_t x, const DevLevel* __restrict__ lev, uint32_t d,
                                               const uint64_t* __restrict__ words) {
