@@ -191,7 +191,7 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
 #pragma unroll
                 for (int it = 0; it < FI; ++it) {
                     if (c0 + it * BW + threadIdx.x < n) {
-                        const uint32_t p = (uint32_t)level_pos(kk[it], L);
+                        const uint32_t p = level_pos32(kk[it], L);   // (a level in LDS: m < 2^32)
                         const uint32_t bit = 1u << (p & 31);
                         const uint32_t old = atomicOr(&Ab[p >> 5], bit);
                         if (old & bit) atomicOr(&Cb[p >> 5], bit);
@@ -224,7 +224,7 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
                 for (int it = 0; it < FI; ++it) {
                     bool keep = false;
                     if (c0 + it * BW + threadIdx.x < n) {
-                        const uint32_t p = (uint32_t)level_pos(kk[it], L);
+                        const uint32_t p = level_pos32(kk[it], L);   // (a level in LDS: m < 2^32)
                         keep = !((Ab[p >> 5] >> (p & 31)) & 1u);
                     }
                     sv |= (uint32_t)keep << it;

@@ -59,6 +59,15 @@ __device__ __forceinline__ uint64_t level_pos(uint64_t key, const LevelHash& L) 
     return mod_invariant(fmix64(key ^ L.seed), L.m, L.magic, L.sh1, L.sh2);
 }
 
+// level_pos for levels below 2^32 positions: the remainder h - q m is below 2^32, so its low 32
+// bits (one 32-bit multiply) are all of it.
+__device__ __forceinline__ uint32_t level_pos32(uint64_t key, const LevelHash& L) {
+    const uint64_t h = fmix64(key ^ L.seed);
+    const uint64_t t = __umul64hi(L.magic, h);
+    const uint64_t q = (t + ((h - t) >> L.sh1)) >> L.sh2;
+    return (uint32_t)h - (uint32_t)q * (uint32_t)L.m;
+}
+
 // Exact floor(a * 2^64 / m) for a < m (any m >= 1) by binary long division (one thread).  The
 // remainder stays below m; when m > 2^63 a doubled remainder can pass 2^64, which the carry out of
 // the shift records (the true remainder is then >= m, and the wrapped subtraction is exact).

@@ -859,7 +859,7 @@ k_tail(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __re
         __syncthreads();
         const LevelHash L = Ls;
         for (uint32_t i = threadIdx.x; i < n; i += BT) {
-            const uint32_t p = (uint32_t)level_pos(keys[i], L);
+            const uint32_t p = level_pos32(keys[i], L);   // (a level in LDS: m < 2^32)
             const uint32_t bit = 1u << (p & 31);
             const uint32_t old = atomicOr(&Abits[p >> 5], bit);
             if (old & bit) atomicOr(&Cbits[p >> 5], bit);
@@ -889,7 +889,7 @@ k_tail(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t* __re
             kk[it] = 0;
             if (i < n) {
                 kk[it] = keys[i];
-                const uint32_t p = (uint32_t)level_pos(kk[it], L);
+                const uint32_t p = level_pos32(kk[it], L);   // (a level in LDS: m < 2^32)
                 if (!((Abits[p >> 5] >> (p & 31)) & 1u)) mask |= 1u << it;
             }
         }
