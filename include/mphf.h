@@ -60,7 +60,8 @@ typedef struct mphf_opts {
     uint32_t flags;           /* 0, or MPHF_FLAG_ATOMIC_LEVELS */
     /* Launch configuration of the batched build (0 = default; ignored by single builds):
      * threads per workgroup 128/256/512 (default 256), keys in flight per thread 4/8/16
-     * (default 8), workgroups per CU 1..8 (default: as many as the LDS allows, at most 8). */
+     * (default 4), workgroups per CU 1..8 (default: as many as the LDS allows, at most 8).
+     * The size-class split of its work queue is at the end of this struct. */
     uint32_t batch_threads;
     uint32_t batch_items;
     uint32_t batch_wgs_per_cu;
@@ -71,6 +72,13 @@ typedef struct mphf_opts {
                                  else 6..16 and at most that default.  Smaller buckets make a level
                                  take more buckets and wider partition passes with the same result;
                                  for checks of those paths on small key sets. */
+    /* Work queues of the batched build (0 = default; ignored by single builds).  Sets of fewer
+     * than 2^(batch_small_class - 1) keys are small (1..64; default 13: below 4096 keys; 1: none,
+     * one queue, largest sets first); every batch_small_every-th workgroup (default 2) takes
+     * small sets first and the others large sets first, so that the small sets' short,
+     * latency-bound levels overlap the large sets' streaming passes.  Same result either way. */
+    uint32_t batch_small_class;
+    uint32_t batch_small_every;
 } mphf_opts;
 
 /* Build every level by global atomic test-and-set on the interleaved A/C words instead of the

@@ -1,11 +1,14 @@
 """Autotuner for the batched build's launch configuration.
 
-The batched build kernel has three knobs: threads per workgroup (128, 256, 512), keys each
-thread keeps in flight in the level passes (4, 8, 16), and workgroups per CU (bounded by the
-LDS the largest set needs).  Which is fastest depends on the device and on the batch's size
-distribution, not on the key values, so the tuner times every candidate on seeded synthetic
-keys of the caller's set sizes with a planned batch (build kernels only, HIP events on the
-build stream, median of a few repetitions) and keeps the winner in a JSON cache on disk.
+The batched build kernel has five knobs: threads per workgroup (128, 256, 512), keys each
+thread keeps in flight in the level passes (4, 8, 16), workgroups per CU (bounded by the LDS
+the largest set needs), and the size-class split of its work queue: the class below which a
+set counts as small, and which share of the workgroups takes small sets first (one queue,
+largest sets first; or every 2nd or 4th workgroup on the sets below 4096 keys).  Which is
+fastest depends on the device and on the batch's size distribution, not on the key values, so
+the tuner times every candidate on seeded synthetic keys of the caller's set sizes with a
+planned batch (build kernels only, HIP events on the build stream, median of a few
+repetitions) and keeps the winner in a JSON cache on disk.
 
 The cache key is the device (name, architecture, CU count), gamma, the level limit and the
 histogram of set sizes by power of two (sets of sizes in [2^k, 2^(k+1)) behave alike), so a
@@ -29,6 +32,9 @@ from . import inputs, mphf
 THREADS = (128, 256, 512)
 ITEMS = (4, 8, 16)
 WGS_PER_CU = (0, 2, 4)          # 0: as many as the LDS allows (at most 8)
+# (small class, small every): (1, 2) has no small sets, so one queue, largest first
+QUEUES = ((1, 2), (13, 2), (13, 4))
+DEFAULT = (256, 4, 0, 13, 2)    # the library's default launch
 
 _lock = threading.Lock()
 
@@ -78,7 +84,8 @@ def candidates():
     for t in THREADS:
         for i in ITEMS:
             for w in WGS_PER_CU:
-                yield (t, i, w)
+                for c, e in QUEUES:
+                    yield (t, i, w, c, e)
 
 
 def time_launch(offsets: torch.Tensor, keys: torch.Tensor, gamma: float, max_levels: int, launch,
@@ -118,15 +125,15 @@ def tune(offsets: torch.Tensor, gamma: float = 2.0, max_levels: int = 25, reps: 
             print(f"# tune {c}: {t:.3f} ms", flush=True)
     results.sort()
     best_t, best = results[0]
-    default_t = next(t for t, c in results if c == (256, 8, 0))
+    default_t = next(t for t, c in results if c == DEFAULT)
     return {"launch": list(best), "ms": best_t, "default_ms": default_t,
             "candidates": [[list(c), t] for t, c in results]}
 
 
 def batch_launch(offsets: torch.Tensor, gamma: float = 2.0, max_levels: int = 25, retune: bool = False,
                  verbose: bool = False):
-    """The tuned (threads, items, workgroups per CU) for this device and batch shape: from the cache,
-    or tuned now and stored."""
+    """The tuned (threads, items, workgroups per CU, small class, small every) for this device and
+    batch shape: from the cache, or tuned now and stored."""
     dk, wk = device_key(offsets.device if offsets.is_cuda else None), workload_key(offsets, gamma, max_levels)
     with _lock:
         cache = _load()

@@ -1798,6 +1798,7 @@ struct mphf_batch {
     // what a planned batch keeps for its rebuilds
     uint64_t* offsets = nullptr;
     uint32_t* order = nullptr;
+    uint32_t* hist = nullptr;   // sets per size class
     uint64_t* region_w = nullptr;
     uint64_t* sreg_base = nullptr;
     unsigned long long* queue = nullptr;
@@ -1934,6 +1935,7 @@ mphf_status check_batch_args(const uint64_t* offsets, uint64_t nsets, double gam
     const uint32_t t = o.batch_threads, it = o.batch_items;
     if ((t && t != 128 && t != 256 && t != 512) || (it && it != 4 && it != 8 && it != 16) || o.batch_wgs_per_cu > 8)
         return fail(MPHF_E_INVALID, "batch launch: threads 128/256/512, items 4/8/16, at most 8 workgroups per CU");
+    if (o.batch_small_class > 64) return fail(MPHF_E_INVALID, "batch_small_class: 0 (default) or 1..64");
     return MPHF_OK;
 }
 
@@ -1967,7 +1969,8 @@ mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* off
         off_copy = keep ? c.take<uint64_t>(S1) : nullptr;
     };
     if ((st = keep ? mem.own(b, lay1, "batch plan") : mem.temp(0, lay1)) != MPHF_OK) return st;
-    b->queue = info + 2;
+    b->queue = info + 2;   // (two counters)
+    b->hist = hist;
     b->fail32 = hist + 2 * ncls;
     if (keep) {
         HIP_TRY(hipMemcpyAsync(off_copy, offsets, S1 * 8, hipMemcpyDeviceToDevice, s), "copy offsets");
@@ -2016,8 +2019,10 @@ mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* off
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device), "CU count");
     b->cfg.threads = o.batch_threads ? o.batch_threads : 256;
-    b->cfg.items = o.batch_items ? o.batch_items : 8;
+    b->cfg.items = o.batch_items ? o.batch_items : 4;
     b->cfg.wgs_per_cu = o.batch_wgs_per_cu;
+    b->cfg.small_class = o.batch_small_class ? o.batch_small_class : 13;
+    b->cfg.small_every = o.batch_small_every ? o.batch_small_every : 2;
     HIP_TRY(batch_kernel_setup(b->cfg, b->max_m, BATCH_LEFT_CAP), "batch kernel setup");
     const uint64_t lds = batch_lds_bytes(b->max_m, BATCH_LEFT_CAP);
     uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(8, 155000 / (lds + 1024)));
@@ -2035,7 +2040,7 @@ mphf_status batch_setup(mphf_batch* b, const uint64_t* keys, const uint64_t* off
 hipError_t batch_levels(const mphf_batch* b, const uint64_t* keys, hipStream_t s) {
     hipError_t e;
     if ((e = launch_batch_reset(b->queue, b->fail32, s)) != hipSuccess) return e;
-    if ((e = launch_batch_build(keys, b->offsets, b->order, b->nsets, b->queue, b->scratch, b->region_w, b->gamma,
+    if ((e = launch_batch_build(keys, b->offsets, b->order, b->nsets, b->hist, b->queue, b->scratch, b->region_w, b->gamma,
                                 b->seeds, b->D, BATCH_LEFT_CAP, b->region, b->sec, b->sreg_base, b->sets, b->levels,
                                 b->max_m, b->cfg, b->grid, s)) != hipSuccess)
         return e;

@@ -122,21 +122,27 @@ k_batch_order(const uint64_t* __restrict__ offsets, uint64_t nsets, const uint32
     }
 }
 
-// Start of every build: empty work queue, no failure (fail[1] is the first failing set).
+// Start of every build: empty work queues, no failure (fail[1] is the first failing set).
 __global__ void k_batch_reset(unsigned long long* queue, uint32_t* fail) {
     if (threadIdx.x == 0) {
-        *queue = 0;
+        queue[0] = 0;
+        queue[1] = 0;
         fail[0] = 0;
         fail[1] = 0xFFFFFFFFu;
     }
 }
 
 // One workgroup of BW threads builds one set at a time, with FI keys per thread in flight in the
-// level passes.
+// level passes.  The sets come from two queues over `order` (descending size class): the large
+// sets (class >= small_class) and after them the small ones.  Every small_every-th workgroup (none
+// when 0) takes small sets first, so that their latency-bound levels run beside the large sets'
+// streaming passes instead of after them; the others take large sets first.  A workgroup whose
+// first queue is empty takes from the other.
 template <int BW, int FI>
 __global__ void __launch_bounds__(BW)
 k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ offsets,
-              const uint32_t* __restrict__ order, uint64_t nsets, unsigned long long* next,
+              const uint32_t* __restrict__ order, uint64_t nsets, const uint32_t* __restrict__ hist,
+              uint32_t small_class, uint32_t small_every, unsigned long long* next,
               uint64_t* __restrict__ scratch, const uint64_t* __restrict__ region_w, double gamma,
               SeedTable seeds, uint32_t D, uint32_t left_cap, uint64_t* __restrict__ region,
               uint32_t* __restrict__ sreg, const uint64_t* __restrict__ sreg_base,
@@ -148,9 +154,27 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
     __shared__ uint32_t s_status;
     __shared__ LevelHash s_L;
     const uint32_t wave = threadIdx.x >> 6;
+    // items [0, first_small) are the large sets
+    uint64_t first_small = 0;
+    if (threadIdx.x == 0)
+        for (uint32_t c = small_class; c < (uint32_t)NCLASS; ++c) first_small += hist[c];
+    const bool small_first = small_every && blockIdx.x % small_every == 0;
+    bool large_left = true, small_left = true;   // (thread 0's view of the queues)
     for (;;) {
         if (threadIdx.x == 0) {
-            s_item = atomicAdd(next, 1ull);
+            uint64_t item = nsets;
+            for (int t = 0; t < 2 && item == nsets; ++t) {
+                if ((t == 0) == small_first) {
+                    if (small_left) {
+                        const uint64_t j = first_small + atomicAdd(&next[1], 1ull);
+                        if (j < nsets) item = j; else small_left = false;
+                    }
+                } else if (large_left) {
+                    const uint64_t i = atomicAdd(&next[0], 1ull);
+                    if (i < first_small) item = i; else large_left = false;
+                }
+            }
+            s_item = item;
             s_status = 0;
         }
         __syncthreads();
@@ -167,37 +191,25 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
         uint64_t off = 0;
         uint32_t d = 0;
         bool overflow = false;
-        while (n > 0 && d < D) {
-            const uint64_t m = (uint64_t)ceil(gamma * (double)n);
-            if (off + 64 * ((m + 63) >> 6) > cap_bits) {   // uniform: stop, the batch is redone larger
+        // A level's start: its size, its hash and A and C cleared in LDS; false (uniform) when the
+        // set's staging region is too small, and the batch is redone larger.
+        auto begin_level = [&](uint64_t& m, uint32_t*& Ab, uint32_t*& Cb, LevelHash& L) {
+            m = (uint64_t)ceil(gamma * (double)n);
+            if (off + 64 * ((m + 63) >> 6) > cap_bits) {
                 overflow = true;
-                break;
+                return false;
             }
             const uint32_t aw = (uint32_t)((m + 31) >> 5);
-            uint32_t* Ab = lds;
-            uint32_t* Cb = lds + aw + (aw & 1);
+            Ab = lds;
+            Cb = lds + aw + (aw & 1);
             if (threadIdx.x == 0) s_L = device_level_hash(seeds.s[d], m, 0);
             for (uint32_t w = threadIdx.x; w < 2 * aw + 2; w += BW) lds[w] = 0;
             __syncthreads();
-            const LevelHash L = s_L;
-            // fill: FI loads in flight per thread, then the LDS test-and-set of each
-            for (uint64_t c0 = 0; c0 < n; c0 += BW * FI) {
-                uint64_t kk[FI];
-#pragma unroll
-                for (int it = 0; it < FI; ++it) {
-                    const uint64_t i = c0 + it * BW + threadIdx.x;
-                    kk[it] = i < n ? F[i] : 0;
-                }
-#pragma unroll
-                for (int it = 0; it < FI; ++it) {
-                    if (c0 + it * BW + threadIdx.x < n) {
-                        const uint32_t p = level_pos32(kk[it], L);   // (a level in LDS: m < 2^32)
-                        const uint32_t bit = 1u << (p & 31);
-                        const uint32_t old = atomicOr(&Ab[p >> 5], bit);
-                        if (old & bit) atomicOr(&Cb[p >> 5], bit);
-                    }
-                }
-            }
+            L = s_L;
+            return true;
+        };
+        // After the fill: the finalized A words to the set's staging region, and A &= ~C in LDS.
+        auto finalize = [&](uint64_t m, uint32_t* Ab, const uint32_t* Cb) {
             __syncthreads();
             const uint64_t words = (m + 63) >> 6;
             for (uint32_t j = threadIdx.x; j < words; j += BW) {
@@ -206,50 +218,16 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
                 A[(off >> 6) + j] = (uint64_t)a0 | ((uint64_t)a1 << 32);
             }
             __syncthreads();
-            for (uint32_t w = threadIdx.x; w < aw; w += BW) Ab[w] &= ~Cb[w];
+            for (uint32_t w = threadIdx.x; w < (uint32_t)((m + 31) >> 5); w += BW) Ab[w] &= ~Cb[w];
             __syncthreads();
-            // filter, compacted in place into the set's scratch region in key order: a chunk is read
-            // into registers before any of its survivors is written, and survivors only move left
-            uint64_t out = 0;
-            for (uint64_t c0 = 0; c0 < n; c0 += BW * FI) {
-                uint64_t kk[FI];
-                uint32_t sv = 0;
-#pragma unroll
-                for (int it = 0; it < FI; ++it) {
-                    const uint64_t i = c0 + it * BW + threadIdx.x;
-                    kk[it] = i < n ? F[i] : 0;
-                }
-                uint32_t wc = 0;
-#pragma unroll
-                for (int it = 0; it < FI; ++it) {
-                    bool keep = false;
-                    if (c0 + it * BW + threadIdx.x < n) {
-                        const uint32_t p = level_pos32(kk[it], L);   // (a level in LDS: m < 2^32)
-                        keep = !((Ab[p >> 5] >> (p & 31)) & 1u);
-                    }
-                    sv |= (uint32_t)keep << it;
-                    wc += (uint32_t)__popcll(__ballot(keep));
-                }
-                if (lane_id() == 0) wsum[wave] = wc;
-                __syncthreads();
-                uint64_t base = out;
-                uint32_t tot = 0;
-#pragma unroll
-                for (int w = 0; w < NWAVE; ++w) {
-                    const uint32_t v = wsum[w];
-                    if (w < (int)wave) base += v;
-                    tot += v;
-                }
-#pragma unroll
-                for (int it = 0; it < FI; ++it) {
-                    const bool keep = (sv >> it) & 1u;
-                    const uint64_t bal = __ballot(keep);
-                    if (keep) scr[base + lanes_below(bal)] = kk[it];
-                    base += (uint32_t)__popcll(bal);
-                }
-                out += tot;
-                __syncthreads();
-            }
+        };
+        auto test_and_set = [&](uint32_t* Ab, uint32_t* Cb, uint32_t p) {
+            const uint32_t bit = 1u << (p & 31);
+            const uint32_t old = atomicOr(&Ab[p >> 5], bit);
+            if (old & bit) atomicOr(&Cb[p >> 5], bit);
+        };
+        // After the filter: the level's record, and the survivors become the next level's keys.
+        auto end_level = [&](uint64_t m, const LevelHash& L, uint64_t nnext) {
             if (threadIdx.x == 0) {
                 BatchLevel& bl = levels[(uint64_t)s * D + d];
                 bl.m = m;
@@ -258,10 +236,126 @@ k_batch_build(const uint64_t* __restrict__ keys, const uint64_t* __restrict__ of
                 bl.n = (uint32_t)n;
                 bl.sh = L.sh1 | (L.sh2 << 8);
             }
-            n = out;
-            off += 64 * words;
-            F = scr;
+            n = nnext;
+            off += 64 * ((m + 63) >> 6);
             ++d;
+        };
+        // The kept items of every thread, in (wave, item, lane) order, to dst from base on (all
+        // threads' values of wsum are read before it is written again).
+        auto write_kept = [&](const uint64_t (&k)[FI], uint32_t kept, uint64_t* dst, uint64_t base) {
+            uint32_t wc = 0;
+#pragma unroll
+            for (int it = 0; it < FI; ++it) wc += (uint32_t)__popcll(__ballot((kept >> it) & 1u));
+            if (lane_id() == 0) wsum[wave] = wc;
+            __syncthreads();
+            uint32_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < NWAVE; ++w) {
+                const uint32_t v = wsum[w];
+                if (w < (int)wave) base += v;
+                tot += v;
+            }
+#pragma unroll
+            for (int it = 0; it < FI; ++it) {
+                const bool keep = (kept >> it) & 1u;
+                const uint64_t bal = __ballot(keep);
+                if (keep) dst[base + lanes_below(bal)] = k[it];
+                base += (uint32_t)__popcll(bal);
+            }
+            __syncthreads();
+            return tot;
+        };
+        auto load = [&](uint64_t (&k)[FI], uint64_t c0) {
+#pragma unroll
+            for (int it = 0; it < FI; ++it) {
+                const uint64_t i = c0 + it * BW + threadIdx.x;
+                k[it] = i < n ? F[i] : 0;
+            }
+        };
+
+        // Levels of more than BW * FI keys: the keys streamed from global memory in chunks of
+        // BW * FI, the next chunk's loads issued before the current one is processed.
+        while (n > (uint64_t)(BW * FI) && d < D) {
+            uint64_t m;
+            uint32_t *Ab, *Cb;
+            LevelHash L;
+            if (!begin_level(m, Ab, Cb, L)) break;
+            uint64_t kn[FI];
+            load(kn, 0);
+            for (uint64_t c0 = 0; c0 < n; c0 += BW * FI) {
+                uint64_t kk[FI];
+#pragma unroll
+                for (int it = 0; it < FI; ++it) kk[it] = kn[it];
+                if (c0 + BW * FI < n) load(kn, c0 + BW * FI);
+#pragma unroll
+                for (int it = 0; it < FI; ++it)
+                    if (c0 + it * BW + threadIdx.x < n) test_and_set(Ab, Cb, level_pos32(kk[it], L));
+            }
+            finalize(m, Ab, Cb);
+            // filter, compacted in place into the set's scratch region in key order: survivors only
+            // move left, so the writes of chunk c stay below chunk c + 1, which every thread has
+            // loaded (and waited for) before the barrier that precedes them
+            uint64_t out = 0;
+            load(kn, 0);
+            for (uint64_t c0 = 0; c0 < n; c0 += BW * FI) {
+                uint64_t kk[FI];
+#pragma unroll
+                for (int it = 0; it < FI; ++it) kk[it] = kn[it];
+                if (c0 + BW * FI < n) load(kn, c0 + BW * FI);
+                uint32_t sv = 0;
+#pragma unroll
+                for (int it = 0; it < FI; ++it) {
+                    bool keep = false;
+                    if (c0 + it * BW + threadIdx.x < n) {
+                        const uint32_t p = level_pos32(kk[it], L);   // (a level in LDS: m < 2^32)
+                        keep = !((Ab[p >> 5] >> (p & 31)) & 1u);
+                    }
+                    sv |= (uint32_t)keep << it;
+                }
+                out += write_kept(kk, sv, scr, out);
+            }
+            end_level(m, L, out);
+            F = scr;
+        }
+        // The remaining levels (at most BW * FI keys) in registers: item it of a thread holds key
+        // it * BW + thread while its bit in `live` is set, so no level reads or writes keys in
+        // global memory; the keys left after the last level go to the front of the scratch region.
+        if (n > 0 && d < D && !overflow) {
+            uint64_t kr[FI];
+            load(kr, 0);
+            uint32_t live = 0;
+#pragma unroll
+            for (int it = 0; it < FI; ++it) live |= (uint32_t)(it * BW + threadIdx.x < n) << it;
+            while (n > 0 && d < D) {
+                uint64_t m;
+                uint32_t *Ab, *Cb;
+                LevelHash L;
+                if (!begin_level(m, Ab, Cb, L)) break;
+#pragma unroll
+                for (int it = 0; it < FI; ++it)
+                    if ((live >> it) & 1u) test_and_set(Ab, Cb, level_pos32(kr[it], L));
+                finalize(m, Ab, Cb);
+                uint32_t wc = 0, next = 0;
+#pragma unroll
+                for (int it = 0; it < FI; ++it) {
+                    bool keep = false;
+                    if ((live >> it) & 1u) {
+                        const uint32_t p = level_pos32(kr[it], L);
+                        keep = !((Ab[p >> 5] >> (p & 31)) & 1u);
+                    }
+                    next |= (uint32_t)keep << it;
+                    wc += (uint32_t)__popcll(__ballot(keep));
+                }
+                live = next;
+                if (lane_id() == 0) wsum[wave] = wc;
+                __syncthreads();
+                uint32_t tot = 0;
+#pragma unroll
+                for (int w = 0; w < NWAVE; ++w) tot += wsum[w];
+                __syncthreads();
+                end_level(m, L, tot);
+            }
+            if (n > 0 && !overflow) write_kept(kr, live, scr, 0);
         }
         // leftovers: sorted ascending by counting, back into the front of the set's scratch region
         // (there are almost never more than a few; above left_cap the set is reported and the batch
@@ -516,7 +610,7 @@ hipError_t launch_batch_reset(unsigned long long* queue, uint32_t* fail, hipStre
 }
 
 hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
-                              uint64_t nsets, unsigned long long* next, uint64_t* scratch,
+                              uint64_t nsets, const uint32_t* hist, unsigned long long* next, uint64_t* scratch,
                               const uint64_t* region_w, double gamma, const SeedTable& seeds,
                               uint32_t D, uint32_t left_cap, uint64_t* region, uint32_t* sreg,
                               const uint64_t* sreg_base, BatchSet* sets, BatchLevel* levels, uint64_t max_m,
@@ -524,7 +618,9 @@ hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, con
     const uint64_t lds = batch_lds_bytes(max_m, left_cap);
     const void* k = batch_kernel(cfg);
     if (!k) return hipErrorInvalidValue;
-    void* args[] = {(void*)&keys, (void*)&offsets, (void*)&order, (void*)&nsets, (void*)&next, (void*)&scratch,
+    uint32_t small_class = cfg.small_class, small_every = cfg.small_every;
+    void* args[] = {(void*)&keys, (void*)&offsets, (void*)&order, (void*)&nsets, (void*)&hist,
+                    (void*)&small_class, (void*)&small_every, (void*)&next, (void*)&scratch,
                     (void*)&region_w, (void*)&gamma, (void*)&seeds, (void*)&D, (void*)&left_cap, (void*)&region,
                     (void*)&sreg, (void*)&sreg_base, (void*)&sets, (void*)&levels};
     return hipLaunchKernel(k, dim3(grid), dim3(cfg.threads), args, (size_t)lds, s);

@@ -311,8 +311,10 @@ hipError_t launch_report(unsigned long long* flag, const uint64_t* total, uint64
 // per thread in flight (4, 8 or 16) and workgroups per CU (1..8, further bounded by LDS).
 struct BatchLaunch {
     uint32_t threads = 256;
-    uint32_t items = 8;
-    uint32_t wgs_per_cu = 0;   // 0: as many as the LDS allows, at most 8
+    uint32_t items = 4;
+    uint32_t wgs_per_cu = 0;     // 0: as many as the LDS allows, at most 8
+    uint32_t small_class = 13;   // sets of fewer than 2^(small_class - 1) keys are small
+    uint32_t small_every = 2;    // every small_every-th workgroup takes small sets first (0: none)
 };
 
 uint32_t batch_classes();
@@ -323,7 +325,7 @@ hipError_t launch_batch_order(const uint64_t* offsets, uint64_t nsets, const uin
                               uint32_t* order, hipStream_t s);
 hipError_t launch_batch_reset(unsigned long long* queue, uint32_t* fail, hipStream_t s);
 hipError_t launch_batch_build(const uint64_t* keys, const uint64_t* offsets, const uint32_t* order,
-                              uint64_t nsets, unsigned long long* next, uint64_t* scratch,
+                              uint64_t nsets, const uint32_t* hist, unsigned long long* next, uint64_t* scratch,
                               const uint64_t* region_w, double gamma, const SeedTable& seeds,
                               uint32_t D, uint32_t left_cap, uint64_t* region, uint32_t* sreg,
                               const uint64_t* sreg_base, BatchSet* sets, BatchLevel* levels, uint64_t max_m,

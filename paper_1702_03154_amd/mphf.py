@@ -33,7 +33,8 @@ class Opts(C.Structure):
     _fields_ = [("max_levels", C.c_uint32), ("rank_sample", C.c_uint32),
                 ("mem_budget", C.c_uint64), ("keep_collisions", C.c_uint32),
                 ("flags", C.c_uint32), ("batch_threads", C.c_uint32), ("batch_items", C.c_uint32),
-                ("batch_wgs_per_cu", C.c_uint32), ("bucket_bits", C.c_uint32)]
+                ("batch_wgs_per_cu", C.c_uint32), ("bucket_bits", C.c_uint32),
+                ("batch_small_class", C.c_uint32), ("batch_small_every", C.c_uint32)]
 
 
 _U64L = C.c_uint64 * MAX_LEVELS
@@ -276,14 +277,20 @@ class Batch:
     def _opts(max_levels: int, launch) -> Opts:
         o = Opts(max_levels, 512, 0, 0, 0)
         if launch is not None:
-            o.batch_threads, o.batch_items, o.batch_wgs_per_cu = (int(v) for v in launch)
+            v = [int(x) for x in launch]
+            if len(v) not in (3, 5):
+                raise ValueError("launch: (threads, items, workgroups per CU[, small class, small every])")
+            o.batch_threads, o.batch_items, o.batch_wgs_per_cu = v[:3]
+            if len(v) == 5:
+                o.batch_small_class, o.batch_small_every = v[3:]
         return o
 
     @classmethod
     def build(cls, keys: torch.Tensor, offsets: torch.Tensor, gamma: float = 2.0, seed: int = 0,
               max_levels: int = 25, stream=None, launch=None) -> "Batch":
-        """One-shot batched build.  ``launch``: (threads, items, workgroups per CU), e.g. from
-        :func:`paper_1702_03154_amd.autotune.batch_launch`; None = the library's default."""
+        """One-shot batched build.  ``launch``: (threads, items, workgroups per CU[, small class,
+        small every]), e.g. from :func:`paper_1702_03154_amd.autotune.batch_launch`; None = the
+        library's default."""
         L = lib()
         o = cls._opts(max_levels, launch)
         h = C.c_void_p()

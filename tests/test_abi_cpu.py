@@ -76,8 +76,8 @@ def test_binding_structs_match_the_header(tmp_path):
 int main(void) {
     printf("%zu %zu %zu %zu\\n", sizeof(mphf_opts), sizeof(mphf_stats_t), sizeof(mphf_view_t),
            sizeof(mphf_set_info_t));
-    printf("%zu %zu %zu\\n", offsetof(mphf_opts, batch_threads), offsetof(mphf_stats_t, n_fallback),
-           offsetof(mphf_set_info_t, total_bits));
+    printf("%zu %zu %zu %zu\\n", offsetof(mphf_opts, batch_threads), offsetof(mphf_stats_t, n_fallback),
+           offsetof(mphf_set_info_t, total_bits), offsetof(mphf_opts, batch_small_every));
     return 0;
 }
 """)
@@ -89,7 +89,7 @@ int main(void) {
     assert sizes == [ctypes.sizeof(mphf.Opts), ctypes.sizeof(mphf.Stats), ctypes.sizeof(mphf.View),
                      ctypes.sizeof(mphf.SetInfo)]
     assert offs == [mphf.Opts.batch_threads.offset, mphf.Stats.n_fallback.offset,
-                    mphf.SetInfo.total_bits.offset]
+                    mphf.SetInfo.total_bits.offset, mphf.Opts.batch_small_every.offset]
 
 
 def test_autotune_cache_keys(tmp_path, monkeypatch):
@@ -104,4 +104,5 @@ def test_autotune_cache_keys(tmp_path, monkeypatch):
     assert autotune.workload_key(a, 2.0, 25) != autotune.workload_key(a, 1.0, 25)
     autotune._store({"dev": {"k": {"launch": [512, 4, 2]}}})
     assert autotune._load()["dev"]["k"]["launch"] == [512, 4, 2]
-    assert len(list(autotune.candidates())) == 27
+    assert len(list(autotune.candidates())) == 81
+    assert autotune.DEFAULT in set(autotune.candidates())

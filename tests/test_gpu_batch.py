@@ -303,6 +303,36 @@ def test_every_launch_configuration_gives_the_same_batch(M):
         M.build_batch(kc, oc, 2.0, 3, launch=(300, 8, 0))
 
 
+@pytest.mark.parametrize("launch", [
+    (256, 4, 0, 1, 1),       # no small sets: one queue, largest first
+    (256, 4, 0, 64, 1),      # every set small, every workgroup on the small queue
+    (256, 8, 0, 13, 1),      # every workgroup takes small sets first
+    (128, 16, 2, 5, 3),      # small = below 16 keys
+    (512, 4, 4, 17, 1000),   # one workgroup in 1000 takes small sets first
+])
+def test_work_queue_split_gives_the_same_batch(M, launch):
+    """The two work queues (large sets first for most workgroups, small sets first for every k-th)
+    only change which workgroup builds which set and when: every label and sector must equal the
+    default build's, whatever the class threshold and share, including the degenerate splits."""
+    sizes, keys, off = make_sets(I.log_uniform_sizes(400, 1, 30000, seed=52))
+    kc, oc = keys.cuda(), off.cuda()
+    ids = torch.repeat_interleave(torch.arange(400), sizes).cuda()
+    ref = M.build_batch(kc, oc, 2.0, 5)
+    b = M.build_batch(kc, oc, 2.0, 5, launch=launch)
+    assert torch.equal(b.lookup(ids, kc), ref.lookup(ids, kc)), launch
+    for s in range(0, 400, 13):
+        assert np.array_equal(b.export_sectors(s), ref.export_sectors(s)), (launch, s)
+    plan = M.Batch.plan(oc, 2.0, 5, launch=launch)
+    plan.rebuild(kc).status()
+    assert torch.equal(plan.lookup(ids, kc), ref.lookup(ids, kc)), launch
+    for s in (0, 1, 2, 3, 399):
+        assert np.array_equal(plan.export_sectors(s), ref.export_sectors(s)), (launch, s)
+    for x in (b, plan, ref):
+        x.close()
+    with pytest.raises(M.MphfError):
+        M.build_batch(kc, oc, 2.0, 5, launch=(256, 4, 0, 65, 2))
+
+
 def test_tuner_picks_a_candidate_and_caches_it(M, tmp_path, monkeypatch):
     from paper_1702_03154_amd import autotune
     monkeypatch.setenv("MPHF_TUNE_CACHE", str(tmp_path / "tune.json"))
