@@ -814,7 +814,7 @@ def bench_gamma(args):
 
 
 
-def plain_steps(mphf, keys, queries, out, gamma, steps, warmup, tag=""):
+def plain_steps(mphf, keys, queries, out, gamma, steps, warmup, tag="", **build_opts):
     """`warmup` + `steps` build + lookup steps; per-step event times on the current stream."""
     import torch
     s = torch.cuda.current_stream()
@@ -824,7 +824,7 @@ def plain_steps(mphf, keys, queries, out, gamma, steps, warmup, tag=""):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         torch.cuda.synchronize()
         e0.record(s)
-        h = mphf.build(keys, gamma, 0)
+        h = mphf.build(keys, gamma, 0, **build_opts)
         e1.record(s)
         h.lookup(queries, out=out)
         e2.record(s)
@@ -988,6 +988,17 @@ def main():
                          "build_ms": t1b, "lookup_ms": t1l, "labels_bijective": ok1,
                          "levels": st1["num_levels"], "bits_per_key": st1["bits_per_key"],
                          "n_fallback": st1["n_fallback"], "mean_probes": mean_probes(st1), "steps": 3}
+        # the same build with every level filled by global atomicOr test-and-set (the old bit
+        # deciding the collision mark): the design the partitioned levels replace, measured
+        ba, _, _, sta = plain_steps(mphf, keys, queries, out, args.gamma, 2, 1, tag="atomic levels ",
+                                    atomic_levels=True)
+        oka = bool(torch.equal(torch.sort(out).values, torch.arange(1, n + 1, device=dev)))
+        tba = statistics.median(ba)
+        res["atomic_levels"] = {
+            "build_ms": tba, "build_keys_per_s": n / (tba / 1e3), "over_partitioned": tba / tb,
+            "labels_bijective": oka, "same_total_bits": sta["total_bits"] == stats["total_bits"], "steps": 2,
+            "what": "every level built by global atomicOr test-and-set on interleaved A/C words "
+                    "(MPHF_FLAG_ATOMIC_LEVELS) instead of the position-partitioned LDS passes"}
     keys_host = queries_host = None
     if not args.no_cpu_baseline:
         import numpy as np
