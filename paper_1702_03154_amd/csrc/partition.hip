@@ -26,6 +26,10 @@
 
 #include "internal.h"
 
+#ifndef MPHF_WIDE_WC
+#define MPHF_WIDE_WC 1
+#endif
+
 namespace mphfk {
 
 namespace {
@@ -63,13 +67,14 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // (HASHED = true); DIG says what the bins and the output records are: DIG = 0 bins by level
 // position and writes h.
 //
-// A tile is counting-sorted by bin in LDS.  With 2^8 bins (WC) a workgroup also keeps, per bin,
-// the keys of its last unfinished 16-key line in LDS, and a tile writes only whole lines: a
-// 128-byte line at a 128-byte boundary of the bin's region (out_cap is a multiple of 16), each
-// line written once, by 16 adjacent lanes.  The runs of a tile average 12 keys per bin, so
-// writing them where they fall would split most lines between two tiles and two writes.  The
-// unfinished lines go out at the end.  With 2^10 bins the per-bin lines would not fit in LDS and
-// the runs are written as they are.
+// A tile is counting-sorted by bin in LDS.  With lines combined (WC) a workgroup also keeps, per
+// bin, the keys of its last unfinished line in LDS, and a tile writes only whole lines, each at a
+// line boundary of the bin's region (out_cap is a multiple of 16) and written once, by adjacent
+// lanes: 128-byte lines of 16 keys with 2^8 bins, 64-byte half lines of 8 keys with 2^10 bins
+// (whose 128-byte lines would not fit in LDS beside the tile; the workgroup then holds a whole
+// compute unit's LDS).  The runs of a tile average 12 or 3 keys per bin, so writing them where
+// they fall would split most lines between tiles and writes.  The unfinished lines go out at the
+// end.  Without WC (one-pass levels of 2^10 bins, or WIDE_WC off) the runs are written as they are.
 //
 // Tiles: with SPAN = false a tile is up to PTILE keys from the segment holding its start and the
 // next segment, and the next tile's keys are loaded while the current one is sorted and written.  With
@@ -90,7 +95,11 @@ __device__ __forceinline__ uint32_t find_segment(const uint64_t* __restrict__ pr
 // lines combined (WC) the bin's lines are counted from the line holding that start, and only the
 // workgroup's own keys of its first and last lines are written.
 
-constexpr int LW = 16;   // keys per 128-byte line
+// Keys per combined line: a 128-byte line with 2^8 bins, a 64-byte half line with 2^10 bins.
+template <int NB>
+constexpr int line_keys() { return NB > 256 ? 8 : 16; }
+// 2^10-bin passes with combined lines (else their runs are written as they fall).
+constexpr bool WIDE_WC = MPHF_WIDE_WC;
 
 // Keys generated instead of read (a first pass over a chunk of a generated stream): the key of
 // dense index i is stream_key(seed, start + i).
@@ -101,6 +110,7 @@ struct GenKeys {
 
 template <int NB, bool WC, bool DENSE>
 struct PartLds {
+    static constexpr int LW = line_keys<NB>();
     static constexpr int MAXL = WC ? (PTILE + NB * (LW - 1)) / LW + 1 : 1;
     // the tile sorted by bin in kbuf[0, PTILE); with WC, the unfinished line of bin d in
     // kbuf[PTILE + d * LW, PTILE + d * LW + LW) (one array, so a key is read from either by index)
@@ -128,6 +138,7 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
                                           uint32_t pack_shift, uint64_t bin_base, uint64_t lim,
                                           uint64_t* __restrict__ obase, uint64_t out_cap,
                                           unsigned long long* overflow) {
+    constexpr int LW = line_keys<NB>();
     uint32_t dg[PITEMS], rk[PITEMS];
     bool bad = false;
 #pragma unroll
@@ -183,25 +194,37 @@ __device__ __forceinline__ void part_tile(PartLds<NB, WC, DIG == 2>& S, uint64_t
     __syncthreads();
     if constexpr (WC) {
         // One scan gives both the tile's sorted offsets (low half) and the flush order of the
-        // lines it completes (high half): bin d completes the lines between floor(run/16) and
-        // floor((run + h)/16).  Both sums stay below 2^16.
-        const int d = threadIdx.x;
-        uint32_t h = 0, r = 0, f = 0;
-        if (d < NB) {
-            h = S.hist[d];
-            r = S.run[d];
-            f = ((r + h) & ~(uint32_t)(LW - 1)) - (r & ~(uint32_t)(LW - 1));
+        // lines it completes (high half): bin d completes the lines between floor(run/LW) and
+        // floor((run + h)/LW).  Both sums stay below 2^16 (PTILE keys; PTILE + NB (LW - 1) at
+        // most in whole lines).  A thread takes BPT consecutive bins.
+        constexpr int BPT = (NB + PT - 1) / PT;
+        uint32_t h[BPT], r[BPT], f[BPT], sum = 0;
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int d = threadIdx.x * BPT + b;
+            h[b] = r[b] = f[b] = 0;
+            if (d < NB) {
+                h[b] = S.hist[d];
+                r[b] = S.run[d];
+                f[b] = ((r[b] + h[b]) & ~(uint32_t)(LW - 1)) - (r[b] & ~(uint32_t)(LW - 1));
+            }
+            sum += h[b] | (f[b] << 16);
         }
         uint32_t tot;
-        const uint32_t ex = block_exclusive_sum<PT>(h | (f << 16), S.wsum, &tot);
-        if (d < NB) {
-            S.hoff[d] = ex & 0xFFFFu;
-            S.fpre[d] = ex >> 16;
-            S.rold[d] = r;
-            S.run[d] = r + h;
-            S.hist[d] = 0;
-            const uint32_t l0 = (ex >> 16) / LW;
-            for (uint32_t q = 0; q < f / LW; ++q) S.lbin[l0 + q] = (uint16_t)d;
+        uint32_t ex = block_exclusive_sum<PT>(sum, S.wsum, &tot);
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+            const int d = threadIdx.x * BPT + b;
+            if (d < NB) {
+                S.hoff[d] = ex & 0xFFFFu;
+                S.fpre[d] = ex >> 16;
+                S.rold[d] = r[b];
+                S.run[d] = r[b] + h[b];
+                S.hist[d] = 0;
+                const uint32_t l0 = (ex >> 16) / LW;
+                for (uint32_t q = 0; q < f[b] / LW; ++q) S.lbin[l0 + q] = (uint16_t)d;
+            }
+            ex += h[b] | (f[b] << 16);
         }
         if (threadIdx.x == 0) S.nf = tot >> 16;
         __syncthreads();
@@ -338,9 +361,11 @@ k_partition(const uint64_t* __restrict__ in, uint64_t in_stride, const uint64_t*
         L = sl.L;
     }
     constexpr int NB = 1 << DBITS;
-    constexpr bool WC = DBITS == 8;
+    // (a one-pass level of 2^9..2^10 buckets is small: it keeps two workgroups per CU instead)
+    constexpr bool WC = DBITS == 8 || (WIDE_WC && DIG != 0);
+    constexpr int LW = line_keys<NB>();
     constexpr bool DENSE = DIG == 2;
-    static_assert(!WC || PT >= NB, "one bin per thread in the line bookkeeping");
+    static_assert(PTILE + NB * (LW - 1) < 65536, "tile sums in 16 bits");
     __shared__ PartLds<NB, WC, DENSE> S;
 
     const uint32_t group = blockIdx.x / K;
