@@ -233,6 +233,35 @@ def probe_rate(kind: str, nbytes: int, ops: int = 0, reps: int = 3) -> dict:
     return {"kind": kind, "footprint_bytes": nbytes, "ops": done, "ops_per_s": done / t, "ms": t * 1e3}
 
 
+def pcie_rate(nbytes: int = 1 << 30, reps: int = 3) -> dict:
+    """The PCIe ceiling of a lookup fed from host memory: a kernel reading nbytes of pinned host
+    memory and writing them to pinned host memory (mphf_probe, host exchange), bytes moved per
+    second counting both directions."""
+    import statistics
+
+    import torch
+
+    from paper_1702_03154_amd import mphf
+
+    src, dst = mphf.HostArray(nbytes // 8), mphf.HostArray(nbytes // 8)
+    src.a[:] = 1
+    s = torch.cuda.current_stream()
+    times = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        mphf.probe_host_exchange(src, dst, nbytes)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if r:
+            times.append(e0.elapsed_time(e1) / 1e3)
+    ok = bool(dst.a[0] == 2 and dst.a[-1] == 2)
+    src.close(), dst.close()
+    t = statistics.median(times)
+    return {"kind": "host_exchange", "footprint_bytes": nbytes, "bytes_per_s": 2 * nbytes / t, "ms": t * 1e3,
+            "checked": ok}
+
+
 def bench_roofline(args):
     """The microbenchmark sweep: each random kind over LDS / L2 / MALL / HBM footprints."""
     foot = [("L2 (4 MiB)", 4 << 20), ("MALL (256 MiB)", 256 << 20), ("HBM (5 GiB)", 5 << 30)]
@@ -247,11 +276,16 @@ def bench_roofline(args):
         r = probe_rate("lds_atomic_or", b, ops=1 << 32)
         r["footprint"] = f"LDS ({b // 1024} KiB per workgroup)"
         rows.append(r)
+    r = pcie_rate()
+    r["footprint"] = "pinned host memory over PCIe (1 GiB each way)"
+    rows.append(r)
+    log(f"host exchange over PCIe: {r['bytes_per_s'] / 1e9:.1f} GB/s (both directions)")
     res = {"metric": METRIC, "value": rows[1]["bytes_per_s"], "unit": "bytes/s",
            "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": rows[1]["ms"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
            "config": {"workload": "memory-system microbenchmarks: streaming read and copy, random 8-byte and "
-                                  "64-byte-sector reads, random atomicOr with return (global and LDS)"},
+                                  "64-byte-sector reads, random atomicOr with return (global and LDS), "
+                                  "a kernel exchanging pinned host memory over PCIe"},
            "rows": rows}
     print(json.dumps(res))
 
@@ -518,6 +552,9 @@ def run_serve(args) -> dict:
         o.close()
     for h in fns:
         h.close()
+    pcie = pcie_rate()
+    log(f"host exchange over PCIe: {pcie['bytes_per_s'] / 1e9:.1f} GB/s; served moves "
+        f"{16 * sat['keys_per_s'] / 1e9:.1f} GB/s")
     return {
         "value": sat["keys_per_s"], "unit": "keys/s", "ms_per_step": 1e3 * total_keys / sat["keys_per_s"],
         "config": {"workload": f"serving: {nfn} resident functions, sizes floor(1e6*1000^u*{args.serve_scale}) "
@@ -529,6 +566,10 @@ def run_serve(args) -> dict:
         "plain": {"requests_per_s": plain_rps, "keys_per_s": total_keys / plain_s,
                   "what": "per request: copy in, lookup, copy out, wait"},
         "served_saturation": sat, "served_over_plain": sat["keys_per_s"] / (total_keys / plain_s),
+        "pcie": {"exchange_bytes_per_s": pcie["bytes_per_s"], "served_bytes_per_s": 16 * sat["keys_per_s"],
+                 "frac": 16 * sat["keys_per_s"] / pcie["bytes_per_s"],
+                 "what": "each served key is read from pinned host memory and its label written back (8 B each "
+                         "way) against a kernel exchanging pinned host memory over PCIe, measured in this run"},
         "poisson_loads_of_served_capacity": of_served,
         "poisson_loads_of_plain_capacity": of_plain,
         "server_stats": st,
@@ -1018,7 +1059,7 @@ def main():
         torch.cuda.empty_cache()
         rs = run_serve(args)
         res["served"] = {k: rs[k] for k in ("value", "unit", "config", "plain", "served_saturation",
-                                            "served_over_plain", "poisson_loads_of_served_capacity",
+                                            "served_over_plain", "pcie", "poisson_loads_of_served_capacity",
                                             "poisson_loads_of_plain_capacity")}
         res["served_over_plain"] = rs["served_over_plain"]
 

@@ -412,8 +412,12 @@ mphf_status mphf_partition_sets_noalloc(const uint64_t* keys, uint64_t n, uint32
  *   MPHF_PROBE_RANDOM_ATOMIC_OR  about `ops` atomicOr with the old value returned at random words of
  *                                buf (the global test-and-set); buf's contents change;
  *   MPHF_PROBE_LDS_ATOMIC_OR     about `ops` atomicOr with return at random words of `bytes`
- *                                (4..49152) of each workgroup's LDS; buf and dst are unused.
- * buf (and dst) are caller-owned device memory, buf 64-byte aligned.  `seed` seeds the random
+ *                                (4..49152) of each workgroup's LDS; buf and dst are unused;
+ *   MPHF_PROBE_HOST_EXCHANGE     a kernel reads `bytes` (a multiple of 8) of buf and writes them
+ *                                to dst, 8 bytes a lane, both pinned host memory (mphf_host_alloc)
+ *                                reached over PCIe: the ceiling of a lookup fed from host memory.
+ * buf (and dst) are caller-owned device memory, buf 64-byte aligned, except for
+ * MPHF_PROBE_HOST_EXCHANGE.  `seed` seeds the random
  * indices.  mphf_probe_ops(ops) is the exact number of random operations a probe of `ops` performs
  * (rounded up to whole rounds of the launch). */
 #define MPHF_PROBE_STREAM_READ 0
@@ -422,6 +426,7 @@ mphf_status mphf_partition_sets_noalloc(const uint64_t* keys, uint64_t n, uint32
 #define MPHF_PROBE_RANDOM_SECTOR64 3
 #define MPHF_PROBE_RANDOM_ATOMIC_OR 4
 #define MPHF_PROBE_LDS_ATOMIC_OR 5
+#define MPHF_PROBE_HOST_EXCHANGE 6
 mphf_status mphf_probe(uint32_t kind, void* buf, uint64_t bytes, void* dst, uint64_t ops, uint64_t seed,
                        void* stream);
 uint64_t mphf_probe_ops(uint64_t ops);

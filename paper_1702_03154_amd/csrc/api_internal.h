@@ -16,5 +16,7 @@ mphf_status hip_error(hipError_t e, const char* what);
 bool device_ptr(const void* p);
 // The lookup descriptor of a built function (device pointers owned by the handle) and its device.
 void lookup_desc(const mphf_t* h, mphfk::SegDesc* d, int* device);
+// The device-visible alias of a pinned host range [p, p + bytes), or null for other memory.
+const void* pinned_alias(const void* p, uint64_t bytes);
 
 }  // namespace mphf_api

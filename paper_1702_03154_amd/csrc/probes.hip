@@ -8,7 +8,9 @@
 //  * random 8-byte reads and random 64-byte sector reads (four 16-byte loads of one aligned
 //    sector, as a lookup probe issues them) over a footprint;
 //  * random atomicOr with the old value returned (the global test-and-set) over a footprint;
-//  * random atomicOr with return in LDS (the test-and-set of the partitioned levels).
+//  * random atomicOr with return in LDS (the test-and-set of the partitioned levels);
+//  * a kernel reading pinned host memory and writing pinned host memory over PCIe, 8 bytes a lane
+//    (as the serving kernel reads request keys and writes their labels in place).
 //
 // Random indices come from a per-thread xorshift64 generator (Marsaglia 2003) reduced by a
 // multiply-high, so that the address arithmetic stays a few instructions per access.  Each thread
@@ -97,6 +99,12 @@ __global__ void __launch_bounds__(PT) k_probe_rand64(const uint4* __restrict__ p
     sink(acc);
 }
 
+__global__ void __launch_bounds__(PT) k_probe_host(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                                   uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * PT;
+    for (uint64_t i = (uint64_t)blockIdx.x * PT + threadIdx.x; i < n; i += stride) dst[i] = src[i] + 1;
+}
+
 __global__ void __launch_bounds__(PT) k_probe_atomic(unsigned long long* __restrict__ p, uint64_t nwords,
                                                      uint64_t per_thread, uint64_t seed) {
     uint64_t x = seed_thread(seed), acc = 0;
@@ -147,6 +155,15 @@ mphf_status mphf_probe(uint32_t kind, void* buf, uint64_t bytes, void* dst, uint
         if (bytes < 4 || bytes > 49152) return mphf_api::set_error(MPHF_E_INVALID, "LDS footprint must be 4..49152 bytes");
         hipLaunchKernelGGL(k_probe_lds_atomic, dim3(GRID), dim3(PT), (size_t)(bytes / 4) * 4, s,
                            (uint32_t)(bytes / 4), per_thread, seed);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? MPHF_OK : mphf_api::hip_error(e, "probe");
+    }
+    if (kind == MPHF_PROBE_HOST_EXCHANGE) {
+        if (bytes < 8 || bytes % 8) return mphf_api::set_error(MPHF_E_INVALID, "a positive multiple of 8 bytes");
+        const void* src = buf ? mphf_api::pinned_alias(buf, bytes) : nullptr;
+        void* out = dst ? const_cast<void*>(mphf_api::pinned_alias(dst, bytes)) : nullptr;
+        if (!src || !out) return mphf_api::set_error(MPHF_E_INVALID, "buf and dst must be pinned host memory of `bytes`");
+        hipLaunchKernelGGL(k_probe_host, dim3(GRID), dim3(PT), 0, s, (const uint64_t*)src, (uint64_t*)out, bytes / 8);
         hipError_t e = hipGetLastError();
         return e == hipSuccess ? MPHF_OK : mphf_api::hip_error(e, "probe");
     }

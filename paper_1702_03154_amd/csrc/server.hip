@@ -5,9 +5,11 @@
 // device memory and pinned staging), admits requests from the head of the queue while their keys
 // and labels fit the slot, and enqueues the batch: one segmented lookup kernel labels every query
 // against its own function (Algorithm 3).  Requests in pinned host memory are read and written by
-// that kernel in place over PCIe; the others are copied into the slot's buffers and back.  A completer thread waits for the batches in
-// launch order and releases their requests and slots.  With several slots, a batch formed while
-// another runs overlaps it on the device; requests arriving in the meantime form the next batch.
+// that kernel in place over PCIe; the others are copied into the slot's buffers and back.  A
+// completer thread releases each batch's requests and slot as soon as the batch ends, in whatever
+// order the batches end (a short batch does not hold its slot behind a long one launched before
+// it).  With several slots, a batch formed while another runs overlaps it on the device; requests
+// arriving in the meantime form the next batch.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -66,24 +68,6 @@ hipError_t launch_lookup_segments(uint64_t n, const ReqDesc* segs, const uint64_
     return hipGetLastError();
 }
 
-// The device-visible alias of a pinned host range [p, p + bytes), or null for other memory.
-const void* pinned_alias(const void* p, uint64_t bytes) {
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
-    hipPointerAttribute_t b;
-    const void* last = (const char*)p + bytes - 1;
-    if (hipPointerGetAttributes(&b, last) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    if (b.type != hipMemoryTypeHost || (const char*)b.devicePointer - (const char*)a.devicePointer != (ptrdiff_t)(bytes - 1))
-        return nullptr;
-    return a.devicePointer;
-}
 
 struct Request {
     uint64_t ticket = 0;
@@ -114,6 +98,29 @@ uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
 }  // namespace
 
+namespace mphf_api {
+
+// The device-visible alias of a pinned host range [p, p + bytes), or null for other memory.
+const void* pinned_alias(const void* p, uint64_t bytes) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (a.type != hipMemoryTypeHost || !a.devicePointer) return nullptr;
+    hipPointerAttribute_t b;
+    const void* last = (const char*)p + bytes - 1;
+    if (hipPointerGetAttributes(&b, last) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (b.type != hipMemoryTypeHost || (const char*)b.devicePointer - (const char*)a.devicePointer != (ptrdiff_t)(bytes - 1))
+        return nullptr;
+    return a.devicePointer;
+}
+
+}  // namespace mphf_api
+
 struct mphf_server {
     int device = 0;
     mphf_server_opts opts{};
@@ -124,7 +131,7 @@ struct mphf_server {
     std::deque<Request*> queue;
     std::unordered_map<uint64_t, Request*> reqs;
     std::vector<Slot> slots;
-    std::deque<int> inflight;   // slot indices in launch order
+    std::deque<int> inflight;   // slot indices of the batches on the device, in launch order
     uint64_t next_ticket = 1, next_batch = 0;
     bool stopping = false, completer_exit = false;
     mphf_server_stats stats{};
@@ -238,15 +245,30 @@ void dispatch_loop(mphf_server* s) {
 void complete_loop(mphf_server* s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
+    std::vector<int> fl;
     for (;;) {
         s->cv.wait(lk, [&] { return !s->inflight.empty() || s->completer_exit; });
         if (s->inflight.empty()) break;
-        const int k = s->inflight.front();
+        // the first batch on the device to end: its completion event, polled with the batches
+        // launched meanwhile (the thread yields between rounds)
+        int k = -1;
+        hipError_t e = hipSuccess;
+        while (k < 0) {
+            fl.assign(s->inflight.begin(), s->inflight.end());
+            lk.unlock();
+            for (int j : fl) {
+                const hipError_t q = hipEventQuery(s->slots[j].done);
+                if (q != hipErrorNotReady) {
+                    k = j;
+                    e = q;
+                    break;
+                }
+            }
+            if (k < 0) std::this_thread::yield();
+            lk.lock();
+        }
         Slot& sl = s->slots[k];
-        lk.unlock();
-        const hipError_t e = hipEventSynchronize(sl.done);
         const double t = s->now_us();
-        lk.lock();
         for (Request* r : sl.reqs) {
             if (e != hipSuccess) r->status = MPHF_E_DEVICE;
             r->t_done = t;
@@ -258,7 +280,11 @@ void complete_loop(mphf_server* s) {
         sl.reqs.clear();
         sl.keys = 0;
         sl.busy = false;
-        s->inflight.pop_front();
+        for (auto it = s->inflight.begin(); it != s->inflight.end(); ++it)
+            if (*it == k) {
+                s->inflight.erase(it);
+                break;
+            }
         s->cv.notify_all();
     }
 }
@@ -358,8 +384,8 @@ mphf_status mphf_server_submit(mphf_server_t* s, uint32_t id, const uint64_t* ke
     r->n = n;
     r->out = out;
     if (n) {   // pinned arrays are read and written by the lookup kernel directly
-        r->dkeys = (const uint64_t*)pinned_alias(keys, 8 * n);
-        r->dout = (uint64_t*)pinned_alias(out, 8 * n);
+        r->dkeys = (const uint64_t*)mphf_api::pinned_alias(keys, 8 * n);
+        r->dout = (uint64_t*)mphf_api::pinned_alias(out, 8 * n);
     }
     r->t_submit = s->now_us();
     s->reqs[r->ticket] = r;

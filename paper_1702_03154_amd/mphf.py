@@ -493,7 +493,7 @@ def set_ids(keys: torch.Tensor, bits: int, seed: int = 0, stream=None) -> torch.
 # ---------------------------------------------------------------- roofline probes
 
 PROBE_KINDS = {"stream_read": 0, "stream_copy": 1, "random_read8": 2, "random_sector64": 3,
-               "random_atomic_or": 4, "lds_atomic_or": 5}
+               "random_atomic_or": 4, "lds_atomic_or": 5, "host_exchange": 6}
 
 
 def probe(kind: str, buf: torch.Tensor | None = None, nbytes: int = 0, dst: torch.Tensor | None = None,
@@ -508,7 +508,16 @@ def probe(kind: str, buf: torch.Tensor | None = None, nbytes: int = 0, dst: torc
     if dst is not None and (not dst.is_cuda or nbytes > dst.numel() * dst.element_size()):
         raise ValueError("dst must be a GPU tensor of at least nbytes")
     _check(lib().mphf_probe(k, bp, nbytes, dp, ops, seed, _stream(stream)))
-    return int(lib().mphf_probe_ops(ops)) if k >= 2 else 0
+    return int(lib().mphf_probe_ops(ops)) if 2 <= k <= 5 else 0
+
+
+def probe_host_exchange(src: "HostArray", dst: "HostArray", nbytes: int, stream=None) -> None:
+    """Enqueue the PCIe probe (mphf_probe, MPHF_PROBE_HOST_EXCHANGE): a kernel reads nbytes of the
+    pinned array src and writes them to the pinned array dst."""
+    if nbytes > 8 * min(len(src.a), len(dst.a)):
+        raise ValueError("src and dst must hold nbytes")
+    _check(lib().mphf_probe(PROBE_KINDS["host_exchange"], src._p.value, nbytes, dst._p.value, 0, 0,
+                            _stream(stream)))
 
 
 # ---------------------------------------------------------------- serving
