@@ -68,13 +68,13 @@ def check_set(b, s, ks, gamma, seed, max_levels, labels, sectors=True):
     return st
 
 
-def check_batch(M, sizes, gamma, seed=0, max_levels=25, check=None, absent=True, planned=False):
+def check_batch(M, sizes, gamma, seed=0, max_levels=25, check=None, absent=True, planned=False, launch=None):
     sizes, keys, off = make_sets(sizes)
     nsets = sizes.numel()
     if planned:
-        b = M.Batch.plan(off.cuda(), gamma, seed, max_levels=max_levels).rebuild(keys.cuda()).status()
+        b = M.Batch.plan(off.cuda(), gamma, seed, max_levels=max_levels, launch=launch).rebuild(keys.cuda()).status()
     else:
-        b = M.build_batch(keys.cuda(), off.cuda(), gamma, seed, max_levels=max_levels)
+        b = M.build_batch(keys.cuda(), off.cuda(), gamma, seed, max_levels=max_levels, launch=launch)
     set_ids = torch.repeat_interleave(torch.arange(nsets), sizes)
     lab = host(b.lookup(set_ids.cuda(), keys.cuda()))
     knp = keys.numpy().view(np.uint64)
@@ -123,6 +123,20 @@ def test_batch_fallback_tables(M, max_levels):
 def test_batch_largest_set_in_lds(M):
     # ceil(gamma n) = 2^19 exactly: A and C take 128 KiB of LDS
     check_batch(M, [1 << 18, 10, 1 << 17], 2.0, seed=11, absent=False)
+
+
+@pytest.mark.parametrize("launch,planned", [
+    ((128, 4, 0, 13, 2), False),    # levels of at most 512 keys in registers
+    ((512, 16, 0, 1, 2), False),    # at most 8192 keys in registers; one queue
+    ((256, 8, 2, 64, 1), True),     # every set small, every workgroup on the small queue; planned
+])
+def test_batch_largest_set_across_launches(M, launch, planned):
+    """The largest set a batch takes streams its first levels from global memory and keeps its
+    last ones in registers, at a threshold (threads x keys per thread) that depends on the launch;
+    its levels, words, sectors and labels must equal the oracle's whichever launch and queue split
+    builds it, beside sets that start in registers."""
+    check_batch(M, [1 << 18, 10, 3000, 1 << 17, 700, 9000], 2.0, seed=12, absent=False, planned=planned,
+                launch=launch)
 
 
 def test_batch_equals_standalone_builds(M):
