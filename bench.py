@@ -900,7 +900,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="batch: autotune the build launch first")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=float, default=1e9)
     ap.add_argument("--gamma", type=float, default=2.0)
     ap.add_argument("--cpu-sample", type=float, default=1e8)
