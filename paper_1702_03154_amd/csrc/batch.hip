@@ -670,8 +670,9 @@ hipError_t launch_batch_lookup(const uint64_t* set_ids, const uint64_t* q, uint6
                                uint64_t nsets, const uint32_t* sec, const uint64_t* left, const SeedTable& seeds,
                                hipStream_t s) {
     if (!n) return hipSuccess;
+    // short blocks (four queries per thread), as many as the queries need, at most 2^24 - 1
     uint64_t blocks = (n + 1023) / 1024;
-    if (blocks > 8192) blocks = 8192;
+    if (blocks > (1ull << 24) - 1) blocks = (1ull << 24) - 1;
     hipLaunchKernelGGL(k_batch_lookup, dim3((unsigned)blocks), dim3(256), 0, s, set_ids, q, n, out, heads, lev, aux,
                        D, nsets, sec, left, seeds);
     return hipGetLastError();

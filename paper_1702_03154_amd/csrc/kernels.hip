@@ -17,6 +17,15 @@ namespace {
 constexpr int NT = 256;          // threads per block for the streaming kernels
 constexpr int MAX_GRID = 8192;   // grid-stride kernels: enough blocks to fill 256 CUs
 
+// Blocks for a random-access kernel: one per per_block items, up to 2^24 - 1 (so that the grid's
+// work-items stay below 2^32); more items than that are strided.
+inline unsigned short_grid(uint64_t items, uint64_t per_block) {
+    uint64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > (1ull << 24) - 1) b = (1ull << 24) - 1;
+    return (unsigned)b;
+}
+
 inline unsigned grid_for(uint64_t items, uint64_t per_block) {
     uint64_t b = (items + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -567,7 +576,9 @@ hipError_t launch_lookup(const uint64_t* q, uint64_t n, uint64_t* out, const Dev
                          uint32_t nlev, const uint32_t* sec, const uint64_t* super,
                          const uint64_t* fb_keys, uint64_t nfb, uint64_t N, hipStream_t s) {
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_lookup, dim3(grid_for(n, NT * 4)), dim3(NT), 0, s, q, n, out, lev, nlev,
+    // short blocks (two passes of two queries per thread), as many as the queries need: measured
+    // faster than a capped grid-stride grid (31.6-31.8 against 32.5 ms for 1e9 queries)
+    hipLaunchKernelGGL(k_lookup, dim3(short_grid(n, NT * 4)), dim3(NT), 0, s, q, n, out, lev, nlev,
                        sec, super, fb_keys, nfb, N);
     return hipGetLastError();
 }

@@ -62,8 +62,8 @@ k_lookup_segments(uint64_t n, const ReqDesc* __restrict__ segs, const uint64_t* 
 hipError_t launch_lookup_segments(uint64_t n, const ReqDesc* segs, const uint64_t* seg_off, uint32_t nseg,
                                   hipStream_t s) {
     if (!n || !nseg) return hipSuccess;
-    uint64_t blocks = (n + 4 * ST - 1) / (4 * ST);
-    if (blocks > 8192) blocks = 8192;
+    uint64_t blocks = (n + 4 * ST - 1) / (4 * ST);   // four queries per thread, at most 2^24 - 1 blocks
+    if (blocks > (1ull << 24) - 1) blocks = (1ull << 24) - 1;
     hipLaunchKernelGGL(k_lookup_segments, dim3((unsigned)blocks), dim3(ST), 0, s, n, segs, seg_off, nseg);
     return hipGetLastError();
 }
