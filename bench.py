@@ -200,11 +200,11 @@ def calibrate_copy():
 
 # ---------------------------------------------------------------- roofline probes
 
-def probe_rate(kind: str, nbytes: int, ops: int = 0, reps: int = 3) -> dict:
-    """Median rate of one microbenchmark (bytes/s for the streaming kinds, operations/s for the
-    random ones), timed with events on the stream it is launched on."""
-    import statistics
-
+def probe_rate(kind: str, nbytes: int, ops: int = 0, reps: int = 5) -> dict:
+    """Rate of one microbenchmark (bytes/s for the streaming kinds, operations/s for the random
+    ones), timed with events on the stream it is launched on: the best of `reps` runs after one
+    warm-up, since it stands for a ceiling (repeated runs of the random kinds spread by a few
+    percent from box to box and within a process)."""
     import torch
 
     from paper_1702_03154_amd import mphf
@@ -225,7 +225,7 @@ def probe_rate(kind: str, nbytes: int, ops: int = 0, reps: int = 3) -> dict:
         torch.cuda.synchronize()
         if r:
             times.append(e0.elapsed_time(e1) / 1e3)
-    t = statistics.median(times)
+    t = min(times)
     del buf, dst
     if kind in ("stream_read", "stream_copy"):
         moved = nbytes * (2 if kind == "stream_copy" else 1)
